@@ -1,0 +1,316 @@
+"""Seeded synthetic workloads for the Yee FDTD solver.
+
+This module only *generates inputs*: material tables, per-cell material
+indices, source positions and waveforms, probe positions and initial
+fields.  It contains none of the update arithmetic, so both the CPU
+oracle (test infrastructure) and the GPU path can consume its output.
+
+The paper measures synthetic N^3 cubes and cavity cases (a PEC box with a
+point current and a few pin-point outputs; Sec. 4.1, Sec. 4.2).  The
+workloads below stand in for those cases with the shapes, sizes and
+structure of the configurations this library is benchmarked on:
+
+* ``cavity32``  -- 32^3 vacuum PEC box, analytic TM110 mode plus noise.
+* ``spheres256`` -- 256^3, 16-entry dielectric table, 40 random spheres,
+  Ez soft source at the centre, 16 probes, 1000 steps.
+* ``spheres512`` -- 512^3, 200 spheres, three sources (Ex, Ey, Ez).
+* ``aniso1024`` -- 1024x512x256, same recipe as ``spheres512``.
+* ``serving``   -- 256 requests with random anisotropic grids.
+
+All randomness comes from splitmix64 (Steele, Lea, Flood 2014), drawn in a
+fixed order: material table, spheres (cx, cy, cz, radius, index), sources,
+probes, noise.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+C0 = 299792458.0            # speed of light in vacuum, m/s
+COMP_NAMES = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+EX, EY, EZ, HX, HY, HZ = range(6)
+FP32, FP16, BF16 = 0, 1, 2
+STORAGE_NAMES = {FP32: "fp32", FP16: "fp16", BF16: "bf16"}
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_MASK64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    """splitmix64 generator; scalar draws and vectorised continuation."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _MASK64
+
+    @staticmethod
+    def _mix(z: int) -> int:
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        return z ^ (z >> 31)
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _MASK64
+        return self._mix(self.state)
+
+    def uniform(self, lo: float = 0.0, hi: float = 1.0) -> float:
+        u = (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+        return lo + (hi - lo) * u
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Uniform integer in the closed range [lo, hi]."""
+        u = (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+        return lo + min(int(u * (hi - lo + 1)), hi - lo)
+
+    def uniform_array(self, n: int, lo: float, hi: float) -> np.ndarray:
+        """The next n draws as uniforms in [lo, hi) (same stream as uniform())."""
+        k = np.arange(1, n + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z = np.uint64(self.state) + k * _GAMMA
+            z = (z ^ (z >> np.uint64(30))) * _M1
+            z = (z ^ (z >> np.uint64(27))) * _M2
+            z = z ^ (z >> np.uint64(31))
+        self.state = (self.state + n * 0x9E3779B97F4A7C15) & _MASK64
+        u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+        return lo + (hi - lo) * u
+
+
+def courant_dt(dx: float, dy: float, dz: float, frac: float = 0.99) -> float:
+    """frac times the 3-D Courant limit 1/(c*sqrt(dx^-2+dy^-2+dz^-2))."""
+    return frac / (C0 * math.sqrt(1.0 / dx ** 2 + 1.0 / dy ** 2 + 1.0 / dz ** 2))
+
+
+def gaussian_sine(n: int, dt: float, dx: float, amplitude: float = 1.0) -> np.ndarray:
+    """Gaussian-modulated sinusoid sampled at t=(n+1/2)dt, in float64.
+
+    f0 = c/(20 dx) (20 cells per vacuum wavelength), tau = 1/f0, t0 = 4 tau.
+    """
+    f0 = C0 / (20.0 * dx)
+    tau = 1.0 / f0
+    t0 = 4.0 * tau
+    t = (np.arange(n, dtype=np.float64) + 0.5) * dt
+    return amplitude * np.exp(-((t - t0) / tau) ** 2) * np.sin(2.0 * math.pi * f0 * (t - t0))
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    dt: float
+    eps_r: np.ndarray            # (n_mat,) float64
+    mu_r: np.ndarray             # (n_mat,) float64 (all 1)
+    sigma: np.ndarray            # (n_mat,) float64, S/m
+    mat: np.ndarray              # (nz, ny, nx) uint8 cell material index
+    sources: List[Tuple[int, int, int, int]]   # (comp, i, j, k)
+    waveforms: np.ndarray        # (n_src, n_wave) float64
+    probes: List[Tuple[int, int, int, int]]    # (comp, i, j, k)
+    n_steps: int
+    init_fields: Optional[np.ndarray] = None   # (6, nz+1, ny+1, nx+1) float64
+    storage: int = FP32
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def box_shape(self) -> Tuple[int, int, int]:
+        return (self.nz + 1, self.ny + 1, self.nx + 1)
+
+
+def material_table(rng: SplitMix64, n_mat: int = 16):
+    """Entry 0 is vacuum; entries 1..n-1: eps_r U[1,12], sigma U[0,0.05] S/m, mu_r=1."""
+    eps = np.ones(n_mat)
+    sig = np.zeros(n_mat)
+    for m in range(1, n_mat):
+        eps[m] = rng.uniform(1.0, 12.0)
+        sig[m] = rng.uniform(0.0, 0.05)
+    return eps, np.ones(n_mat), sig
+
+
+def paint_spheres(rng: SplitMix64, nx: int, ny: int, nz: int, n_spheres: int,
+                  rmin: int, rmax: int, n_mat: int) -> np.ndarray:
+    """Cell material index array; later spheres overwrite earlier ones.
+
+    A cell (i,j,k) is inside when its centre (i+1/2, j+1/2, k+1/2) lies within
+    radius r of the sphere centre.
+    """
+    mat = np.zeros((nz, ny, nx), dtype=np.uint8)
+    for _ in range(n_spheres):
+        cx = rng.uniform(0.0, nx)
+        cy = rng.uniform(0.0, ny)
+        cz = rng.uniform(0.0, nz)
+        r = rng.randint(rmin, rmax)
+        idx = rng.randint(1, n_mat - 1)
+        i0, i1 = max(0, int(math.floor(cx - r - 1))), min(nx, int(math.ceil(cx + r + 1)))
+        j0, j1 = max(0, int(math.floor(cy - r - 1))), min(ny, int(math.ceil(cy + r + 1)))
+        k0, k1 = max(0, int(math.floor(cz - r - 1))), min(nz, int(math.ceil(cz + r + 1)))
+        if i0 >= i1 or j0 >= j1 or k0 >= k1:
+            continue
+        zi = (np.arange(k0, k1) + 0.5 - cz)[:, None, None]
+        yi = (np.arange(j0, j1) + 0.5 - cy)[None, :, None]
+        xi = (np.arange(i0, i1) + 0.5 - cx)[None, None, :]
+        inside = (xi * xi + yi * yi + zi * zi) <= float(r * r)
+        sub = mat[k0:k1, j0:j1, i0:i1]
+        sub[inside] = idx
+    return mat
+
+
+_PROBE_CYCLE = (EZ, HX, HY, EX, EY, HZ)
+
+
+def seeded_probes(rng: SplitMix64, nx: int, ny: int, nz: int, n: int):
+    """n probes at interior positions; components cycle Ez, Hx, Hy, Ex, Ey, Hz."""
+    out = []
+    for p in range(n):
+        i = rng.randint(1, nx - 2)
+        j = rng.randint(1, ny - 2)
+        k = rng.randint(1, nz - 2)
+        out.append((_PROBE_CYCLE[p % 6], i, j, k))
+    return out
+
+
+def interior_e_mask(nx: int, ny: int, nz: int) -> np.ndarray:
+    """(3, nz+1, ny+1, nx+1) bool: E edges not tangential to the PEC walls."""
+    m = np.zeros((3, nz + 1, ny + 1, nx + 1), dtype=bool)
+    m[0, 1:nz, 1:ny, 0:nx] = True
+    m[1, 1:nz, 0:ny, 1:nx] = True
+    m[2, 0:nz, 1:ny, 1:nx] = True
+    return m
+
+
+def tm110_state(nx: int, ny: int, nz: int, dx: float, dy: float, dz: float, dt: float) -> np.ndarray:
+    """Closed-form discrete TM110 cavity mode, amplitude 1 (float64).
+
+    E^0_z(i,j,k) = sin(pi i/nx) sin(pi j/ny); other E components are 0.
+    H^{-1/2} is half a time step of the mode's discrete rotation, in closed
+    form, chosen so that H^{+1/2} = -H^{-1/2} (the mode is then advanced at
+    its exact discrete frequency).  H is stored as eta0*H, in V/m.
+    """
+    f = np.zeros((6, nz + 1, ny + 1, nx + 1))
+    si = np.sin(math.pi * np.arange(nx + 1) / nx)
+    sj = np.sin(math.pi * np.arange(ny + 1) / ny)
+    f[EZ, 0:nz, :, :] = sj[None, :, None] * si[None, None, :]
+    half = 0.5 * C0 * dt
+    dsj = (sj[1:] - sj[:-1]) / dy           # j in [0, ny)
+    dsi = (si[1:] - si[:-1]) / dx           # i in [0, nx)
+    f[HX, 0:nz, 0:ny, :] = half * dsj[None, :, None] * si[None, None, :]
+    f[HY, 0:nz, :, 0:nx] = -half * sj[None, :, None] * dsi[None, None, :]
+    return f
+
+
+def cavity32(seed: int = 1000, n: int = 32, n_steps: int = 100, noise: float = 1e-4) -> Workload:
+    """32^3 vacuum PEC box, TM110 mode plus seeded noise on interior E, 4 probes."""
+    nx = ny = nz = n
+    d = 1e-3
+    dt = courant_dt(d, d, d)
+    rng = SplitMix64(seed)
+    probes = seeded_probes(rng, nx, ny, nz, 4)
+    f = tm110_state(nx, ny, nz, d, d, d, dt)
+    mask = interior_e_mask(nx, ny, nz)
+    cnt = int(mask.sum())
+    f[0:3][mask] += rng.uniform_array(cnt, -noise, noise)
+    return Workload("cavity32", nx, ny, nz, d, d, d, dt,
+                    np.ones(1), np.ones(1), np.zeros(1),
+                    np.zeros((nz, ny, nx), np.uint8), [], np.zeros((0, n_steps)),
+                    probes, n_steps, init_fields=f)
+
+
+def spheres(nx: int, ny: int, nz: int, n_spheres: int, n_steps: int, seed: int,
+            n_sources: int = 1, n_probes: int = 16, rmin: int = 8, rmax: int = 40,
+            name: str = "spheres", storage: int = FP32, d: float = 1e-3) -> Workload:
+    """Dielectric-scatterer cavity: 16-entry table, random spheres, soft sources.
+
+    n_sources == 1: an Ez source at the grid centre.  n_sources == 3: Ex, Ey
+    and Ez sources at seeded edges at least 16 cells (or a quarter of the
+    grid, if smaller) from every wall.
+    """
+    dt = courant_dt(d, d, d)
+    rng = SplitMix64(seed)
+    eps, mu, sig = material_table(rng, 16)
+    mat = paint_spheres(rng, nx, ny, nz, n_spheres, rmin, rmax, 16)
+    srcs = []
+    if n_sources == 1:
+        srcs.append((EZ, nx // 2, ny // 2, nz // 2))
+    else:
+        for s in range(n_sources):
+            m = [max(1, min(16, n // 4)) for n in (nx, ny, nz)]
+            i = rng.randint(m[0], nx - m[0])
+            j = rng.randint(m[1], ny - m[1])
+            k = rng.randint(m[2], nz - m[2])
+            srcs.append(((EX, EY, EZ)[s % 3], i, j, k))
+    w = gaussian_sine(n_steps, dt, d)
+    waves = np.tile(w, (len(srcs), 1))
+    probes = seeded_probes(rng, nx, ny, nz, n_probes)
+    return Workload(name, nx, ny, nz, d, d, d, dt, eps, mu, sig, mat, srcs, waves,
+                    probes, n_steps, storage=storage)
+
+
+def spheres256(n_steps: int = 1000) -> Workload:
+    return spheres(256, 256, 256, 40, n_steps, seed=1001, n_sources=1, name="spheres256")
+
+
+def spheres512(n_steps: int = 500) -> Workload:
+    return spheres(512, 512, 512, 200, n_steps, seed=1002, n_sources=3, name="spheres512")
+
+
+def precision512(storage: int, n_steps: int = 2000) -> Workload:
+    return spheres(512, 512, 512, 200, n_steps, seed=1003, n_sources=3,
+                   name="precision512", storage=storage)
+
+
+def precision1024(storage: int, n_steps: int = 2000) -> Workload:
+    return spheres(1024, 512, 256, 200, n_steps, seed=1003, n_sources=3,
+                   name="precision1024x512x256", storage=storage)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float               # seconds from the start of the run
+    nx: int
+    ny: int
+    nz: int
+    n_spheres: int
+    n_steps: int
+    storage: int
+
+    def workload(self) -> Workload:
+        wl = spheres(self.nx, self.ny, self.nz, self.n_spheres, self.n_steps,
+                     seed=(1004 << 20) + self.rid, n_sources=1, n_probes=8,
+                     rmin=min(8, max(1, min(self.nx, self.ny, self.nz) // 8)),
+                     rmax=min(40, max(2, min(self.nx, self.ny, self.nz) // 4)),
+                     name=f"req{self.rid}", storage=self.storage)
+        return wl
+
+
+def serving_requests(n: int = 256, rate: float = 8.0, seed: int = 1004,
+                     dim_lo: int = 48, dim_hi: int = 320,
+                     steps_lo: int = 200, steps_hi: int = 3000) -> List[Request]:
+    """Poisson arrivals at `rate` req/s; dims, sphere counts, steps, storage seeded."""
+    rng = SplitMix64(seed)
+    t = 0.0
+    out = []
+    for r in range(n):
+        nx, ny, nz = (rng.randint(dim_lo, dim_hi) for _ in range(3))
+        ns = rng.randint(5, 60)
+        steps = rng.randint(steps_lo, steps_hi)
+        storage = FP16 if rng.uniform() < 0.5 else FP32
+        t += -math.log(1.0 - rng.uniform()) / rate
+        out.append(Request(r, t, nx, ny, nz, ns, steps, storage))
+    return out
+
+
+def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
+    """||a-b||_2/||b||_2 with float64 accumulation (b is the reference)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = float(np.sqrt(np.sum(b * b)))
+    return float(np.sqrt(np.sum((a - b) ** 2))) / den if den > 0 else float(np.sqrt(np.sum(a * a)))
