@@ -1,0 +1,192 @@
+/*
+ * fdtd.h -- C ABI of the MI355X (gfx950) Yee FDTD library.
+ *
+ * The library advances Maxwell's equations on a Cartesian Yee grid with the
+ * explicit leapfrog of Cessenat, "Sophie, an FDTD code on the way to
+ * multicore", Sec. 2.1: an H (Faraday) half-step from the curl of E, then an
+ * E (Ampere) half-step from the curl of H, every coefficient one-dimensional
+ * or table-sized (Sec. 2.2).  Materials enter through a per-cell uint8 index
+ * into a small table (relative permittivity, conductivity); the outer walls
+ * are perfect electric conductors (tangential E held at zero, Sec. 3.3);
+ * sources are currents added to Ampere's law at pin points and probes read
+ * single field values after every step (pin-point outputs, Sec. 3.4, 4.2).
+ *
+ * Grid and storage conventions
+ * ----------------------------
+ * nx, ny, nz cells of size dx, dy, dz (metres); time step dt (seconds).
+ * Every component is addressed on the (nx+1)(ny+1)(nz+1) node box, x
+ * fastest (index i + (nx+1)*(j + (ny+1)*k)); positions outside the
+ * component's staggered range hold 0:
+ *   Ex (i+1/2, j, k)      i<nx            Hx (i, j+1/2, k+1/2)  j<ny, k<nz
+ *   Ey (i, j+1/2, k)      j<ny            Hy (i+1/2, j, k+1/2)  i<nx, k<nz
+ *   Ez (i, j, k+1/2)      k<nz            Hz (i+1/2, j+1/2, k)  i<nx, j<ny
+ * E is in V/m and H is stored as eta0*H (V/m), so both updates carry the
+ * factor c*dt/delta of the antisymmetric form (Sec. 2.1).  The state after
+ * n steps is (E^n, H^{n-1/2}).  Each interior E edge uses the material of
+ * its owner cell, the cell whose lowest corner is the edge's lower end.
+ *
+ * Arithmetic: FP32 throughout, every update in a fixed fused-multiply-add
+ * order (z-difference term, then y, cyclically), so results are
+ * reproducible bit for bit and do not depend on the kernel variant, the
+ * time-block length T or the tile shape when fields are stored in FP32.
+ * Fields may instead be stored as binary16 or bfloat16 with one power-of-two
+ * scale per component; they are then re-encoded at the end of every block
+ * of T steps (blocks end at absolute step counts that are multiples of T and
+ * at the end of each fdtd_step call).
+ *
+ * Ownership and errors
+ * --------------------
+ * Host inputs are copied during the call; the caller may free them on
+ * return.  A caller-supplied device workspace stays owned by the caller and
+ * must outlive fdtd_destroy.  The stream is never destroyed by the library.
+ * Every function returns FDTD_OK (0) or a negative fdtd_status; output
+ * arguments are written only on FDTD_OK.  fdtd_last_error() gives a
+ * thread-local message for the last failure.  One host thread at a time may
+ * use a given solver; different solvers may be used concurrently.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_solver fdtd_solver;
+
+enum fdtd_status {
+    FDTD_OK = 0,
+    FDTD_EINVAL = -1,   /* bad argument: dimensions, index, component, range */
+    FDTD_ENOMEM = -2,   /* device or host allocation failed, workspace too small */
+    FDTD_EDEVICE = -3,  /* a HIP call or kernel launch failed */
+    FDTD_ECFL = -4,     /* dt above the 3-D Courant limit */
+    FDTD_ERANGE = -5,   /* reduced storage saturated or a non-finite value was stored */
+    FDTD_ESTATE = -6    /* call not allowed in the solver's current state */
+};
+
+enum fdtd_storage { FDTD_FP32 = 0, FDTD_FP16 = 1, FDTD_BF16 = 2 };
+
+enum fdtd_component { FDTD_EX = 0, FDTD_EY = 1, FDTD_EZ = 2, FDTD_HX = 3, FDTD_HY = 4, FDTD_HZ = 5 };
+
+/* Kernel families.  PLAIN: one in-place H pass then one in-place E pass per
+ * step (the standard loop of Sec. 2.2; FP32 storage only).  FUSED: one pass
+ * over HBM advances T steps, H and E interleaved plane by plane along z
+ * with T time levels pipelined in registers (Sec. 3.2-3.4).  AUTO picks
+ * FUSED. */
+enum fdtd_kernel { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_PLAIN = 1, FDTD_KERNEL_FUSED = 2 };
+
+typedef struct {
+    double eps_r;   /* relative permittivity, > 0 */
+    double mu_r;    /* relative permeability; must be 1 */
+    double sigma;   /* conductivity in S/m, >= 0 */
+} fdtd_material;
+
+/* Diagnostics of the current state (E^n, H^{n-1/2}), reduced in FP64 in a
+ * fixed order (results do not depend on scheduling).
+ *   energy  = 1/2 sum eps_r E^n.E^n + 1/2 sum H^{n-1/2}.H^{n+1/2}, in units of
+ *             eps0*dx*dy*dz; conserved exactly by a lossless PEC box
+ *   div_e_* = div(eps_r E) at interior nodes; div_h_* = div(H) at cell
+ *             centres (both in V/m^2): largest magnitude and sum of squares
+ *   max_abs = largest |value| of each component */
+typedef struct {
+    double energy;
+    double div_e_max, div_e_sumsq;
+    double div_h_max, div_h_sumsq;
+    double max_abs[6];
+} fdtd_diag;
+
+/* Device bytes fdtd_create needs for a caller-supplied workspace: two field
+ * buffers (ping-pong), the material index and a small control block.
+ * Returns 0 for invalid dimensions or storage. */
+size_t fdtd_workspace_bytes(int nx, int ny, int nz, int storage);
+
+/* Create a solver with all fields zero.
+ *   nx, ny, nz    >= 2 cells each (and (nx+1)(ny+1) < 2^31)
+ *   dx, dy, dz    > 0; dt > 0 and <= 1/(c sqrt(dx^-2+dy^-2+dz^-2)) (else FDTD_ECFL)
+ *   table         n_materials entries (1..256), copied
+ *   mat_index     host, nx*ny*nz bytes, x fastest (i + nx*(j + ny*k)); every
+ *                 entry < n_materials (scanned; else FDTD_EINVAL); NULL = all 0
+ *   storage       fdtd_storage
+ *   device_workspace  NULL: the library allocates; else at least
+ *                 fdtd_workspace_bytes(...) bytes of device memory, 256-byte
+ *                 aligned, owned by the caller
+ *   hip_stream    hipStream_t to enqueue on (NULL = the default stream) */
+int fdtd_create(fdtd_solver **out, int nx, int ny, int nz,
+                double dx, double dy, double dz, double dt,
+                const fdtd_material *table, int n_materials,
+                const uint8_t *mat_index, int storage,
+                void *device_workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Kernel family (fdtd_kernel) and steps per HBM pass T (1..8) for the FUSED
+ * family.  Allowed before the first step and between steps. */
+int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
+
+/* Replace the whole state.  host: 6*(nx+1)*(ny+1)*(nz+1) floats, components
+ * Ex, Ey, Ez, Hx, Hy, Hz one after another (E^n, then H^{n-1/2}); NULL sets
+ * every field to zero.  Positions outside a component's range and
+ * tangential E on the walls are forced to zero.  With reduced storage the
+ * values are encoded here, with scales from their own maxima and from the
+ * sources registered so far.  Synchronises the stream. */
+int fdtd_set_fields(fdtd_solver *s, const float *host);
+
+/* Add a soft source E_comp(i,j,k) += waveform[n] during step n (the step
+ * that produces E^{n+1}), for n < n_samples; zero afterwards.  comp is an E
+ * component and (i,j,k) must be an interior (non-PEC) edge.  waveform is
+ * copied.  *id receives the source index (0, 1, ...). */
+int fdtd_set_source(fdtd_solver *s, int comp, int i, int j, int k,
+                    const float *waveform, int n_samples, int *id);
+
+/* Add a probe of component comp at storage position (i,j,k) (inside that
+ * component's range).  After every step n (E^{n+1}, H^{n+1/2}) the value is
+ * recorded in FP64.  Only allowed before the first step.  *id receives the
+ * probe index. */
+int fdtd_set_probe(fdtd_solver *s, int comp, int i, int j, int k, int *id);
+
+/* Enqueue n_steps >= 0 steps on the solver's stream and return without
+ * waiting.  Fails with FDTD_ERANGE if an earlier block saturated. */
+int fdtd_step(fdtd_solver *s, int n_steps);
+
+/* Copy one component of the current state to host (float,
+ * (nx+1)(ny+1)(nz+1), x fastest; decoded if stored in reduced precision).
+ * Synchronises the stream. */
+int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst);
+
+/* Copy probe records for steps [first_step, first_step+n_steps) to host_dst
+ * as n_steps rows of n_probes doubles (row = step, column = probe id).
+ * The steps must have been run.  Synchronises the stream. */
+int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int n_steps);
+
+/* Compute diagnostics of the current state.  Synchronises the stream. */
+int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out);
+
+/* Number of steps enqueued so far. */
+int fdtd_steps_done(const fdtd_solver *s, long long *n);
+
+/* Current per-component storage scales (2^scale multiplies a value before
+ * encoding; all 0 for FP32 storage) and the saturation flag.  Synchronises. */
+int fdtd_storage_state(fdtd_solver *s, int scales[6], int *saturated);
+
+/* Wait for all work enqueued on the solver's stream; reports FDTD_ERANGE if
+ * reduced storage saturated. */
+int fdtd_synchronize(fdtd_solver *s);
+
+/* Release the solver and everything the library allocated for it. */
+void fdtd_destroy(fdtd_solver *s);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *fdtd_last_error(void);
+
+/* FP32 coefficients the library derives from a material table: out gets
+ * n_materials x {Ca, Cbx, Cby, Cbz} and ch gets {c dt/dx, c dt/dy, c dt/dz}.
+ * Host-only; no device is needed. */
+int fdtd_coefficients(const fdtd_material *table, int n_materials,
+                      double dx, double dy, double dz, double dt,
+                      float *out, float *ch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDTD_H */

@@ -1,0 +1,719 @@
+// Host runtime of the Yee FDTD library: the C ABI declared in include/fdtd.h.
+//
+// Responsibilities: argument validation, coefficient precompute (FP64,
+// rounded once to FP32), device workspace layout, upload/readback of fields
+// (with the reduced-storage codec), source/probe tables, and the step
+// scheduler, which cuts fdtd_step(n) into blocks of at most T steps ending at
+// absolute step counts that are multiples of T (a pin-point output never
+// forces an extra block: probes are recorded inside the kernels, the GPU
+// counterpart of Sec. 3.4's advice not to start a multi-step block the step
+// before an output is needed).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "yee_internal.hpp"
+
+namespace {
+
+constexpr double C0 = 299792458.0;
+constexpr double EPS0 = 8.8541878128e-12;
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(FDTD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+int elem_size(int storage) { return storage == FDTD_FP32 ? 4 : 2; }
+
+struct Dims {
+    int pitch;
+    long long plane, cstride;
+    size_t fbytes, matbytes, total;
+};
+
+Dims dims_for(int nx, int ny, int nz, int storage)
+{
+    Dims d;
+    const int es = elem_size(storage);
+    d.pitch = (int)round_up((size_t)nx + 1, 128 / es);          // rows start on 128-byte lines
+    d.plane = (long long)d.pitch * (ny + 1);
+    d.cstride = (long long)round_up((size_t)d.plane * (nz + 1), 256 / es);
+    d.fbytes = (size_t)d.cstride * 6 * es;
+    d.matbytes = round_up((size_t)d.plane * (nz + 1), 256);
+    d.total = 2 * d.fbytes + d.matbytes + 256;
+    return d;
+}
+
+// 1 if component c exists at (i,j,k) of the node box
+bool in_range(int nx, int ny, int nz, int c, int i, int j, int k)
+{
+    if (i < 0 || j < 0 || k < 0 || i > nx || j > ny || k > nz) return false;
+    switch (c) {
+    case 0: return i < nx;
+    case 1: return j < ny;
+    case 2: return k < nz;
+    case 3: return j < ny && k < nz;
+    case 4: return i < nx && k < nz;
+    case 5: return i < nx && j < ny;
+    }
+    return false;
+}
+
+// 1 if E component c at (i,j,k) is not tangential to a wall
+bool e_interior(int nx, int ny, int nz, int c, int i, int j, int k)
+{
+    switch (c) {
+    case 0: return i < nx && j > 0 && j < ny && k > 0 && k < nz;
+    case 1: return j < ny && i > 0 && i < nx && k > 0 && k < nz;
+    case 2: return k < nz && i > 0 && i < nx && j > 0 && j < ny;
+    }
+    return false;
+}
+
+// ---- reduced-storage codec on the host (upload and readback) ---------------
+uint16_t enc_f16(float y)
+{
+    _Float16 h = (_Float16)y;                  // round to nearest even, subnormals kept
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+
+float dec_f16(uint16_t b)
+{
+    _Float16 h;
+    std::memcpy(&h, &b, 2);
+    return (float)h;
+}
+
+uint16_t enc_bf16(float y)
+{
+    uint32_t u;
+    std::memcpy(&u, &y, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+float dec_bf16(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Encode y (already scaled); saturate at the largest finite value.
+uint16_t encode(int storage, float y, bool *sat)
+{
+    if (storage == FDTD_FP16) {
+        uint16_t h = enc_f16(y);
+        if ((h & 0x7fffu) == 0x7c00u) { h = (uint16_t)((h & 0x8000u) | 0x7bffu); *sat = true; }
+        else if ((h & 0x7fffu) > 0x7c00u) *sat = true;
+        return h;
+    }
+    uint16_t h = enc_bf16(y);
+    if ((h & 0x7fffu) == 0x7f80u) { h = (uint16_t)((h & 0x8000u) | 0x7f7fu); *sat = true; }
+    else if ((h & 0x7fffu) > 0x7f80u) *sat = true;
+    return h;
+}
+
+float decode(int storage, uint16_t h) { return storage == FDTD_FP16 ? dec_f16(h) : dec_bf16(h); }
+
+int scale_from(float m)
+{
+    if (!(m > 0.0f) || std::isinf(m)) return 0;
+    int e;
+    float fr = std::frexp(m, &e);
+    int cl = fr == 0.5f ? e - 1 : e;
+    int s = 10 - cl;
+    return std::max(-64, std::min(64, s));
+}
+
+void choose_scales(const float *m, float a_max, int *s)
+{
+    float all = 0.0f;
+    for (int c = 0; c < 6; ++c) all = std::max(all, m[c]);
+    for (int c = 0; c < 6; ++c) {
+        float v = m[c] > a_max ? m[c] : a_max;
+        if (!(v > 0.0f)) v = all;
+        s[c] = scale_from(v);
+    }
+}
+
+}  // namespace
+
+struct fdtd_solver {
+    yee::Layout L{};
+    double dx = 0, dy = 0, dz = 0, dt = 0;
+    int storage = FDTD_FP32;
+    int kernel = FDTD_KERNEL_AUTO;
+    int T = 2;
+    hipStream_t st = nullptr;
+    Dims d{};
+    char *ws = nullptr;
+    bool own_ws = false;
+    char *fbuf[2] = {nullptr, nullptr};
+    uint8_t *mat = nullptr;
+    yee::Ctrl *ctrl = nullptr;
+    int n_mat = 0;
+    float coef_h[256 * 4];
+    float ch[3];
+    double eps_h[256];
+    float4 *coef_d = nullptr;
+    double *eps_d = nullptr;
+    int cur = 0;
+    long long steps = 0;
+    long long block = 0;                // reduced-storage blocks run since the last upload
+    // sources
+    std::vector<int4> src_pos;
+    std::vector<int2> src_wave;
+    std::vector<float> samples;
+    int4 *src_pos_d = nullptr;
+    int2 *src_wave_d = nullptr;
+    float *samples_d = nullptr;
+    float a_max = 0.0f;
+    // probes
+    std::vector<int4> probe_pos;
+    int4 *probe_pos_d = nullptr;
+    double *probe_out_d = nullptr;
+    long long probe_cap = 0;            // rows
+    // diagnostics scratch
+    double *diag_part_d = nullptr;
+    double *diag_out_d = nullptr;
+};
+
+namespace {
+
+void free_dev(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+int upload_sources(fdtd_solver *s)
+{
+    free_dev(s->src_pos_d);
+    free_dev(s->src_wave_d);
+    free_dev(s->samples_d);
+    s->src_pos_d = nullptr;
+    s->src_wave_d = nullptr;
+    s->samples_d = nullptr;
+    const size_t n = s->src_pos.size();
+    if (n == 0) return FDTD_OK;
+    hipError_t e;
+    if ((e = hipMalloc(&s->src_pos_d, n * sizeof(int4))) != hipSuccess) return hip_fail(e, "hipMalloc(sources)");
+    if ((e = hipMalloc(&s->src_wave_d, n * sizeof(int2))) != hipSuccess) return hip_fail(e, "hipMalloc(sources)");
+    const size_t ns = std::max<size_t>(1, s->samples.size());
+    if ((e = hipMalloc(&s->samples_d, ns * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc(samples)");
+    if ((e = hipMemcpyAsync(s->src_pos_d, s->src_pos.data(), n * sizeof(int4), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipMemcpyAsync(s->src_wave_d, s->src_wave.data(), n * sizeof(int2), hipMemcpyHostToDevice, s->st)))
+        return hip_fail(e, "hipMemcpy(sources)");
+    if (!s->samples.empty() &&
+        (e = hipMemcpyAsync(s->samples_d, s->samples.data(), s->samples.size() * sizeof(float),
+                            hipMemcpyHostToDevice, s->st)))
+        return hip_fail(e, "hipMemcpy(samples)");
+    if ((e = hipStreamSynchronize(s->st))) return hip_fail(e, "hipStreamSynchronize");
+    return FDTD_OK;
+}
+
+int ensure_probe_rows(fdtd_solver *s, long long rows)
+{
+    if (s->probe_pos.empty() || rows <= s->probe_cap) return FDTD_OK;
+    long long cap = std::max(rows, 2 * s->probe_cap);
+    cap = std::max(cap, 256LL);
+    double *p = nullptr;
+    hipError_t e;
+    const size_t np = s->probe_pos.size();
+    if ((e = hipMalloc(&p, (size_t)cap * np * sizeof(double)))) return hip_fail(e, "hipMalloc(probes)");
+    if (s->probe_out_d) {
+        if ((e = hipMemcpyAsync(p, s->probe_out_d, (size_t)s->probe_cap * np * sizeof(double),
+                                hipMemcpyDeviceToDevice, s->st)))
+            return hip_fail(e, "hipMemcpy(probes)");
+        if ((e = hipStreamSynchronize(s->st))) return hip_fail(e, "hipStreamSynchronize");
+        free_dev(s->probe_out_d);
+    }
+    s->probe_out_d = p;
+    s->probe_cap = cap;
+    return FDTD_OK;
+}
+
+yee::SourceTable src_table(const fdtd_solver *s)
+{
+    yee::SourceTable t;
+    t.n = (int)s->src_pos.size();
+    t.pos = s->src_pos_d;
+    t.wave = s->src_wave_d;
+    t.samples = s->samples_d;
+    return t;
+}
+
+yee::ProbeTable probe_table(const fdtd_solver *s)
+{
+    yee::ProbeTable t;
+    t.n = (int)s->probe_pos.size();
+    t.pos = s->probe_pos_d;
+    t.out = s->probe_out_d;
+    t.base = 0;
+    return t;
+}
+
+yee::StorageBlock storage_block(const fdtd_solver *s)
+{
+    yee::StorageBlock b;
+    b.ctrl = s->ctrl;
+    b.slot_in = (int)(s->block % 3);
+    b.slot_out = (int)((s->block + 1) % 3);
+    b.slot_clear = (int)((s->block + 2) % 3);
+    b.par = (int)(s->block % 2);
+    b.a_max = s->a_max;
+    return b;
+}
+
+int read_ctrl(fdtd_solver *s, yee::Ctrl *out)
+{
+    hipError_t e = hipMemcpyAsync(out, s->ctrl, sizeof(yee::Ctrl), hipMemcpyDeviceToHost, s->st);
+    if (!e) e = hipStreamSynchronize(s->st);
+    return e ? hip_fail(e, "hipMemcpy(ctrl)") : FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fdtd_last_error(void) { return g_err.c_str(); }
+
+size_t fdtd_workspace_bytes(int nx, int ny, int nz, int storage)
+{
+    if (nx < 2 || ny < 2 || nz < 2 || storage < 0 || storage > 2) return 0;
+    if ((long long)(nx + 1) * (ny + 1) >= (1LL << 31)) return 0;
+    return dims_for(nx, ny, nz, storage).total;
+}
+
+int fdtd_coefficients(const fdtd_material *table, int n_materials, double dx, double dy, double dz, double dt,
+                      float *out, float *ch)
+{
+    if (!table || !out || !ch || n_materials < 1 || n_materials > 256) return fail(FDTD_EINVAL, "bad table");
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !(dt > 0)) return fail(FDTD_EINVAL, "bad spacing or dt");
+    for (int m = 0; m < n_materials; ++m) {
+        const double eps = table[m].eps_r, sig = table[m].sigma;
+        if (!(eps > 0) || !(sig >= 0) || table[m].mu_r != 1.0)
+            return fail(FDTD_EINVAL, "material " + std::to_string(m) + ": need eps_r > 0, sigma >= 0, mu_r = 1");
+        // semi-implicit loss: a = sigma dt / (2 eps0 eps_r)
+        const double a = (sig * dt) / (2.0 * EPS0 * eps);
+        const double cb = ((C0 * dt) / eps) / (1.0 + a);
+        out[4 * m + 0] = (float)((1.0 - a) / (1.0 + a));
+        out[4 * m + 1] = (float)(cb / dx);
+        out[4 * m + 2] = (float)(cb / dy);
+        out[4 * m + 3] = (float)(cb / dz);
+    }
+    ch[0] = (float)((C0 * dt) / dx);
+    ch[1] = (float)((C0 * dt) / dy);
+    ch[2] = (float)((C0 * dt) / dz);
+    return FDTD_OK;
+}
+
+int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy, double dz, double dt,
+                const fdtd_material *table, int n_materials, const uint8_t *mat_index, int storage,
+                void *device_workspace, size_t workspace_bytes, void *hip_stream)
+{
+    if (!out) return fail(FDTD_EINVAL, "out is NULL");
+    if (nx < 2 || ny < 2 || nz < 2) return fail(FDTD_EINVAL, "need at least 2 cells per axis");
+    if ((long long)(nx + 1) * (ny + 1) >= (1LL << 31)) return fail(FDTD_EINVAL, "plane too large");
+    if (storage < 0 || storage > 2) return fail(FDTD_EINVAL, "bad storage format");
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !(dt > 0)) return fail(FDTD_EINVAL, "bad spacing or dt");
+    const double limit = 1.0 / (C0 * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy) + 1.0 / (dz * dz)));
+    if (dt > limit) return fail(FDTD_ECFL, "dt exceeds the Courant limit " + std::to_string(limit));
+
+    fdtd_solver *s = new (std::nothrow) fdtd_solver();
+    if (!s) return fail(FDTD_ENOMEM, "host allocation failed");
+    int rc = fdtd_coefficients(table, n_materials, dx, dy, dz, dt, s->coef_h, s->ch);
+    if (rc) { delete s; return rc; }
+    const size_t ncell = (size_t)nx * ny * nz;
+    if (mat_index)
+        for (size_t q = 0; q < ncell; ++q)
+            if (mat_index[q] >= n_materials) {
+                delete s;
+                return fail(FDTD_EINVAL, "material index " + std::to_string(mat_index[q]) + " >= n_materials");
+            }
+    s->n_mat = n_materials;
+    for (int m = 0; m < n_materials; ++m) s->eps_h[m] = table[m].eps_r;
+    s->dx = dx; s->dy = dy; s->dz = dz; s->dt = dt;
+    s->storage = storage;
+    s->st = (hipStream_t)hip_stream;
+    s->d = dims_for(nx, ny, nz, storage);
+    s->L.nx = nx; s->L.ny = ny; s->L.nz = nz;
+    s->L.pitch = s->d.pitch; s->L.plane = s->d.plane; s->L.cstride = s->d.cstride;
+
+    hipError_t e;
+    if (device_workspace) {
+        if (workspace_bytes < s->d.total || ((uintptr_t)device_workspace & 255u)) {
+            delete s;
+            return fail(FDTD_ENOMEM, "workspace smaller than fdtd_workspace_bytes or not 256-byte aligned");
+        }
+        s->ws = (char *)device_workspace;
+    } else {
+        if ((e = hipMalloc(&s->ws, s->d.total))) { delete s; return fail(FDTD_ENOMEM, std::string("hipMalloc(workspace): ") + hipGetErrorString(e)); }
+        s->own_ws = true;
+    }
+    s->fbuf[0] = s->ws;
+    s->fbuf[1] = s->ws + s->d.fbytes;
+    s->mat = (uint8_t *)(s->ws + 2 * s->d.fbytes);
+    s->ctrl = (yee::Ctrl *)(s->ws + 2 * s->d.fbytes + s->d.matbytes);
+
+    // material index in the padded box layout (zero outside the cells)
+    {
+        std::vector<uint8_t> box((size_t)s->d.plane * (nz + 1), 0);
+        if (mat_index)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    std::memcpy(&box[(size_t)k * s->d.plane + (size_t)j * s->d.pitch],
+                                mat_index + ((size_t)k * ny + j) * nx, nx);
+        if ((e = hipMemcpyAsync(s->mat, box.data(), box.size(), hipMemcpyHostToDevice, s->st)) ||
+            (e = hipStreamSynchronize(s->st))) {
+            fdtd_destroy(s);
+            return hip_fail(e, "upload material index");
+        }
+    }
+    if ((e = hipMalloc(&s->coef_d, 256 * sizeof(float4))) || (e = hipMalloc(&s->eps_d, 256 * sizeof(double)))) {
+        fdtd_destroy(s);
+        return hip_fail(e, "hipMalloc(tables)");
+    }
+    if ((e = hipMemcpyAsync(s->coef_d, s->coef_h, n_materials * sizeof(float4), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipMemcpyAsync(s->eps_d, s->eps_h, n_materials * sizeof(double), hipMemcpyHostToDevice, s->st))) {
+        fdtd_destroy(s);
+        return hip_fail(e, "upload tables");
+    }
+    rc = fdtd_set_fields(s, nullptr);
+    if (rc) { fdtd_destroy(s); return rc; }
+    *out = s;
+    return FDTD_OK;
+}
+
+int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (kernel < 0 || kernel > 2) return fail(FDTD_EINVAL, "bad kernel family");
+    if (time_block < 1 || time_block > 4) return fail(FDTD_EINVAL, "time_block must be 1..4");
+    if (kernel == FDTD_KERNEL_PLAIN && s->storage != FDTD_FP32)
+        return fail(FDTD_EINVAL, "the plain kernel needs FP32 storage");
+    s->kernel = kernel;
+    s->T = time_block;
+    return FDTD_OK;
+}
+
+int fdtd_set_fields(fdtd_solver *s, const float *host)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    const int nx = s->L.nx, ny = s->L.ny, nz = s->L.nz;
+    const size_t nbox = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
+    const int es = elem_size(s->storage);
+    hipError_t e;
+    if ((e = hipStreamSynchronize(s->st))) return hip_fail(e, "hipStreamSynchronize");
+    yee::Ctrl ctrl;
+    std::memset(&ctrl, 0, sizeof(ctrl));
+    s->cur = 0;
+    s->block = 0;
+    if (!host) {
+        if ((e = hipMemsetAsync(s->fbuf[0], 0, s->d.fbytes, s->st)) ||
+            (e = hipMemcpyAsync(s->ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s->st)) ||
+            (e = hipStreamSynchronize(s->st)))
+            return hip_fail(e, "zero fields");
+        return FDTD_OK;
+    }
+    // clean copy: zero outside each component's range and on PEC edges
+    std::vector<float> f(host, host + 6 * nbox);
+    for (int c = 0; c < 6; ++c)
+        for (int k = 0; k <= nz; ++k)
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i <= nx; ++i) {
+                    const size_t p = (size_t)c * nbox + i + (size_t)(nx + 1) * (j + (size_t)(ny + 1) * k);
+                    bool keep = in_range(nx, ny, nz, c, i, j, k);
+                    if (c < 3) keep = keep && e_interior(nx, ny, nz, c, i, j, k);
+                    if (!keep) f[p] = 0.0f;
+                }
+    std::vector<uint16_t> q;
+    if (s->storage != FDTD_FP32) {
+        float m[6];
+        for (int c = 0; c < 6; ++c) {
+            m[c] = 0.0f;
+            for (size_t p = 0; p < nbox; ++p) m[c] = std::max(m[c], std::fabs(f[c * nbox + p]));
+        }
+        int sc[6];
+        choose_scales(m, s->a_max, sc);
+        q.resize(6 * nbox);
+        bool sat = false;
+        for (int c = 0; c < 6; ++c) {
+            const float upf = std::ldexp(1.0f, sc[c]), dnf = std::ldexp(1.0f, -sc[c]);
+            float mx = 0.0f;
+            for (size_t p = 0; p < nbox; ++p) {
+                uint16_t h = encode(s->storage, f[c * nbox + p] * upf, &sat);
+                q[c * nbox + p] = h;
+                const float v = std::fabs(decode(s->storage, h) * dnf);
+                if (v > mx) mx = v;           // NaN never compares greater
+            }
+            ctrl.scale[0][c] = sc[c];
+            std::memcpy(&ctrl.maxbits[0][c], &mx, 4);
+        }
+        ctrl.flag = sat ? 1u : 0u;
+    }
+    const void *src = s->storage == FDTD_FP32 ? (const void *)f.data() : (const void *)q.data();
+    if ((e = hipMemsetAsync(s->fbuf[0], 0, s->d.fbytes, s->st))) return hip_fail(e, "hipMemset");
+    for (int c = 0; c < 6; ++c) {
+        e = hipMemcpy2DAsync(s->fbuf[0] + (size_t)c * s->d.cstride * es, (size_t)s->d.pitch * es,
+                             (const char *)src + (size_t)c * nbox * es, (size_t)(nx + 1) * es,
+                             (size_t)(nx + 1) * es, (size_t)(ny + 1) * (nz + 1), hipMemcpyHostToDevice, s->st);
+        if (e) return hip_fail(e, "upload fields");
+    }
+    if ((e = hipMemcpyAsync(s->ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipStreamSynchronize(s->st)))
+        return hip_fail(e, "upload fields");
+    return FDTD_OK;
+}
+
+int fdtd_set_source(fdtd_solver *s, int comp, int i, int j, int k, const float *waveform, int n_samples, int *id)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (comp < 0 || comp > 2) return fail(FDTD_EINVAL, "sources act on E components only");
+    if (!e_interior(s->L.nx, s->L.ny, s->L.nz, comp, i, j, k))
+        return fail(FDTD_EINVAL, "source must sit on an interior (non-PEC) edge");
+    if (n_samples < 0 || (n_samples > 0 && !waveform)) return fail(FDTD_EINVAL, "bad waveform");
+    const int off = (int)s->samples.size();
+    float amax = s->a_max;
+    for (int n = 0; n < n_samples; ++n) {
+        if (!std::isfinite(waveform[n])) return fail(FDTD_EINVAL, "non-finite waveform sample");
+        amax = std::max(amax, std::fabs(waveform[n]));
+    }
+    s->samples.insert(s->samples.end(), waveform, waveform + n_samples);
+    s->src_pos.push_back(make_int4(comp, i, j, k));
+    s->src_wave.push_back(make_int2(off, n_samples));
+    s->a_max = amax;
+    int rc = upload_sources(s);
+    if (rc) return rc;
+    if (id) *id = (int)s->src_pos.size() - 1;
+    return FDTD_OK;
+}
+
+int fdtd_set_probe(fdtd_solver *s, int comp, int i, int j, int k, int *id)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (s->steps > 0) return fail(FDTD_ESTATE, "probes must be added before the first step");
+    if (comp < 0 || comp > 5 || !in_range(s->L.nx, s->L.ny, s->L.nz, comp, i, j, k))
+        return fail(FDTD_EINVAL, "probe outside the component's range");
+    s->probe_pos.push_back(make_int4(comp, i, j, k));
+    free_dev(s->probe_pos_d);
+    free_dev(s->probe_out_d);
+    s->probe_pos_d = nullptr;
+    s->probe_out_d = nullptr;
+    s->probe_cap = 0;
+    hipError_t e;
+    if ((e = hipMalloc(&s->probe_pos_d, s->probe_pos.size() * sizeof(int4))) ||
+        (e = hipMemcpyAsync(s->probe_pos_d, s->probe_pos.data(), s->probe_pos.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, s->st)) ||
+        (e = hipStreamSynchronize(s->st)))
+        return hip_fail(e, "upload probes");
+    if (id) *id = (int)s->probe_pos.size() - 1;
+    return FDTD_OK;
+}
+
+int fdtd_step(fdtd_solver *s, int n_steps)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (n_steps < 0) return fail(FDTD_EINVAL, "negative step count");
+    if (n_steps == 0) return FDTD_OK;
+    int rc = ensure_probe_rows(s, s->steps + n_steps);
+    if (rc) return rc;
+    const yee::SourceTable src = src_table(s);
+    const yee::ProbeTable probe = probe_table(s);
+    hipError_t e;
+    if (s->kernel == FDTD_KERNEL_PLAIN) {
+        yee::PlainArgs a;
+        a.L = s->L;
+        a.f = (float *)s->fbuf[s->cur];
+        a.mat = s->mat;
+        a.coef = s->coef_d;
+        a.n_mat = s->n_mat;
+        a.chx = s->ch[0]; a.chy = s->ch[1]; a.chz = s->ch[2];
+        for (int q = 0; q < n_steps; ++q) {
+            if ((e = yee::launch_plain_step(a, src, probe, s->steps + q, s->st))) return hip_fail(e, "plain step");
+        }
+        s->steps += n_steps;
+        return FDTD_OK;
+    }
+    yee::FusedArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.L = s->L;
+    a.mat = s->mat;
+    a.coef = s->coef_d;
+    a.n_mat = s->n_mat;
+    a.chx = s->ch[0]; a.chy = s->ch[1]; a.chz = s->ch[2];
+    a.src = src;
+    a.probe = probe;
+    int left = n_steps;
+    while (left > 0) {
+        const int T = s->T;
+        int len = T - (int)(s->steps % T);          // end blocks on multiples of T
+        len = std::min(len, left);
+        a.fin = s->fbuf[s->cur];
+        a.fout = s->fbuf[s->cur ^ 1];
+        a.step0 = s->steps;
+        a.sb = storage_block(s);
+        if ((e = yee::launch_fused(s->storage, len, a, s->st))) return hip_fail(e, "fused step");
+        s->cur ^= 1;
+        s->steps += len;
+        s->block += 1;
+        left -= len;
+    }
+    return FDTD_OK;
+}
+
+int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst)
+{
+    if (!s || !host_dst) return fail(FDTD_EINVAL, "NULL argument");
+    if (comp < 0 || comp > 5) return fail(FDTD_EINVAL, "bad component");
+    const int nx = s->L.nx, ny = s->L.ny, nz = s->L.nz;
+    const size_t nbox = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
+    const int es = elem_size(s->storage);
+    hipError_t e;
+    std::vector<uint16_t> q;
+    void *dst = host_dst;
+    if (s->storage != FDTD_FP32) {
+        q.resize(nbox);
+        dst = q.data();
+    }
+    e = hipMemcpy2DAsync(dst, (size_t)(nx + 1) * es, s->fbuf[s->cur] + (size_t)comp * s->d.cstride * es,
+                         (size_t)s->d.pitch * es, (size_t)(nx + 1) * es, (size_t)(ny + 1) * (nz + 1),
+                         hipMemcpyDeviceToHost, s->st);
+    if (!e) e = hipStreamSynchronize(s->st);
+    if (e) return hip_fail(e, "read fields");
+    if (s->storage != FDTD_FP32) {
+        yee::Ctrl c;
+        int rc = read_ctrl(s, &c);
+        if (rc) return rc;
+        const float dnf = std::ldexp(1.0f, -c.scale[s->block % 2][comp]);
+        for (size_t p = 0; p < nbox; ++p) host_dst[p] = decode(s->storage, q[p]) * dnf;
+    }
+    return FDTD_OK;
+}
+
+int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int n_steps)
+{
+    if (!s || (!host_dst && n_steps > 0)) return fail(FDTD_EINVAL, "NULL argument");
+    if (first_step < 0 || n_steps < 0 || first_step + n_steps > s->steps)
+        return fail(FDTD_EINVAL, "requested steps have not been run");
+    const size_t np = s->probe_pos.size();
+    if (np == 0 || n_steps == 0) return FDTD_OK;
+    hipError_t e = hipMemcpyAsync(host_dst, s->probe_out_d + (size_t)first_step * np,
+                                  (size_t)n_steps * np * sizeof(double), hipMemcpyDeviceToHost, s->st);
+    if (!e) e = hipStreamSynchronize(s->st);
+    return e ? hip_fail(e, "read probes") : FDTD_OK;
+}
+
+int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
+{
+    if (!s || !out) return fail(FDTD_EINVAL, "NULL argument");
+    hipError_t e;
+    if (!s->diag_part_d) {
+        const size_t nb = (size_t)yee::diag_blocks(s->L);
+        if ((e = hipMalloc(&s->diag_part_d, nb * yee::DIAG_W * sizeof(double))) ||
+            (e = hipMalloc(&s->diag_out_d, yee::DIAG_W * sizeof(double))))
+            return hip_fail(e, "hipMalloc(diagnostics)");
+    }
+    yee::DiagArgs a;
+    a.L = s->L;
+    a.f = s->fbuf[s->cur];
+    a.mat = s->mat;
+    a.coef = s->coef_d;
+    a.eps = s->eps_d;
+    a.n_mat = s->n_mat;
+    a.chx = s->ch[0]; a.chy = s->ch[1]; a.chz = s->ch[2];
+    a.idx = 1.0 / s->dx; a.idy = 1.0 / s->dy; a.idz = 1.0 / s->dz;
+    a.partial = s->diag_part_d;
+    a.sb = storage_block(s);
+    if ((e = yee::launch_diag(s->storage, a, s->diag_out_d, s->st))) return hip_fail(e, "diagnostics");
+    double v[yee::DIAG_W];
+    e = hipMemcpyAsync(v, s->diag_out_d, sizeof(v), hipMemcpyDeviceToHost, s->st);
+    if (!e) e = hipStreamSynchronize(s->st);
+    if (e) return hip_fail(e, "diagnostics");
+    out->energy = v[0];
+    out->div_e_sumsq = v[1];
+    out->div_h_sumsq = v[2];
+    out->div_e_max = v[3];
+    out->div_h_max = v[4];
+    for (int c = 0; c < 6; ++c) out->max_abs[c] = v[5 + c];
+    return FDTD_OK;
+}
+
+int fdtd_steps_done(const fdtd_solver *s, long long *n)
+{
+    if (!s || !n) return fail(FDTD_EINVAL, "NULL argument");
+    *n = s->steps;
+    return FDTD_OK;
+}
+
+int fdtd_storage_state(fdtd_solver *s, int scales[6], int *saturated)
+{
+    if (!s || !scales || !saturated) return fail(FDTD_EINVAL, "NULL argument");
+    if (s->storage == FDTD_FP32) {
+        hipError_t e = hipStreamSynchronize(s->st);
+        if (e) return hip_fail(e, "hipStreamSynchronize");
+        for (int c = 0; c < 6; ++c) scales[c] = 0;
+        *saturated = 0;
+        return FDTD_OK;
+    }
+    yee::Ctrl c;
+    int rc = read_ctrl(s, &c);
+    if (rc) return rc;
+    for (int q = 0; q < 6; ++q) scales[q] = c.scale[s->block % 2][q];
+    *saturated = c.flag ? 1 : 0;
+    return FDTD_OK;
+}
+
+int fdtd_synchronize(fdtd_solver *s)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    hipError_t e = hipStreamSynchronize(s->st);
+    if (e) return hip_fail(e, "hipStreamSynchronize");
+    if (s->storage != FDTD_FP32) {
+        yee::Ctrl c;
+        int rc = read_ctrl(s, &c);
+        if (rc) return rc;
+        if (c.flag) return fail(FDTD_ERANGE, "reduced storage saturated or stored a non-finite value");
+    }
+    return FDTD_OK;
+}
+
+void fdtd_destroy(fdtd_solver *s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->st);
+    if (s->own_ws) free_dev(s->ws);
+    free_dev(s->coef_d);
+    free_dev(s->eps_d);
+    free_dev(s->src_pos_d);
+    free_dev(s->src_wave_d);
+    free_dev(s->samples_d);
+    free_dev(s->probe_pos_d);
+    free_dev(s->probe_out_d);
+    free_dev(s->diag_part_d);
+    free_dev(s->diag_out_d);
+    delete s;
+}
+
+}  // extern "C"

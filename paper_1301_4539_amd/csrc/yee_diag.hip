@@ -1,0 +1,155 @@
+// FP64 diagnostics of a state (E^n, H^{n-1/2}):
+//   energy W^n = 1/2 sum eps_r E^n.E^n + 1/2 sum H^{n-1/2}.H^{n+1/2}, the
+//     quantity the leapfrog conserves in a lossless PEC box (consequence of
+//     the discrete antisymmetry noted in Sec. 2.1); H^{n+1/2} is recomputed
+//     in registers with the same FP32 operation order as the update kernels;
+//   div(eps_r E) at interior nodes and div(H) at cell centres: largest
+//     magnitude and sum of squares (both constant in time without sources
+//     and losses);
+//   largest |value| per component.
+// Reduction is deterministic: each block reduces its points in a fixed
+// tree, then one block sums the block partials in index order.
+
+#include "yee_device.hpp"
+#include "yee_internal.hpp"
+
+namespace yee {
+
+namespace {
+
+constexpr int DBX = 64, DBY = 4, DT = DBX * DBY;
+
+template <class Codec>
+__global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
+{
+    using S = typename Codec::T;
+    __shared__ double s_eps[256];
+    __shared__ double s_red[DT];
+    const int t = threadIdx.y * DBX + threadIdx.x;
+    for (int q = t; q < a.n_mat; q += DT) s_eps[q] = a.eps[q];
+    __syncthreads();
+
+    const Layout &L = a.L;
+    const int i = blockIdx.x * DBX + threadIdx.x;
+    const int j = blockIdx.y * DBY + threadIdx.y;
+    const int k = blockIdx.z;
+    const S *f = static_cast<const S *>(a.f);
+    float dn[6];
+    for (int c = 0; c < 6; ++c) dn[c] = Codec::scaled ? ldexpf(1.0f, -a.sb.ctrl->scale[a.sb.par][c]) : 1.0f;
+    auto F = [&](int c, long long p) -> float { return Codec::load(f + c * L.cstride + p, dn[c]); };
+
+    double v[DIAG_W];
+    for (int q = 0; q < DIAG_W; ++q) v[q] = 0.0;
+    if (i <= L.nx && j <= L.ny) {
+        const int nx = L.nx, ny = L.ny, nz = L.nz;
+        const long long p = k * L.plane + (long long)j * L.pitch + i;
+        // owner-cell permittivity of an E edge, zero on wall (PEC) edges
+        auto eps_edge = [&](int c, int ii, int jj, int kk) -> double {
+            bool interior = c == 0 ? (ii < nx && jj > 0 && jj < ny && kk > 0 && kk < nz)
+                          : c == 1 ? (jj < ny && ii > 0 && ii < nx && kk > 0 && kk < nz)
+                                   : (kk < nz && ii > 0 && ii < nx && jj > 0 && jj < ny);
+            if (!interior) return 0.0;
+            return s_eps[a.mat[kk * L.plane + (long long)jj * L.pitch + ii]];
+        };
+        const float ex = F(0, p), ey = F(1, p), ez = F(2, p);
+        const float hx = F(3, p), hy = F(4, p), hz = F(5, p);
+        // electric energy
+        v[0] += 0.5 * eps_edge(0, i, j, k) * (double)ex * (double)ex;
+        v[0] += 0.5 * eps_edge(1, i, j, k) * (double)ey * (double)ey;
+        v[0] += 0.5 * eps_edge(2, i, j, k) * (double)ez * (double)ez;
+        // magnetic energy with H^{n+1/2} from the Faraday half-step
+        if (j < ny && k < nz) {
+            const float h1 = __builtin_fmaf(-a.chy, F(2, p + L.pitch) - ez, __builtin_fmaf(a.chz, F(1, p + L.plane) - ey, hx));
+            v[0] += 0.5 * (double)hx * (double)h1;
+        }
+        if (i < nx && k < nz) {
+            const float h1 = __builtin_fmaf(-a.chz, F(0, p + L.plane) - ex, __builtin_fmaf(a.chx, F(2, p + 1) - ez, hy));
+            v[0] += 0.5 * (double)hy * (double)h1;
+        }
+        if (i < nx && j < ny) {
+            const float h1 = __builtin_fmaf(-a.chx, F(1, p + 1) - ey, __builtin_fmaf(a.chy, F(0, p + L.pitch) - ex, hz));
+            v[0] += 0.5 * (double)hz * (double)h1;
+        }
+        // div(eps_r E) at interior nodes
+        if (i > 0 && i < nx && j > 0 && j < ny && k > 0 && k < nz) {
+            double d = (eps_edge(0, i, j, k) * ex - eps_edge(0, i - 1, j, k) * F(0, p - 1)) * a.idx;
+            d += (eps_edge(1, i, j, k) * ey - eps_edge(1, i, j - 1, k) * F(1, p - L.pitch)) * a.idy;
+            d += (eps_edge(2, i, j, k) * ez - eps_edge(2, i, j, k - 1) * F(2, p - L.plane)) * a.idz;
+            v[1] = d * d;
+            v[3] = fabs(d);
+        }
+        // div(H) at cell centres
+        if (i < nx && j < ny && k < nz) {
+            double d = ((double)F(3, p + 1) - hx) * a.idx + ((double)F(4, p + L.pitch) - hy) * a.idy
+                     + ((double)F(5, p + L.plane) - hz) * a.idz;
+            v[2] = d * d;
+            v[4] = fabs(d);
+        }
+        v[5] = fabs(ex); v[6] = fabs(ey); v[7] = fabs(ez);
+        v[8] = fabs(hx); v[9] = fabs(hy); v[10] = fabs(hz);
+    }
+    // fixed-tree block reduction, one quantity at a time
+    const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    for (int q = 0; q < DIAG_W; ++q) {
+        s_red[t] = v[q];
+        __syncthreads();
+        for (int s = DT / 2; s > 0; s >>= 1) {
+            if (t < s) s_red[t] = (q == 0 || q == 1 || q == 2) ? s_red[t] + s_red[t + s] : fmax(s_red[t], s_red[t + s]);
+            __syncthreads();
+        }
+        if (t == 0) a.partial[blk * DIAG_W + q] = s_red[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void diag_final(const double *partial, long long nblk, double *out)
+{
+    __shared__ double s_red[256];
+    const int t = threadIdx.x;
+    for (int q = 0; q < DIAG_W; ++q) {
+        const bool sum = q <= 2;
+        double acc = 0.0;
+        for (long long b = t; b < nblk; b += 256) {
+            const double x = partial[b * DIAG_W + q];
+            acc = sum ? acc + x : fmax(acc, x);
+        }
+        s_red[t] = acc;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (t < s) s_red[t] = sum ? s_red[t] + s_red[t + s] : fmax(s_red[t], s_red[t + s]);
+            __syncthreads();
+        }
+        if (t == 0) out[q] = s_red[0];
+        __syncthreads();
+    }
+}
+
+template <class Codec>
+hipError_t launch_diag_t(const DiagArgs &a, double *out, hipStream_t st)
+{
+    dim3 block(DBX, DBY, 1);
+    dim3 grid((a.L.nx + 1 + DBX - 1) / DBX, (a.L.ny + 1 + DBY - 1) / DBY, a.L.nz + 1);
+    hipLaunchKernelGGL(diag_points<Codec>, grid, block, 0, st, a);
+    const long long nblk = (long long)grid.x * grid.y * grid.z;
+    hipLaunchKernelGGL(diag_final, dim3(1), dim3(256), 0, st, (const double *)a.partial, nblk, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int diag_blocks(const Layout &L)
+{
+    return ((L.nx + 1 + DBX - 1) / DBX) * ((L.ny + 1 + DBY - 1) / DBY) * (L.nz + 1);
+}
+
+hipError_t launch_diag(int storage, const DiagArgs &a, double *out, hipStream_t st)
+{
+    switch (storage) {
+    case 0: return launch_diag_t<CodecF32>(a, out, st);
+    case 1: return launch_diag_t<CodecF16>(a, out, st);
+    case 2: return launch_diag_t<CodecBF16>(a, out, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace yee

@@ -1,0 +1,101 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the Yee FDTD library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace yee {
+
+// Device field layout: component c of buffer b starts at base + c*cstride
+// (elements); point (i,j,k) sits at k*plane + j*pitch + i with
+// pitch >= nx+1 and plane = pitch*(ny+1).  The material index uses the
+// same offsets (one byte per point; bytes outside the cell range are 0).
+struct Layout {
+    int nx, ny, nz;
+    int pitch;
+    long long plane;
+    long long cstride;
+};
+
+// Reduced-storage control block (device).  maxbits holds, per component,
+// the largest |stored value| as float bits (non-negative floats order like
+// their bit patterns); three slots rotate so that the block that reads one
+// slot fills the next and clears the one after.  scale[par] is the scale
+// of the currently stored fields.
+struct Ctrl {
+    uint32_t maxbits[3][6];
+    int32_t scale[2][6];
+    uint32_t flag;
+    uint32_t pad[3];
+};
+
+struct SourceTable {
+    int n;
+    const int4 *pos;      // (comp, i, j, k)
+    const int2 *wave;     // (offset into samples, n_samples)
+    const float *samples;
+};
+
+struct ProbeTable {
+    int n;
+    const int4 *pos;      // (comp, i, j, k)
+    double *out;          // rows of n doubles, row = step - base
+    long long base;       // step of row 0
+};
+
+struct StorageBlock {
+    Ctrl *ctrl;
+    int slot_in, slot_out, slot_clear, par;
+    float a_max;          // largest |source sample|
+};
+
+struct FusedArgs {
+    Layout L;
+    const void *fin;
+    void *fout;
+    const uint8_t *mat;
+    const float4 *coef;   // per material (Ca, Cbx, Cby, Cbz)
+    int n_mat;
+    float chx, chy, chz;
+    int ntx, nty, ntz, nwg;
+    int zc;               // planes per z chunk
+    long long step0;      // absolute step index advanced by time level 1
+    SourceTable src;
+    ProbeTable probe;
+    StorageBlock sb;
+};
+
+struct PlainArgs {
+    Layout L;
+    float *f;             // in-place FP32 fields
+    const uint8_t *mat;
+    const float4 *coef;
+    int n_mat;
+    float chx, chy, chz;
+};
+
+struct DiagArgs {
+    Layout L;
+    const void *f;
+    const uint8_t *mat;
+    const float4 *coef;
+    const double *eps;    // per material eps_r
+    int n_mat;
+    float chx, chy, chz;
+    double idx, idy, idz; // 1/dx, 1/dy, 1/dz
+    double *partial;      // per block: 11 doubles
+    StorageBlock sb;      // scale[par] decodes the stored fields
+};
+
+enum { DIAG_W = 11 };     // energy, div_e_sumsq, div_h_sumsq, div_e_max, div_h_max, max_abs[6]
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_plain_step(const PlainArgs &a, const SourceTable &src, const ProbeTable &probe,
+                             long long step, hipStream_t st);
+hipError_t launch_fused(int storage, int T, const FusedArgs &a, hipStream_t st);
+void fused_geometry(int T, const Layout &L, int *ntx, int *nty, int *ntz, int *zc, int *threads);
+hipError_t launch_diag(int storage, const DiagArgs &a, double *out11, hipStream_t st);
+int diag_blocks(const Layout &L);
+
+}  // namespace yee

@@ -1,0 +1,116 @@
+// Plain two-pass Yee step: an in-place H pass over the whole grid, then an
+// in-place E pass (the standard loop structure of Sec. 2.2, one thread per
+// node-box point updating all three components there).  FP32 storage only.
+// Each pass streams its fields from HBM once; the E pass also reads the
+// uint8 material index and looks the coefficients up in an LDS table.
+
+#include "yee_device.hpp"
+#include "yee_internal.hpp"
+
+namespace yee {
+
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+__global__ __launch_bounds__(BX *BY) void h_plain(PlainArgs a)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    const Layout &L = a.L;
+    if (i > L.nx || j > L.ny) return;
+    float *ex = a.f, *ey = a.f + L.cstride, *ez = a.f + 2 * L.cstride;
+    float *hx = a.f + 3 * L.cstride, *hy = a.f + 4 * L.cstride, *hz = a.f + 5 * L.cstride;
+    const long long p = k * L.plane + (long long)j * L.pitch + i;
+    // Faraday: H -= c dt curl E, z-difference term first, then y (cyclic).
+    if (j < L.ny && k < L.nz) {
+        float dey_z = ey[p + L.plane] - ey[p];
+        float dez_y = ez[p + L.pitch] - ez[p];
+        hx[p] = __builtin_fmaf(-a.chy, dez_y, __builtin_fmaf(a.chz, dey_z, hx[p]));
+    }
+    if (i < L.nx && k < L.nz) {
+        float dez_x = ez[p + 1] - ez[p];
+        float dex_z = ex[p + L.plane] - ex[p];
+        hy[p] = __builtin_fmaf(-a.chz, dex_z, __builtin_fmaf(a.chx, dez_x, hy[p]));
+    }
+    if (i < L.nx && j < L.ny) {
+        float dex_y = ex[p + L.pitch] - ex[p];
+        float dey_x = ey[p + 1] - ey[p];
+        hz[p] = __builtin_fmaf(-a.chx, dey_x, __builtin_fmaf(a.chy, dex_y, hz[p]));
+    }
+}
+
+__global__ __launch_bounds__(BX *BY) void e_plain(PlainArgs a)
+{
+    __shared__ float4 s_coef[256];
+    const int t = threadIdx.y * BX + threadIdx.x;
+    for (int q = t; q < a.n_mat; q += BX * BY) s_coef[q] = a.coef[q];
+    __syncthreads();
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    const Layout &L = a.L;
+    if (i > L.nx || j > L.ny) return;
+    float *ex = a.f, *ey = a.f + L.cstride, *ez = a.f + 2 * L.cstride;
+    const float *hx = a.f + 3 * L.cstride, *hy = a.f + 4 * L.cstride, *hz = a.f + 5 * L.cstride;
+    const long long p = k * L.plane + (long long)j * L.pitch + i;
+    const float4 cf = s_coef[a.mat[p]];   // Ca, Cbx, Cby, Cbz of the owner cell
+    const bool kin = k > 0 && k < L.nz, jin = j > 0 && j < L.ny, iin = i > 0 && i < L.nx;
+    // Ampere with loss: E = Ca E + Cb curl H on edges not tangential to a wall.
+    if (i < L.nx && jin && kin) {
+        float dhz_y = hz[p] - hz[p - L.pitch];
+        float dhy_z = hy[p] - hy[p - L.plane];
+        ex[p] = __builtin_fmaf(-cf.w, dhy_z, __builtin_fmaf(cf.z, dhz_y, cf.x * ex[p]));
+    }
+    if (j < L.ny && iin && kin) {
+        float dhx_z = hx[p] - hx[p - L.plane];
+        float dhz_x = hz[p] - hz[p - 1];
+        ey[p] = __builtin_fmaf(-cf.y, dhz_x, __builtin_fmaf(cf.w, dhx_z, cf.x * ey[p]));
+    }
+    if (k < L.nz && iin && jin) {
+        float dhy_x = hy[p] - hy[p - 1];
+        float dhx_y = hx[p] - hx[p - L.pitch];
+        ez[p] = __builtin_fmaf(-cf.z, dhx_y, __builtin_fmaf(cf.y, dhy_x, cf.x * ez[p]));
+    }
+}
+
+// Soft sources of step `step`, added in source order by one thread.
+__global__ void src_plain(float *f, Layout L, SourceTable s, long long step)
+{
+    for (int q = 0; q < s.n; ++q) {
+        int4 d = s.pos[q];
+        int2 w = s.wave[q];
+        if (step < w.y) {
+            long long p = d.x * L.cstride + d.w * L.plane + (long long)d.z * L.pitch + d.y;
+            f[p] = f[p] + s.samples[w.x + step];
+        }
+    }
+}
+
+__global__ void probe_plain(const float *f, Layout L, ProbeTable pt, long long step)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= pt.n) return;
+    int4 d = pt.pos[q];
+    long long p = d.x * L.cstride + d.w * L.plane + (long long)d.z * L.pitch + d.y;
+    pt.out[(step - pt.base) * pt.n + q] = (double)f[p];
+}
+
+}  // namespace
+
+hipError_t launch_plain_step(const PlainArgs &a, const SourceTable &src, const ProbeTable &probe,
+                             long long step, hipStream_t st)
+{
+    dim3 block(BX, BY, 1);
+    dim3 grid((a.L.nx + 1 + BX - 1) / BX, (a.L.ny + 1 + BY - 1) / BY, a.L.nz + 1);
+    hipLaunchKernelGGL(h_plain, grid, block, 0, st, a);
+    hipLaunchKernelGGL(e_plain, grid, block, 0, st, a);
+    if (src.n > 0) hipLaunchKernelGGL(src_plain, dim3(1), dim3(1), 0, st, a.f, a.L, src, step);
+    if (probe.n > 0)
+        hipLaunchKernelGGL(probe_plain, dim3((probe.n + 63) / 64), dim3(64), 0, st, (const float *)a.f, a.L,
+                           probe, step);
+    return hipGetLastError();
+}
+
+}  // namespace yee

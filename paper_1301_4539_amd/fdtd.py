@@ -1,0 +1,223 @@
+"""Python binding of the Yee FDTD C ABI (include/fdtd.h) -- marshalling only.
+
+Every step of the solver runs in the HIP library libfdtd.so; this module
+only converts arguments.  PyTorch provides device memory (the workspace is
+a torch uint8 tensor) and the stream (torch's current stream).  There is no
+fallback: if libfdtd.so is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from .workload import FP32, FP16, BF16  # noqa: F401  (re-exported storage codes)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdtd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ECFL, ERANGE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_FUSED = 0, 1, 2
+
+_lib = None
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fdtd error {code}: {msg}")
+        self.code = code
+
+
+class _Material(C.Structure):
+    _fields_ = [("eps_r", C.c_double), ("mu_r", C.c_double), ("sigma", C.c_double)]
+
+
+class _Diag(C.Structure):
+    _fields_ = [("energy", C.c_double), ("div_e_max", C.c_double), ("div_e_sumsq", C.c_double),
+                ("div_h_max", C.c_double), ("div_h_sumsq", C.c_double), ("max_abs", C.c_double * 6)]
+
+
+def lib():
+    """Load libfdtd.so (after torch, so the process uses one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  -- loads the HIP runtime the library binds to
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i, d, sz, ll = C.c_void_p, C.c_int, C.c_double, C.c_size_t, C.c_longlong
+        L.fdtd_workspace_bytes.argtypes = [i, i, i, i]
+        L.fdtd_workspace_bytes.restype = sz
+        L.fdtd_create.argtypes = [C.POINTER(vp), i, i, i, d, d, d, d, C.POINTER(_Material), i, vp, i, vp, sz, vp]
+        L.fdtd_set_kernel.argtypes = [vp, i, i]
+        L.fdtd_set_fields.argtypes = [vp, vp]
+        L.fdtd_set_source.argtypes = [vp, i, i, i, i, vp, i, C.POINTER(i)]
+        L.fdtd_set_probe.argtypes = [vp, i, i, i, i, C.POINTER(i)]
+        L.fdtd_step.argtypes = [vp, i]
+        L.fdtd_read_fields.argtypes = [vp, i, vp]
+        L.fdtd_read_probes.argtypes = [vp, vp, ll, i]
+        L.fdtd_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
+        L.fdtd_steps_done.argtypes = [vp, C.POINTER(ll)]
+        L.fdtd_storage_state.argtypes = [vp, C.POINTER(i), C.POINTER(i)]
+        L.fdtd_synchronize.argtypes = [vp]
+        L.fdtd_destroy.argtypes = [vp]
+        L.fdtd_destroy.restype = None
+        L.fdtd_last_error.restype = C.c_char_p
+        L.fdtd_coefficients.argtypes = [C.POINTER(_Material), i, d, d, d, d, vp, vp]
+        for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
+                     "fdtd_step", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
+                     "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients"):
+            getattr(L, name).restype = i
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise FdtdError(rc, lib().fdtd_last_error().decode())
+
+
+def _materials(eps_r, sigma, mu_r=None):
+    eps_r = np.asarray(eps_r, dtype=np.float64).ravel()
+    sigma = np.asarray(sigma, dtype=np.float64).ravel()
+    mu_r = np.ones_like(eps_r) if mu_r is None else np.asarray(mu_r, dtype=np.float64).ravel()
+    arr = (_Material * len(eps_r))()
+    for m in range(len(eps_r)):
+        arr[m].eps_r, arr[m].mu_r, arr[m].sigma = float(eps_r[m]), float(mu_r[m]), float(sigma[m])
+    return arr, len(eps_r)
+
+
+def coefficients(eps_r, sigma, dx, dy, dz, dt, mu_r=None):
+    """The library's FP32 coefficient table (n_mat, 4) and ch (3,)."""
+    arr, n = _materials(eps_r, sigma, mu_r)
+    out = np.zeros((n, 4), np.float32)
+    ch = np.zeros(3, np.float32)
+    _check(lib().fdtd_coefficients(arr, n, dx, dy, dz, dt, out.ctypes.data, ch.ctypes.data))
+    return out, ch
+
+
+def workspace_bytes(nx, ny, nz, storage=FP32):
+    return int(lib().fdtd_workspace_bytes(nx, ny, nz, storage))
+
+
+class Solver:
+    """One FDTD solve on the GPU.  Arrays use the (nz+1, ny+1, nx+1) node box."""
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, dt, eps_r, sigma, mat=None, storage=FP32,
+                 kernel=KERNEL_AUTO, time_block=2, mu_r=None, torch_workspace=True, stream=None):
+        import torch
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.storage = storage
+        arr, n_mat = _materials(eps_r, sigma, mu_r)
+        mat_ptr = None
+        if mat is not None:
+            self._mat = np.ascontiguousarray(mat, dtype=np.uint8).reshape(nz, ny, nx)
+            mat_ptr = self._mat.ctypes.data
+        self._ws = None
+        ws_ptr, ws_bytes = None, 0
+        if torch_workspace:
+            ws_bytes = workspace_bytes(nx, ny, nz, storage)
+            if ws_bytes == 0:
+                raise FdtdError(EINVAL, "invalid dimensions or storage")
+            self._ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+            ws_ptr = self._ws.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = C.c_void_p()
+        _check(lib().fdtd_create(C.byref(h), nx, ny, nz, dx, dy, dz, dt, arr, n_mat, mat_ptr, storage,
+                                 ws_ptr, ws_bytes, C.c_void_p(stream.cuda_stream)))
+        self._h = h
+        self.n_probes = 0
+        self.set_kernel(kernel, time_block)
+
+    @classmethod
+    def from_workload(cls, wl, storage=None, kernel=KERNEL_AUTO, time_block=2, **kw):
+        s = cls(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.dt, wl.eps_r, wl.sigma, wl.mat,
+                storage=wl.storage if storage is None else storage, kernel=kernel, time_block=time_block, **kw)
+        for q, (c, i, j, k) in enumerate(wl.sources):
+            s.add_source(c, i, j, k, wl.waveforms[q].astype(np.float32))
+        for (c, i, j, k) in wl.probes:
+            s.add_probe(c, i, j, k)
+        if wl.init_fields is not None:
+            s.set_fields(wl.init_fields.astype(np.float32))
+        return s
+
+    def set_kernel(self, kernel, time_block):
+        _check(lib().fdtd_set_kernel(self._h, kernel, time_block))
+
+    def set_fields(self, f: Optional[np.ndarray]):
+        if f is None:
+            _check(lib().fdtd_set_fields(self._h, None))
+            return
+        f = np.ascontiguousarray(f, dtype=np.float32)
+        assert f.shape == (6, self.nz + 1, self.ny + 1, self.nx + 1)
+        _check(lib().fdtd_set_fields(self._h, f.ctypes.data))
+
+    def add_source(self, comp, i, j, k, waveform) -> int:
+        w = np.ascontiguousarray(waveform, dtype=np.float32)
+        sid = C.c_int()
+        _check(lib().fdtd_set_source(self._h, comp, i, j, k, w.ctypes.data, len(w), C.byref(sid)))
+        return sid.value
+
+    def add_probe(self, comp, i, j, k) -> int:
+        pid = C.c_int()
+        _check(lib().fdtd_set_probe(self._h, comp, i, j, k, C.byref(pid)))
+        self.n_probes = pid.value + 1
+        return pid.value
+
+    def step(self, n: int):
+        _check(lib().fdtd_step(self._h, int(n)))
+
+    def read_field(self, comp) -> np.ndarray:
+        out = np.empty((self.nz + 1, self.ny + 1, self.nx + 1), np.float32)
+        _check(lib().fdtd_read_fields(self._h, comp, out.ctypes.data))
+        return out
+
+    def read_fields(self) -> np.ndarray:
+        return np.stack([self.read_field(c) for c in range(6)])
+
+    def read_probes(self, first: int, n: int) -> np.ndarray:
+        out = np.zeros((n, max(self.n_probes, 1)), np.float64)
+        _check(lib().fdtd_read_probes(self._h, out.ctypes.data, first, n))
+        return out[:, :self.n_probes]
+
+    def diagnostics(self) -> dict:
+        d = _Diag()
+        _check(lib().fdtd_diagnostics(self._h, C.byref(d)))
+        return {"energy": d.energy, "div_e_max": d.div_e_max, "div_e_sumsq": d.div_e_sumsq,
+                "div_h_max": d.div_h_max, "div_h_sumsq": d.div_h_sumsq, "max_abs": list(d.max_abs)}
+
+    def steps_done(self) -> int:
+        n = C.c_longlong()
+        _check(lib().fdtd_steps_done(self._h, C.byref(n)))
+        return n.value
+
+    def storage_state(self):
+        sc = (C.c_int * 6)()
+        sat = C.c_int()
+        _check(lib().fdtd_storage_state(self._h, sc, C.byref(sat)))
+        return list(sc), bool(sat.value)
+
+    def synchronize(self):
+        _check(lib().fdtd_synchronize(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fdtd_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

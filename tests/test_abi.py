@@ -1,0 +1,74 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/fdtd.h declares, validates its arguments before touching a device,
+and derives the same FP32 coefficients as the oracle (FP64, rounded once)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_4539_amd import fdtd, workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = _declared()
+    assert len(names) >= 15
+    L = fdtd.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_workspace_bytes():
+    assert fdtd.workspace_bytes(1, 4, 4) == 0
+    assert fdtd.workspace_bytes(4, 4, 4, 7) == 0
+    b32 = fdtd.workspace_bytes(256, 256, 256, W.FP32)
+    b16 = fdtd.workspace_bytes(256, 256, 256, W.FP16)
+    assert b32 > 2 * 6 * 4 * 257 ** 3 and b16 < b32
+    assert b32 % 256 == 0
+
+
+def _create(nx=8, ny=8, nz=8, d=1e-3, dt=None, eps=(1.0,), sig=(0.0,), mu=None, mat=None, storage=0):
+    arr, n = fdtd._materials(eps, sig, mu)
+    dt = W.courant_dt(d, d, d) if dt is None else dt
+    h = C.c_void_p()
+    mptr = None if mat is None else np.ascontiguousarray(mat, np.uint8).ctypes.data
+    rc = fdtd.lib().fdtd_create(C.byref(h), nx, ny, nz, d, d, d, dt, arr, n, mptr, storage, None, 0, None)
+    return rc
+
+
+def test_create_rejects_before_touching_the_device():
+    d = 1e-3
+    limit = 1.0 / (W.C0 * np.sqrt(3.0 / d ** 2))
+    assert _create(dt=limit * 1.0001) == fdtd.ECFL
+    assert "Courant" in fdtd.lib().fdtd_last_error().decode()
+    assert _create(nx=1) == fdtd.EINVAL
+    assert _create(mu=(2.0,)) == fdtd.EINVAL
+    assert _create(eps=(0.0,)) == fdtd.EINVAL
+    assert _create(sig=(-1.0,)) == fdtd.EINVAL
+    assert _create(storage=3) == fdtd.EINVAL
+    bad = np.zeros((8, 8, 8), np.uint8)
+    bad[3, 2, 1] = 1                      # only one material in the table
+    assert _create(mat=bad) == fdtd.EINVAL
+    assert "material index" in fdtd.lib().fdtd_last_error().decode()
+
+
+def test_coefficients_match_oracle_rounded_once():
+    rng = np.random.default_rng(0)
+    eps = np.concatenate([[1.0], rng.uniform(1, 12, 255)])
+    sig = np.concatenate([[0.0], rng.uniform(0, 0.05, 255)])
+    for d in [(1e-3, 1e-3, 1e-3), (1e-3, 1.3e-3, 0.7e-3)]:
+        dt = W.courant_dt(*d)
+        ours, ch = fdtd.coefficients(eps, sig, *d, dt)
+        ref, ref_ch = oracle.coefficients(eps, sig, dt, *d)
+        assert np.array_equal(ours, ref.astype(np.float32))
+        assert np.array_equal(ch, ref_ch.astype(np.float32))
