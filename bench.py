@@ -1,0 +1,227 @@
+"""Benchmark of the Yee FDTD hot path on one MI355X.
+
+Workload: the 256^3 dielectric-scatterer cavity (16-entry material table,
+40 seeded spheres, Ez soft source at the centre, 16 probes), FP32 storage,
+fused kernel with T steps per HBM pass.  A "step" is one leapfrog time step
+of the whole grid (H and E half-steps with materials, PEC walls, source,
+probes); --steps K steps are timed with HIP events on the solver's stream,
+after --warmup W untimed steps.  Inputs are resident in HBM before timing.
+
+Prints one JSON line: G cell-updates/s, the HBM roofline fraction of the
+dominant kernel at B_alg = 49 B per cell-update (no temporal reuse counted),
+the FP16-storage rate beside it, p50/p99 per-solve latency, and the CPU
+oracle timed on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "G Yee cell-updates/s and % HBM roofline (FP32 vs FP16 store); p50/p99 latency"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("yee_fused.hip", "yee_device.hpp", "yee_internal.hpp", "fdtd_runtime.cpp"):
+        with open(os.path.join(ROOT, "paper_1301_4539_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, storage: str, T: int):
+    """Physical HBM bytes per launch (FETCH_SIZE + WRITE_SIZE from rocprofv3,
+    scaled by the copy-kernel calibration) from the committed summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        e = d[f"{workload}/{storage}/T{T}"]
+        if e.get("kernel_hash") != kernel_source_hash():
+            return None
+        return float(e["bytes_per_launch"])
+    except (KeyError, ValueError, OSError):
+        return None
+
+
+def time_steps(solver, n, torch, stream):
+    solver.synchronize()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    solver.step(n)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    solver.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3
+
+
+def launches_for(steps_done, n, T):
+    c, s = 0, steps_done
+    while n > 0:
+        ln = min(T - s % T, n)
+        s += ln
+        n -= ln
+        c += 1
+    return c
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The oracle (FP32 operation-order mode, as it stands) on the host cores,
+    over a bounded number of steps of the same grid."""
+    import numpy as np
+    import oracle
+    prob = oracle.Problem.from_workload(wl)
+    f = oracle.zero_fields(wl.nx, wl.ny, wl.nz, np.float32)
+    t0 = time.perf_counter()
+    prob.run_f32(f, 0, 2)
+    per = (time.perf_counter() - t0) / 2
+    n = int(max(2, min(200, budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    prob.run_f32(f, 2, n)
+    dt = time.perf_counter() - t0
+    return {"value": wl.cells * n / dt / 1e9, "unit": "G cell-updates/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{wl.nx}x{wl.ny}x{wl.nz} {wl.name}, steps 3-{2 + n} ({n} steps) of the FP32 "
+                      f"operation-order oracle from zero fields, {oracle.threads()} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--T", type=int, default=4, help="steps per HBM pass of the fused kernel (1..4)")
+    ap.add_argument("--workload", default="spheres256", choices=["spheres256", "spheres512"])
+    ap.add_argument("--tiling", type=int, default=0, help="fused-kernel tile variant (0 = auto, 1..3)")
+    ap.add_argument("--zchunk", type=int, default=0, help="planes per z chunk (0 = automatic)")
+    ap.add_argument("--solves", type=int, default=5, help="full solves for the latency percentiles")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP16 and latency measurements")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"],
+                    help="storage of the timed run (the JSON line reports fp32)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (reference for HBM counter scaling)")
+    args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("copy calibration: 5 x (1 GiB read + 1 GiB written)", flush=True)
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported in this build "
+              f"(multi-GPU decomposition is design-only).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1301_4539_amd import fdtd, roofline, workload as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    wl = W.spheres256() if args.workload == "spheres256" else W.spheres512()
+    cells = wl.cells
+    T = args.T
+
+    print(f"[bench] workload {wl.name} {wl.nx}x{wl.ny}x{wl.nz}, T={T}, warmup {args.warmup}, "
+          f"steps {args.steps}", file=sys.stderr, flush=True)
+    storage = {"fp32": W.FP32, "fp16": W.FP16, "bf16": W.BF16}[args.storage]
+    s = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_FUSED, time_block=T)
+    s.set_tiling(args.tiling, args.zchunk)
+    if args.warmup:
+        s.step(args.warmup)
+    start = s.steps_done()
+    t = time_steps(s, args.steps, torch, stream)
+    launches = launches_for(start, args.steps, T)
+    value = cells * args.steps / t / 1e9
+    b_alg = roofline.algorithmic_bytes(4)
+    achieved = b_alg * cells * args.steps / t / 1e9          # GB/s, algorithmic
+    traffic = measured_traffic(wl.name, "fp32", T)
+    print(f"[bench] {args.storage}: {value:.2f} G cell-updates/s, {t * 1e3 / launches:.3f} ms per launch",
+          file=sys.stderr, flush=True)
+
+    extras = {}
+    if not args.no_extras:
+        # per-solve latency: full config solves from zero fields
+        lat = []
+        for _ in range(args.solves):
+            s.set_fields(None)
+            lat.append(time_steps(s, wl.n_steps, torch, stream) * 1e3)
+        extras["latency_ms"] = {"solve": f"{wl.n_steps} steps", "p50": float(np.percentile(lat, 50)),
+                                "p99": float(np.percentile(lat, 99)), "n": len(lat)}
+        s.close()
+        # FP16 storage, same workload and T
+        s16 = fdtd.Solver.from_workload(wl, storage=W.FP16, kernel=fdtd.KERNEL_FUSED, time_block=T)
+        s16.set_tiling(args.tiling, args.zchunk)
+        if args.warmup:
+            s16.step(args.warmup)
+        t16 = time_steps(s16, args.steps, torch, stream)
+        v16 = cells * args.steps / t16 / 1e9
+        a16 = roofline.algorithmic_bytes(2) * cells * args.steps / t16 / 1e9
+        extras["fp16_store"] = {"value": v16, "ratio_vs_fp32": v16 / value,
+                                "roofline_frac": a16 / roofline.HBM_PEAK_GBPS}
+        s16.close()
+        print(f"[bench] fp16: {v16:.2f} G cell-updates/s", file=sys.stderr, flush=True)
+        # streaming-copy ceiling on this GPU (torch copy of 2 GiB)
+        x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        extras["copy_GBps"] = 2 * x.numel() * 4 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+        del x, y
+    else:
+        s.close()
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "G cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "storage": "fp32",
+                   "kernel": "fused", "T": T, "materials": 16, "spheres": 40, "sources": len(wl.sources),
+                   "probes": len(wl.probes), "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": roofline.HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / roofline.HBM_PEAK_GBPS,
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": b_alg * cells * args.steps / launches,
+                     "kernel": f"yee_fused<T={T},fp32>", "bytes_per_cell_update": b_alg,
+                     "avg_launch_ms": t * 1e3 / launches, "launches": launches},
+    }
+    line.update(extras)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -119,9 +119,15 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz,
                 const uint8_t *mat_index, int storage,
                 void *device_workspace, size_t workspace_bytes, void *hip_stream);
 
-/* Kernel family (fdtd_kernel) and steps per HBM pass T (1..8) for the FUSED
+/* Kernel family (fdtd_kernel) and steps per HBM pass T (1..4) for the FUSED
  * family.  Allowed before the first step and between steps. */
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
+
+/* Tile shape of the FUSED kernel -- variant 0 = chosen per storage format and
+ * T (default), 1..3 = the three rows-per-lane / waves-per-workgroup splits of
+ * that T -- and planes per z chunk (0 = chosen from the grid).  Results do
+ * not depend on either; they only change speed.  For tuning. */
+int fdtd_set_tiling(fdtd_solver *s, int variant, int z_chunk);
 
 /* Replace the whole state.  host: 6*(nx+1)*(ny+1)*(nz+1) floats, components
  * Ex, Ey, Ez, Hx, Hy, Hz one after another (E^n, then H^{n-1/2}); NULL sets
@@ -134,18 +140,19 @@ int fdtd_set_fields(fdtd_solver *s, const float *host);
 /* Add a soft source E_comp(i,j,k) += waveform[n] during step n (the step
  * that produces E^{n+1}), for n < n_samples; zero afterwards.  comp is an E
  * component and (i,j,k) must be an interior (non-PEC) edge.  waveform is
- * copied.  *id receives the source index (0, 1, ...). */
+ * copied.  At most 256 sources per solver; several sources on one edge add
+ * in index order.  *id receives the source index (0, 1, ...). */
 int fdtd_set_source(fdtd_solver *s, int comp, int i, int j, int k,
                     const float *waveform, int n_samples, int *id);
 
 /* Add a probe of component comp at storage position (i,j,k) (inside that
  * component's range).  After every step n (E^{n+1}, H^{n+1/2}) the value is
- * recorded in FP64.  Only allowed before the first step.  *id receives the
- * probe index. */
+ * recorded in FP64.  Only allowed before the first step; at most 256 probes
+ * per solver.  *id receives the probe index. */
 int fdtd_set_probe(fdtd_solver *s, int comp, int i, int j, int k, int *id);
 
 /* Enqueue n_steps >= 0 steps on the solver's stream and return without
- * waiting.  Fails with FDTD_ERANGE if an earlier block saturated. */
+ * waiting.  Saturation of reduced storage is reported by fdtd_synchronize. */
 int fdtd_step(fdtd_solver *s, int n_steps);
 
 /* Copy one component of the current state to host (float,

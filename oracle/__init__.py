@@ -52,6 +52,7 @@ def lib():
         L.orc_energy_f64.restype = C.c_double
         L.orc_energy_f32.argtypes = [_i, _i, _i, _fp, _dp, _u8, _fp]
         L.orc_energy_f32.restype = C.c_double
+        L.orc_threads.restype = _i
         L.orc_divergence_f64.argtypes = [_i, _i, _i, C.c_double, C.c_double, C.c_double, _dp, _u8, _dp, _dp, _dp]
         _lib = L
     return _lib
@@ -187,3 +188,8 @@ def choose_scales(m_prev, a_max):
     out = np.zeros(6, np.int32)
     lib().orc_choose_scales(m, float(a_max), out)
     return out
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())

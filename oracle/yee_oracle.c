@@ -592,3 +592,11 @@ void orc_divergence_f64(int nx, int ny, int nz, double dx, double dy, double dz,
                 }
             }
 }
+
+/* Number of threads the parallel loops use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

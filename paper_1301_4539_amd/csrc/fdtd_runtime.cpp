@@ -45,18 +45,20 @@ int elem_size(int storage) { return storage == FDTD_FP32 ? 4 : 2; }
 
 struct Dims {
     int pitch;
-    long long plane, cstride;
+    long long plane, kstride;
     size_t fbytes, matbytes, total;
 };
 
+// Plane-interleaved field buffers: the six components of one z plane are
+// consecutive, each plane of one component pitch*(ny+1) elements.
 Dims dims_for(int nx, int ny, int nz, int storage)
 {
     Dims d;
     const int es = elem_size(storage);
     d.pitch = (int)round_up((size_t)nx + 1, 128 / es);          // rows start on 128-byte lines
     d.plane = (long long)d.pitch * (ny + 1);
-    d.cstride = (long long)round_up((size_t)d.plane * (nz + 1), 256 / es);
-    d.fbytes = (size_t)d.cstride * 6 * es;
+    d.kstride = 6 * d.plane;
+    d.fbytes = round_up((size_t)d.kstride * (nz + 1) * es, 256);
     d.matbytes = round_up((size_t)d.plane * (nz + 1), 256);
     d.total = 2 * d.fbytes + d.matbytes + 256;
     return d;
@@ -166,6 +168,8 @@ struct fdtd_solver {
     int storage = FDTD_FP32;
     int kernel = FDTD_KERNEL_AUTO;
     int T = 2;
+    int tiling = 0;                     // fused-kernel tile shape: 0 = auto, 1..3 = explicit
+    int zchunk = 0;                     // planes per z chunk (0 = automatic)
     hipStream_t st = nullptr;
     Dims d{};
     char *ws = nullptr;
@@ -286,6 +290,15 @@ yee::StorageBlock storage_block(const fdtd_solver *s)
     return b;
 }
 
+// Fastest tile shape per (storage, T) measured on MI355X with the 256^3
+// dielectric workload (shape indices of the fused kernel's tile table).
+int auto_shape(int storage, int T)
+{
+    static const int f32[5] = {0, 0, 2, 2, 0};
+    static const int f16[5] = {0, 0, 2, 2, 1};
+    return storage == FDTD_FP32 ? f32[T] : f16[T];
+}
+
 int read_ctrl(fdtd_solver *s, yee::Ctrl *out)
 {
     hipError_t e = hipMemcpyAsync(out, s->ctrl, sizeof(yee::Ctrl), hipMemcpyDeviceToHost, s->st);
@@ -359,7 +372,10 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy,
     s->st = (hipStream_t)hip_stream;
     s->d = dims_for(nx, ny, nz, storage);
     s->L.nx = nx; s->L.ny = ny; s->L.nz = nz;
-    s->L.pitch = s->d.pitch; s->L.plane = s->d.plane; s->L.cstride = s->d.cstride;
+    s->L.pitch = s->d.pitch;
+    s->L.plane = s->d.plane;
+    s->L.cstride = s->d.plane;
+    s->L.kstride = s->d.kstride;
 
     hipError_t e;
     if (device_workspace) {
@@ -413,8 +429,20 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
     if (time_block < 1 || time_block > 4) return fail(FDTD_EINVAL, "time_block must be 1..4");
     if (kernel == FDTD_KERNEL_PLAIN && s->storage != FDTD_FP32)
         return fail(FDTD_EINVAL, "the plain kernel needs FP32 storage");
+    if (kernel != FDTD_KERNEL_PLAIN && !yee::fused_fits(s->L, s->storage, time_block))
+        return fail(FDTD_EINVAL, "grid planes too large for the fused kernel; use the plain kernel");
     s->kernel = kernel;
     s->T = time_block;
+    return FDTD_OK;
+}
+
+int fdtd_set_tiling(fdtd_solver *s, int variant, int z_chunk)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (variant < 0 || variant > 3) return fail(FDTD_EINVAL, "tiling variant must be 0 (auto) or 1..3");
+    if (z_chunk < 0) return fail(FDTD_EINVAL, "negative z chunk");
+    s->tiling = variant;
+    s->zchunk = z_chunk;
     return FDTD_OK;
 }
 
@@ -475,12 +503,16 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
     }
     const void *src = s->storage == FDTD_FP32 ? (const void *)f.data() : (const void *)q.data();
     if ((e = hipMemsetAsync(s->fbuf[0], 0, s->d.fbytes, s->st))) return hip_fail(e, "hipMemset");
-    for (int c = 0; c < 6; ++c) {
-        e = hipMemcpy2DAsync(s->fbuf[0] + (size_t)c * s->d.cstride * es, (size_t)s->d.pitch * es,
-                             (const char *)src + (size_t)c * nbox * es, (size_t)(nx + 1) * es,
-                             (size_t)(nx + 1) * es, (size_t)(ny + 1) * (nz + 1), hipMemcpyHostToDevice, s->st);
-        if (e) return hip_fail(e, "upload fields");
-    }
+    const size_t nplane = (size_t)(nx + 1) * (ny + 1);
+    for (int c = 0; c < 6; ++c)
+        for (int k = 0; k <= nz; ++k) {
+            e = hipMemcpy2DAsync(s->fbuf[0] + ((size_t)c * s->L.cstride + (size_t)k * s->L.kstride) * es,
+                                 (size_t)s->d.pitch * es,
+                                 (const char *)src + ((size_t)c * nbox + (size_t)k * nplane) * es,
+                                 (size_t)(nx + 1) * es, (size_t)(nx + 1) * es, (size_t)(ny + 1),
+                                 hipMemcpyHostToDevice, s->st);
+            if (e) return hip_fail(e, "upload fields");
+        }
     if ((e = hipMemcpyAsync(s->ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s->st)) ||
         (e = hipStreamSynchronize(s->st)))
         return hip_fail(e, "upload fields");
@@ -494,6 +526,7 @@ int fdtd_set_source(fdtd_solver *s, int comp, int i, int j, int k, const float *
     if (!e_interior(s->L.nx, s->L.ny, s->L.nz, comp, i, j, k))
         return fail(FDTD_EINVAL, "source must sit on an interior (non-PEC) edge");
     if (n_samples < 0 || (n_samples > 0 && !waveform)) return fail(FDTD_EINVAL, "bad waveform");
+    if (s->src_pos.size() >= 256) return fail(FDTD_EINVAL, "at most 256 sources per solver");
     const int off = (int)s->samples.size();
     float amax = s->a_max;
     for (int n = 0; n < n_samples; ++n) {
@@ -516,6 +549,7 @@ int fdtd_set_probe(fdtd_solver *s, int comp, int i, int j, int k, int *id)
     if (s->steps > 0) return fail(FDTD_ESTATE, "probes must be added before the first step");
     if (comp < 0 || comp > 5 || !in_range(s->L.nx, s->L.ny, s->L.nz, comp, i, j, k))
         return fail(FDTD_EINVAL, "probe outside the component's range");
+    if (s->probe_pos.size() >= 256) return fail(FDTD_EINVAL, "at most 256 probes per solver");
     s->probe_pos.push_back(make_int4(comp, i, j, k));
     free_dev(s->probe_pos_d);
     free_dev(s->probe_out_d);
@@ -574,7 +608,8 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         a.fout = s->fbuf[s->cur ^ 1];
         a.step0 = s->steps;
         a.sb = storage_block(s);
-        if ((e = yee::launch_fused(s->storage, len, a, s->st))) return hip_fail(e, "fused step");
+        const int shape = s->tiling > 0 ? s->tiling - 1 : auto_shape(s->storage, len);
+        if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
         s->cur ^= 1;
         s->steps += len;
         s->block += 1;
@@ -597,9 +632,13 @@ int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst)
         q.resize(nbox);
         dst = q.data();
     }
-    e = hipMemcpy2DAsync(dst, (size_t)(nx + 1) * es, s->fbuf[s->cur] + (size_t)comp * s->d.cstride * es,
-                         (size_t)s->d.pitch * es, (size_t)(nx + 1) * es, (size_t)(ny + 1) * (nz + 1),
-                         hipMemcpyDeviceToHost, s->st);
+    const size_t nplane = (size_t)(nx + 1) * (ny + 1);
+    e = hipSuccess;
+    for (int k = 0; k <= nz && !e; ++k)
+        e = hipMemcpy2DAsync((char *)dst + (size_t)k * nplane * es, (size_t)(nx + 1) * es,
+                             s->fbuf[s->cur] + ((size_t)comp * s->L.cstride + (size_t)k * s->L.kstride) * es,
+                             (size_t)s->d.pitch * es, (size_t)(nx + 1) * es, (size_t)(ny + 1),
+                             hipMemcpyDeviceToHost, s->st);
     if (!e) e = hipStreamSynchronize(s->st);
     if (e) return hip_fail(e, "read fields");
     if (s->storage != FDTD_FP32) {

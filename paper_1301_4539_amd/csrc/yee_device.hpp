@@ -94,9 +94,17 @@ __device__ inline void choose_scales(const float *mprev, float a_max, int *s)
 }
 
 // ---- cross-lane moves (wave64) ---------------------------------------------
-// Value held by lane+1 (lane 63 gets its own value: it is a halo lane).
-__device__ inline float from_right(float v) { return __shfl_down(v, 1, 64); }
-// Value held by lane-1 (lane 0 gets its own value: it is a halo lane).
-__device__ inline float from_left(float v) { return __shfl_up(v, 1, 64); }
+// DPP wave shifts: one VALU op, no LDS traffic.  Lanes with no source lane
+// (lane 63 for from_right, lane 0 for from_left) get 0; they are halo lanes.
+// Value held by lane+1 (wave_shl:1).
+__device__ inline float from_right(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+// Value held by lane-1 (wave_shr:1).
+__device__ inline float from_left(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
 
 }  // namespace yee

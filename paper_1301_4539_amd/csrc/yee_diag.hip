@@ -42,7 +42,7 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
     for (int q = 0; q < DIAG_W; ++q) v[q] = 0.0;
     if (i <= L.nx && j <= L.ny) {
         const int nx = L.nx, ny = L.ny, nz = L.nz;
-        const long long p = k * L.plane + (long long)j * L.pitch + i;
+        const long long p = k * L.kstride + (long long)j * L.pitch + i;
         // owner-cell permittivity of an E edge, zero on wall (PEC) edges
         auto eps_edge = [&](int c, int ii, int jj, int kk) -> double {
             bool interior = c == 0 ? (ii < nx && jj > 0 && jj < ny && kk > 0 && kk < nz)
@@ -59,11 +59,11 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
         v[0] += 0.5 * eps_edge(2, i, j, k) * (double)ez * (double)ez;
         // magnetic energy with H^{n+1/2} from the Faraday half-step
         if (j < ny && k < nz) {
-            const float h1 = __builtin_fmaf(-a.chy, F(2, p + L.pitch) - ez, __builtin_fmaf(a.chz, F(1, p + L.plane) - ey, hx));
+            const float h1 = __builtin_fmaf(-a.chy, F(2, p + L.pitch) - ez, __builtin_fmaf(a.chz, F(1, p + L.kstride) - ey, hx));
             v[0] += 0.5 * (double)hx * (double)h1;
         }
         if (i < nx && k < nz) {
-            const float h1 = __builtin_fmaf(-a.chz, F(0, p + L.plane) - ex, __builtin_fmaf(a.chx, F(2, p + 1) - ez, hy));
+            const float h1 = __builtin_fmaf(-a.chz, F(0, p + L.kstride) - ex, __builtin_fmaf(a.chx, F(2, p + 1) - ez, hy));
             v[0] += 0.5 * (double)hy * (double)h1;
         }
         if (i < nx && j < ny) {
@@ -74,14 +74,14 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
         if (i > 0 && i < nx && j > 0 && j < ny && k > 0 && k < nz) {
             double d = (eps_edge(0, i, j, k) * ex - eps_edge(0, i - 1, j, k) * F(0, p - 1)) * a.idx;
             d += (eps_edge(1, i, j, k) * ey - eps_edge(1, i, j - 1, k) * F(1, p - L.pitch)) * a.idy;
-            d += (eps_edge(2, i, j, k) * ez - eps_edge(2, i, j, k - 1) * F(2, p - L.plane)) * a.idz;
+            d += (eps_edge(2, i, j, k) * ez - eps_edge(2, i, j, k - 1) * F(2, p - L.kstride)) * a.idz;
             v[1] = d * d;
             v[3] = fabs(d);
         }
         // div(H) at cell centres
         if (i < nx && j < ny && k < nz) {
             double d = ((double)F(3, p + 1) - hx) * a.idx + ((double)F(4, p + L.pitch) - hy) * a.idy
-                     + ((double)F(5, p + L.plane) - hz) * a.idz;
+                     + ((double)F(5, p + L.kstride) - hz) * a.idz;
             v[2] = d * d;
             v[4] = fabs(d);
         }

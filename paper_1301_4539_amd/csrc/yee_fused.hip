@@ -3,7 +3,7 @@
 // This is the GPU form of the cache-reuse ideas of Sec. 3: Ampere and
 // Faraday interleaved per sub-domain (Sec. 3.2), plane by plane along z
 // (Sec. 3.3), several time steps gathered per pass (Sec. 3.4, generalised
-// to T steps as suggested in the conclusion).  On a GPU the "cache" is the
+// to T steps as the conclusion suggests).  On a GPU the "cache" is the
 // register file: a workgroup owns an x-y tile, marches z, and keeps T+1 time
 // levels of the six fields in registers; level t runs one plane behind level
 // t-1.  Overlapped tiles (a halo of T cells on every side in x and y, T
@@ -15,10 +15,19 @@
 //
 // Thread layout: lane = x (64 consecutive points, coalesced), each lane holds
 // RY consecutive rows in y, NW waves stack in y.  x neighbours move between
-// lanes with cross-lane shuffles; the y neighbour across a wave boundary goes
+// lanes with DPP wave shifts; the y neighbour across a wave boundary goes
 // through a small LDS slot.  Fields are read from buffer fin and the advanced
 // state is written to buffer fout (ping-pong): an in-place update would race
 // with neighbouring tiles still reading the old time level.
+//
+// Addressing: every array is read through a buffer resource based at the
+// chunk's first plane; the per-lane x offset lives in one VGPR and the plane
+// and row offsets are scalar, so a load costs one instruction.  Halo lanes
+// and rows outside the grid read clamped (in-grid) addresses: their values
+// only ever feed other halo values, never an owned output.
+
+#include <algorithm>
+#include <type_traits>
 
 #include "yee_device.hpp"
 #include "yee_internal.hpp"
@@ -27,28 +36,65 @@ namespace yee {
 
 namespace {
 
-template <int T>
-struct Shape;
-// rows per lane, waves per workgroup
-template <> struct Shape<1> { static constexpr int RY = 4, NW = 4; };
-template <> struct Shape<2> { static constexpr int RY = 4, NW = 8; };
-template <> struct Shape<3> { static constexpr int RY = 4, NW = 8; };
-template <> struct Shape<4> { static constexpr int RY = 4, NW = 8; };
+constexpr int BUF_FLAGS = 0x00020000;   // raw (untyped) dword buffer, gfx9 word 3
 
-template <int T, class Codec>
-__global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void *base, long long bytes)
 {
-    constexpr int RY = Shape<T>::RY, NW = Shape<T>::NW;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, BUF_FLAGS);
+}
+
+template <class Codec> struct Buf;
+template <> struct Buf<CodecF32> {
+    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, int vo, int so, float)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float, uint32_t &,
+                                        uint32_t &)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+    }
+};
+template <class Codec> struct Buf16 {
+    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, int vo, int so, float down)
+    {
+        const uint16_t q = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+        return Codec::load(&q, down);
+    }
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float up, uint32_t &mx,
+                                        uint32_t &flag)
+    {
+        uint16_t q;
+        Codec::store(&q, v, up, mx, flag);
+        __builtin_amdgcn_raw_buffer_store_b16(q, r, vo, so, 0);
+    }
+};
+template <> struct Buf<CodecF16> : Buf16<CodecF16> {};
+template <> struct Buf<CodecBF16> : Buf16<CodecBF16> {};
+
+constexpr int MAX_LOCAL = 256;   // sources / probes per solver
+
+template <int T, int RY, int NW, class Codec>
+__global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
+{
     constexpr int OX = 64 - 2 * T;      // owned points per tile in x
     constexpr int NR = NW * RY;         // rows per tile
     constexpr int OY = NR - 2 * T;      // owned rows per tile
     using S = typename Codec::T;
+    using B = Buf<Codec>;
+    constexpr int ES = sizeof(S);
 
     __shared__ float4 s_coef[256];
     __shared__ float2 s_e[NW + 1][64];  // (Ex, Ez) of each wave's first row; slot NW stays zero
     __shared__ float2 s_h[NW + 1][64];  // (Hx, Hz) of each wave's last row, in slot w+1; slot 0 stays zero
+    __shared__ int4 s_src[MAX_LOCAL];   // sources this workgroup computes: (comp, lane, row, plane)
+    __shared__ int2 s_srcw[MAX_LOCAL];  // their (sample offset, n_samples)
+    __shared__ int4 s_prb[MAX_LOCAL];   // probes this workgroup owns: (comp, lane, row, plane)
+    __shared__ int s_prbid[MAX_LOCAL];
+    __shared__ int s_nsrc, s_nprb;
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int q = tid; q < a.n_mat; q += 64 * NW) s_coef[q] = a.coef[q];
     if (tid < 64) {
         s_e[NW][tid] = make_float2(0.0f, 0.0f);
@@ -80,8 +126,7 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
     } else {
         for (int c = 0; c < 6; ++c) dn[c] = up[c] = 1.0f;
     }
-    __syncthreads();
-    if (logical >= a.nwg) return;   // uniform per workgroup
+    if (logical >= a.nwg) return;   // uniform per workgroup; no barrier passed yet
 
     const Layout L = a.L;
     const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -97,14 +142,52 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
     const int kb = max(0, z0 - T);      // first plane the pipeline loads
     const int ke = min(nz, z1 - 1 + T); // last plane the pipeline loads
 
+    // sources on points this tile computes, probes on points it owns
+    if (tid == 0) {
+        int ns = 0, np = 0;
+        for (int q = 0; q < a.src.n; ++q) {
+            const int4 d = a.src.pos[q];
+            const int lx = d.y - xl, ry = d.z - yt;
+            if (lx >= 0 && lx < 64 && ry >= 0 && ry < NR && d.w >= kb && d.w <= ke && ns < MAX_LOCAL) {
+                s_src[ns] = make_int4(d.x, lx, ry, d.w);
+                s_srcw[ns] = a.src.wave[q];
+                ++ns;
+            }
+        }
+        for (int q = 0; q < a.probe.n; ++q) {
+            const int4 d = a.probe.pos[q];
+            const int lx = d.y - xl, ry = d.z - yt;
+            if (lx >= T && lx < T + OX && ry >= T && ry < T + OY && d.w >= z0 && d.w < z1 && np < MAX_LOCAL) {
+                s_prb[np] = make_int4(d.x, lx, ry, d.w);
+                s_prbid[np] = q;
+                ++np;
+            }
+        }
+        s_nsrc = ns;
+        s_nprb = np;
+    }
+    __syncthreads();
+    const int nsrc = s_nsrc, nprb = s_nprb;
+
+    // lane and row predicates
     const bool xin = x >= 0 && x <= nx;
-    const bool xlt = x < nx;
+    const bool xlt = x >= 0 && x < nx;
     const bool xint = x > 0 && x < nx;
     const bool xown = lane >= T && lane < T + OX && x <= nx;
+    const int xc = min(max(x, 0), nx);
+    const int vo = xc * ES;             // per-lane byte offset of the field arrays
+    const int vom = xc;                 // per-lane byte offset of the material index
 
-    const S *fin = static_cast<const S *>(a.fin);
-    S *fout = static_cast<S *>(a.fout);
-    const long long cs = L.cstride;
+    // buffer resources based at this chunk's first plane
+    const long long cs = L.cstride, ks = L.kstride;
+    const __amdgpu_buffer_rsrc_t rin = rsrc(static_cast<const S *>(a.fin) + (long long)kb * ks,
+                                            (long long)(ke - kb + 1) * ks * ES);
+    const __amdgpu_buffer_rsrc_t rout = rsrc(static_cast<S *>(a.fout) + (long long)kb * ks,
+                                             (long long)(ke - kb + 1) * ks * ES);
+    const __amdgpu_buffer_rsrc_t rmat = rsrc(a.mat + (long long)kb * L.plane, (long long)(ke - kb + 1) * L.plane);
+    int rowoff[RY];                     // clamped row offsets (elements), uniform per wave
+#pragma unroll
+    for (int r = 0; r < RY; ++r) rowoff[r] = min(max(yw + r, 0), ny) * L.pitch;
 
     float E[T + 1][3][RY], H[T + 1][3][RY];
     int M[T + 1][RY];
@@ -121,19 +204,18 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
     float PE[3][RY], PH[3][RY];
     int PM[RY];
 
-#define YEE_LOAD_PLANE(KK)                                                              \
-    do {                                                                                \
-        const int kk_ = (KK);                                                           \
-        _Pragma("unroll") for (int r = 0; r < RY; ++r) {                                \
-            const int y = yw + r;                                                       \
-            const bool in = xin && y >= 0 && y <= ny && kk_ <= ke;                      \
-            const long long off = (long long)kk_ * L.plane + (long long)y * L.pitch + x; \
-            _Pragma("unroll") for (int c = 0; c < 3; ++c) {                             \
-                PE[c][r] = in ? Codec::load(fin + c * cs + off, dn[c]) : 0.0f;          \
-                PH[c][r] = in ? Codec::load(fin + (3 + c) * cs + off, dn[3 + c]) : 0.0f; \
-            }                                                                           \
-            PM[r] = in ? (int)a.mat[off] : 0;                                           \
-        }                                                                               \
+#define YEE_LOAD_PLANE(KK)                                                                  \
+    do {                                                                                    \
+        const int pofs_ = ((KK) - kb) * (int)ks;                                            \
+        const int mofs_ = ((KK) - kb) * (int)L.plane;                                       \
+        _Pragma("unroll") for (int r = 0; r < RY; ++r) {                                    \
+            const int so_ = pofs_ + rowoff[r];                                              \
+            _Pragma("unroll") for (int c = 0; c < 3; ++c) {                                 \
+                PE[c][r] = B::load(rin, vo, (so_ + c * (int)cs) * ES, dn[c]);               \
+                PH[c][r] = B::load(rin, vo, (so_ + (3 + c) * (int)cs) * ES, dn[3 + c]);     \
+            }                                                                               \
+            PM[r] = __builtin_amdgcn_raw_buffer_load_b8(rmat, vom, mofs_ + rowoff[r], 0);   \
+        }                                                                                   \
     } while (0)
 
     YEE_LOAD_PLANE(kb);
@@ -141,7 +223,10 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
     uint32_t mx[6] = {0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t flag = 0u;
 
-    for (int K = kb; K <= ke + T; ++K) {
+    // One z step of the pipeline.  ALL: every time level is active and the
+    // next plane is loaded (steady state), so no per-level branches remain.
+    auto iterate = [&](const int K, auto all_c) __attribute__((always_inline)) {
+        constexpr bool ALL = decltype(all_c)::value;
         // Level 0 takes plane K; plane K-1 of level 0 becomes level 1's input.
         float Eo[3][RY], Ho[3][RY];
         int Mo[RY];
@@ -157,12 +242,12 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
                 H[0][c][r] = PH[c][r];
             }
         }
-        YEE_LOAD_PLANE(K + 1);
+        if (ALL || K + 1 <= ke) YEE_LOAD_PLANE(K + 1);
 
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
             const int p = K - t;                      // plane of time level t
-            if (p >= kb && p <= ke) {                 // uniform over the workgroup
+            if (ALL || (p >= kb && p <= ke)) {        // uniform over the workgroup
                 const bool plt = p < nz, pint = p > 0 && p < nz;
                 // ---- Faraday: H^(t) at plane p from E^(t-1) at p and p+1 ----
                 if constexpr (NW > 1) {
@@ -174,7 +259,7 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
                     const int y = yw + r;
-                    const bool in = xin && y >= 0 && y <= ny;
+                    const bool yin = y >= 0 && y <= ny;
                     const float exu = r + 1 < RY ? Eo[0][(r + 1) % RY] : eup.x;
                     const float ezu = r + 1 < RY ? Eo[2][(r + 1) % RY] : eup.y;
                     const float ezr = from_right(Eo[2][r]);
@@ -188,9 +273,9 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
                     const float dex_y = exu - Eo[0][r];
                     const float dey_x = eyr - Eo[1][r];
                     const float hz = __builtin_fmaf(-a.chx, dey_x, __builtin_fmaf(a.chy, dex_y, Ho[2][r]));
-                    Hn[0][r] = (in && y < ny && plt) ? hx : Ho[0][r];
-                    Hn[1][r] = (in && xlt && plt) ? hy : Ho[1][r];
-                    Hn[2][r] = (in && xlt && y < ny) ? hz : Ho[2][r];
+                    Hn[0][r] = (xin && yin && y < ny && plt) ? hx : Ho[0][r];
+                    Hn[1][r] = (xlt && yin && plt) ? hy : Ho[1][r];
+                    Hn[2][r] = (xlt && y >= 0 && y < ny) ? hz : Ho[2][r];
                 }
                 // ---- Ampere: E^(t) at plane p from H^(t) at p and p-1 ----
                 if constexpr (NW > 1) {
@@ -202,7 +287,6 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
                     const int y = yw + r;
-                    const bool in = xin && y >= 0 && y <= ny;
                     const bool yint = y > 0 && y < ny;
                     const float hxd = r > 0 ? Hn[0][(r + RY - 1) % RY] : hdn.x;
                     const float hzd = r > 0 ? Hn[2][(r + RY - 1) % RY] : hdn.y;
@@ -218,47 +302,41 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
                     const float dhy_x = Hn[1][r] - hyl;
                     const float dhx_y = Hn[0][r] - hxd;
                     const float ez = __builtin_fmaf(-cf.z, dhx_y, __builtin_fmaf(cf.y, dhy_x, cf.x * Eo[2][r]));
-                    En[0][r] = (in && xlt && yint && pint) ? ex : Eo[0][r];
-                    En[1][r] = (in && y < ny && xint && pint) ? ey : Eo[1][r];
-                    En[2][r] = (in && plt && xint && yint) ? ez : Eo[2][r];
+                    En[0][r] = (xlt && yint && pint) ? ex : Eo[0][r];
+                    En[1][r] = (xint && y >= 0 && y < ny && pint) ? ey : Eo[1][r];
+                    En[2][r] = (xint && yint && plt) ? ez : Eo[2][r];
                 }
                 // ---- soft sources of step step0+t-1, on every tile computing the edge ----
                 const long long n = a.step0 + (t - 1);
-                for (int q = 0; q < a.src.n; ++q) {
-                    const int4 d = a.src.pos[q];
-                    if (d.w != p) continue;
-                    const int2 wv = a.src.wave[q];
-                    if (n >= wv.y) continue;
-                    const int lx = d.y - xl, ry = d.z - yt;
-                    if (lx < 0 || lx >= 64 || ry < 0 || ry >= NR || ry / RY != w) continue;
+                for (int q = 0; q < nsrc; ++q) {
+                    const int4 d = s_src[q];
+                    const int2 wv = s_srcw[q];
+                    if (d.w != p || n >= wv.y || d.z / RY != w) continue;
                     const float val = a.src.samples[wv.x + n];
-                    if (lane == lx) {
+                    if (lane == d.y) {
 #pragma unroll
                         for (int r = 0; r < RY; ++r)
-                            if (r == ry - w * RY) {
+                            if (r == d.z - w * RY) {
                                 if (d.x == 0) En[0][r] = En[0][r] + val;
                                 else if (d.x == 1) En[1][r] = En[1][r] + val;
                                 else En[2][r] = En[2][r] + val;
                             }
                     }
                 }
-                // ---- probes, recorded by the owning tile only: planes outside
-                // [z0, z1) are this chunk's warm-up/drain halo, where upper time
-                // levels are incomplete ----
-                for (int q = 0; q < a.probe.n; ++q) {
-                    const int4 d = a.probe.pos[q];
-                    if (d.w != p || p < z0 || p >= z1) continue;
-                    const int lx = d.y - xl, ry = d.z - yt;
-                    if (lx < T || lx >= T + OX || ry < T || ry >= T + OY || ry / RY != w) continue;
-                    if (lane == lx) {
+                // ---- probes, recorded by the owning tile only (planes outside
+                // [z0, z1) are this chunk's halo, where upper levels are incomplete) ----
+                for (int q = 0; q < nprb; ++q) {
+                    const int4 d = s_prb[q];
+                    if (d.w != p || d.z / RY != w) continue;
+                    if (lane == d.y) {
                         float v = 0.0f;
 #pragma unroll
                         for (int r = 0; r < RY; ++r)
-                            if (r == ry - w * RY) {
+                            if (r == d.z - w * RY) {
                                 v = d.x == 0 ? En[0][r] : d.x == 1 ? En[1][r] : d.x == 2 ? En[2][r]
                                   : d.x == 3 ? Hn[0][r] : d.x == 4 ? Hn[1][r] : Hn[2][r];
                             }
-                        a.probe.out[(n - a.probe.base) * a.probe.n + q] = (double)v;
+                        a.probe.out[(n - a.probe.base) * a.probe.n + s_prbid[q]] = (double)v;
                     }
                 }
                 // ---- rotate: level t's previous plane becomes level t+1's input ----
@@ -292,21 +370,32 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
         // ---- store the owned part of level T (plane K-T) ----
         const int q = K - T;
         if (q >= z0 && q < z1) {
+            const int pofs = (q - kb) * (int)ks;
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 const int row = w * RY + r;
                 const int y = yw + r;
-                if (xown && row >= T && row < T + OY && y <= ny) {
-                    const long long off = (long long)q * L.plane + (long long)y * L.pitch + x;
+                if (row >= T && row < T + OY && y <= ny) {        // uniform per wave
+                    const int so = (pofs + rowoff[r]) * ES;
+                    if (xown) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        Codec::store(fout + c * cs + off, E[T][c][r], up[c], mx[c], flag);
-                        Codec::store(fout + (3 + c) * cs + off, H[T][c][r], up[3 + c], mx[3 + c], flag);
+                        for (int c = 0; c < 3; ++c) {
+                            B::store(rout, vo, so + c * (int)cs * ES, E[T][c][r], up[c], mx[c], flag);
+                            B::store(rout, vo, so + (3 + c) * (int)cs * ES, H[T][c][r], up[3 + c], mx[3 + c], flag);
+                        }
                     }
                 }
             }
         }
-    }
+    };
+
+    // warm-up (upper levels still empty), steady state, drain (lower levels done)
+    int K = kb;
+    const int kw = min(kb + T, ke);
+    for (; K < kw; ++K) iterate(K, std::false_type{});
+#pragma unroll 2
+    for (; K < ke; ++K) iterate(K, std::true_type{});
+    for (; K <= ke + T; ++K) iterate(K, std::false_type{});
 #undef YEE_LOAD_PLANE
 
     if constexpr (Codec::scaled) {
@@ -322,66 +411,94 @@ __global__ __launch_bounds__(64 * Shape<T>::NW) void yee_fused(FusedArgs a)
     }
 }
 
-template <int T>
-void geometry(const Layout &L, int *ntx, int *nty, int *ntz, int *zc, int *threads)
+// ---- tilings ---------------------------------------------------------------
+// (RY rows per lane, NW waves) per time-block length; variant 0 is the default.
+struct Tiling { int ry, nw; };
+constexpr Tiling kTilings[5][3] = {
+    {},
+    {{4, 4}, {2, 8}, {2, 16}},    // T = 1
+    {{2, 16}, {4, 8}, {3, 12}},   // T = 2
+    {{2, 16}, {4, 8}, {3, 12}},   // T = 3
+    {{2, 16}, {4, 8}, {3, 12}},   // T = 4
+};
+
+int planes_fit(const Layout &L, int es)
 {
-    constexpr int OX = 64 - 2 * T, OY = Shape<T>::NW * Shape<T>::RY - 2 * T;
-    *ntx = (L.nx + 1 + OX - 1) / OX;
-    *nty = (L.ny + 1 + OY - 1) / OY;
-    // Enough z chunks for ~8 workgroups per CU, each chunk at least 8T planes deep.
-    const int per_plane = *ntx * *nty;
-    int want = (2048 + per_plane - 1) / per_plane;
-    int maxc = (L.nz + 1) / (8 * T);
-    if (maxc < 1) maxc = 1;
-    if (want > maxc) want = maxc;
-    if (want < 1) want = 1;
-    *zc = (L.nz + 1 + want - 1) / want;
-    *ntz = (L.nz + 1 + *zc - 1) / *zc;
-    *threads = 64 * Shape<T>::NW;
+    // a chunk's buffer resource spans (planes * kstride * es) bytes, below 2^31
+    long long p = ((1LL << 31) - 1) / ((long long)L.kstride * es);
+    return (int)std::min<long long>(p, 1 << 20);
 }
 
-template <int T, class Codec>
-hipError_t launch_t(const FusedArgs &a0, hipStream_t st)
+void geometry_for(int T, int variant, int zc_req, int es, const Layout &L, int *ntx, int *nty, int *ntz, int *zc,
+                  int *threads)
 {
+    const Tiling tl = kTilings[T][variant];
+    const int OX = 64 - 2 * T, OY = tl.nw * tl.ry - 2 * T;
+    *ntx = (L.nx + 1 + OX - 1) / OX;
+    *nty = (L.ny + 1 + OY - 1) / OY;
+    int z = zc_req;
+    if (z <= 0) {
+        // chunks of ~64 planes, fewer when that leaves the GPU short of workgroups
+        const int per_plane = *ntx * *nty;
+        const int want = std::max(1, (1024 + per_plane - 1) / per_plane);
+        z = std::max(8 * T, std::min(64, (L.nz + 1 + want - 1) / want));
+    }
+    z = std::min(z, std::max(1, planes_fit(L, es) - 2 * T - 1));
+    z = std::max(1, std::min(z, L.nz + 1));
+    *zc = z;
+    *ntz = (L.nz + 1 + z - 1) / z;
+    *threads = 64 * tl.nw;
+}
+
+template <int T, int V, class Codec>
+hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
+{
+    constexpr Tiling tl = kTilings[T][V];
     FusedArgs a = a0;
     int threads;
-    geometry<T>(a.L, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+    geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
     a.nwg = a.ntx * a.nty * a.ntz;
     const int grid = (a.nwg + 7) / 8 * 8;
-    hipLaunchKernelGGL((yee_fused<T, Codec>), dim3(grid), dim3(threads), 0, st, a);
+    hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, a);
     return hipGetLastError();
 }
 
+template <int T, class Codec>
+hipError_t launch_t(const FusedArgs &a, int variant, int zc, hipStream_t st)
+{
+    switch (variant) {
+    case 1: return launch_tv<T, 1, Codec>(a, zc, st);
+    case 2: return launch_tv<T, 2, Codec>(a, zc, st);
+    default: return launch_tv<T, 0, Codec>(a, zc, st);
+    }
+}
+
 template <class Codec>
-hipError_t launch_codec(int T, const FusedArgs &a, hipStream_t st)
+hipError_t launch_codec(int T, const FusedArgs &a, int variant, int zc, hipStream_t st)
 {
     switch (T) {
-    case 1: return launch_t<1, Codec>(a, st);
-    case 2: return launch_t<2, Codec>(a, st);
-    case 3: return launch_t<3, Codec>(a, st);
-    case 4: return launch_t<4, Codec>(a, st);
+    case 1: return launch_t<1, Codec>(a, variant, zc, st);
+    case 2: return launch_t<2, Codec>(a, variant, zc, st);
+    case 3: return launch_t<3, Codec>(a, variant, zc, st);
+    case 4: return launch_t<4, Codec>(a, variant, zc, st);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-void fused_geometry(int T, const Layout &L, int *ntx, int *nty, int *ntz, int *zc, int *threads)
+bool fused_fits(const Layout &L, int storage, int T)
 {
-    switch (T) {
-    case 1: geometry<1>(L, ntx, nty, ntz, zc, threads); break;
-    case 2: geometry<2>(L, ntx, nty, ntz, zc, threads); break;
-    case 3: geometry<3>(L, ntx, nty, ntz, zc, threads); break;
-    default: geometry<4>(L, ntx, nty, ntz, zc, threads); break;
-    }
+    const int es = storage == 0 ? 4 : 2;
+    return planes_fit(L, es) >= 2 * T + 2 && (long long)L.pitch * es < (1LL << 31);
 }
 
-hipError_t launch_fused(int storage, int T, const FusedArgs &a, hipStream_t st)
+hipError_t launch_fused(int storage, int T, const FusedArgs &a, int variant, int zc, hipStream_t st)
 {
     switch (storage) {
-    case 0: return launch_codec<CodecF32>(T, a, st);
-    case 1: return launch_codec<CodecF16>(T, a, st);
-    case 2: return launch_codec<CodecBF16>(T, a, st);
+    case 0: return launch_codec<CodecF32>(T, a, variant, zc, st);
+    case 1: return launch_codec<CodecF16>(T, a, variant, zc, st);
+    case 2: return launch_codec<CodecBF16>(T, a, variant, zc, st);
     }
     return hipErrorInvalidValue;
 }

@@ -7,15 +7,19 @@
 
 namespace yee {
 
-// Device field layout: component c of buffer b starts at base + c*cstride
-// (elements); point (i,j,k) sits at k*plane + j*pitch + i with
-// pitch >= nx+1 and plane = pitch*(ny+1).  The material index uses the
-// same offsets (one byte per point; bytes outside the cell range are 0).
+// Device field layout, plane-interleaved: the six components of one z plane
+// are stored one after another, so a z march reads one contiguous run per
+// plane.  Component c of point (i,j,k) sits at
+//     c*cstride + k*kstride + j*pitch + i
+// with pitch >= nx+1, plane = pitch*(ny+1), cstride = plane and
+// kstride = 6*plane.  The material index is a separate byte array addressed
+// k*plane + j*pitch + i (bytes outside the cell range are 0).
 struct Layout {
     int nx, ny, nz;
     int pitch;
     long long plane;
     long long cstride;
+    long long kstride;
 };
 
 // Reduced-storage control block (device).  maxbits holds, per component,
@@ -93,8 +97,11 @@ enum { DIAG_W = 11 };     // energy, div_e_sumsq, div_h_sumsq, div_e_max, div_h_
 // Launchers (return hipError_t of the launch).
 hipError_t launch_plain_step(const PlainArgs &a, const SourceTable &src, const ProbeTable &probe,
                              long long step, hipStream_t st);
-hipError_t launch_fused(int storage, int T, const FusedArgs &a, hipStream_t st);
-void fused_geometry(int T, const Layout &L, int *ntx, int *nty, int *ntz, int *zc, int *threads);
+// variant: tile shape (0 = default; FP32 also has 1 and 2); zc: planes per
+// z chunk (0 = automatic).
+hipError_t launch_fused(int storage, int T, const FusedArgs &a, int variant, int zc, hipStream_t st);
+// false if a z chunk of this grid cannot be addressed with 32-bit offsets
+bool fused_fits(const Layout &L, int storage, int T);
 hipError_t launch_diag(int storage, const DiagArgs &a, double *out11, hipStream_t st);
 int diag_blocks(const Layout &L);
 

@@ -22,16 +22,16 @@ __global__ __launch_bounds__(BX *BY) void h_plain(PlainArgs a)
     if (i > L.nx || j > L.ny) return;
     float *ex = a.f, *ey = a.f + L.cstride, *ez = a.f + 2 * L.cstride;
     float *hx = a.f + 3 * L.cstride, *hy = a.f + 4 * L.cstride, *hz = a.f + 5 * L.cstride;
-    const long long p = k * L.plane + (long long)j * L.pitch + i;
+    const long long p = k * L.kstride + (long long)j * L.pitch + i;
     // Faraday: H -= c dt curl E, z-difference term first, then y (cyclic).
     if (j < L.ny && k < L.nz) {
-        float dey_z = ey[p + L.plane] - ey[p];
+        float dey_z = ey[p + L.kstride] - ey[p];
         float dez_y = ez[p + L.pitch] - ez[p];
         hx[p] = __builtin_fmaf(-a.chy, dez_y, __builtin_fmaf(a.chz, dey_z, hx[p]));
     }
     if (i < L.nx && k < L.nz) {
         float dez_x = ez[p + 1] - ez[p];
-        float dex_z = ex[p + L.plane] - ex[p];
+        float dex_z = ex[p + L.kstride] - ex[p];
         hy[p] = __builtin_fmaf(-a.chz, dex_z, __builtin_fmaf(a.chx, dez_x, hy[p]));
     }
     if (i < L.nx && j < L.ny) {
@@ -54,17 +54,17 @@ __global__ __launch_bounds__(BX *BY) void e_plain(PlainArgs a)
     if (i > L.nx || j > L.ny) return;
     float *ex = a.f, *ey = a.f + L.cstride, *ez = a.f + 2 * L.cstride;
     const float *hx = a.f + 3 * L.cstride, *hy = a.f + 4 * L.cstride, *hz = a.f + 5 * L.cstride;
-    const long long p = k * L.plane + (long long)j * L.pitch + i;
-    const float4 cf = s_coef[a.mat[p]];   // Ca, Cbx, Cby, Cbz of the owner cell
+    const long long p = k * L.kstride + (long long)j * L.pitch + i;
+    const float4 cf = s_coef[a.mat[k * L.plane + (long long)j * L.pitch + i]];   // owner cell's Ca, Cbx, Cby, Cbz
     const bool kin = k > 0 && k < L.nz, jin = j > 0 && j < L.ny, iin = i > 0 && i < L.nx;
     // Ampere with loss: E = Ca E + Cb curl H on edges not tangential to a wall.
     if (i < L.nx && jin && kin) {
         float dhz_y = hz[p] - hz[p - L.pitch];
-        float dhy_z = hy[p] - hy[p - L.plane];
+        float dhy_z = hy[p] - hy[p - L.kstride];
         ex[p] = __builtin_fmaf(-cf.w, dhy_z, __builtin_fmaf(cf.z, dhz_y, cf.x * ex[p]));
     }
     if (j < L.ny && iin && kin) {
-        float dhx_z = hx[p] - hx[p - L.plane];
+        float dhx_z = hx[p] - hx[p - L.kstride];
         float dhz_x = hz[p] - hz[p - 1];
         ey[p] = __builtin_fmaf(-cf.y, dhz_x, __builtin_fmaf(cf.w, dhx_z, cf.x * ey[p]));
     }
@@ -82,7 +82,7 @@ __global__ void src_plain(float *f, Layout L, SourceTable s, long long step)
         int4 d = s.pos[q];
         int2 w = s.wave[q];
         if (step < w.y) {
-            long long p = d.x * L.cstride + d.w * L.plane + (long long)d.z * L.pitch + d.y;
+            long long p = d.x * L.cstride + d.w * L.kstride + (long long)d.z * L.pitch + d.y;
             f[p] = f[p] + s.samples[w.x + step];
         }
     }
@@ -93,7 +93,7 @@ __global__ void probe_plain(const float *f, Layout L, ProbeTable pt, long long s
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= pt.n) return;
     int4 d = pt.pos[q];
-    long long p = d.x * L.cstride + d.w * L.plane + (long long)d.z * L.pitch + d.y;
+    long long p = d.x * L.cstride + d.w * L.kstride + (long long)d.z * L.pitch + d.y;
     pt.out[(step - pt.base) * pt.n + q] = (double)f[p];
 }
 

@@ -52,6 +52,7 @@ def lib():
         L.fdtd_workspace_bytes.restype = sz
         L.fdtd_create.argtypes = [C.POINTER(vp), i, i, i, d, d, d, d, C.POINTER(_Material), i, vp, i, vp, sz, vp]
         L.fdtd_set_kernel.argtypes = [vp, i, i]
+        L.fdtd_set_tiling.argtypes = [vp, i, i]
         L.fdtd_set_fields.argtypes = [vp, vp]
         L.fdtd_set_source.argtypes = [vp, i, i, i, i, vp, i, C.POINTER(i)]
         L.fdtd_set_probe.argtypes = [vp, i, i, i, i, C.POINTER(i)]
@@ -66,7 +67,7 @@ def lib():
         L.fdtd_destroy.restype = None
         L.fdtd_last_error.restype = C.c_char_p
         L.fdtd_coefficients.argtypes = [C.POINTER(_Material), i, d, d, d, d, vp, vp]
-        for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
+        for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients"):
             getattr(L, name).restype = i
@@ -147,6 +148,9 @@ class Solver:
 
     def set_kernel(self, kernel, time_block):
         _check(lib().fdtd_set_kernel(self._h, kernel, time_block))
+
+    def set_tiling(self, variant=0, z_chunk=0):
+        _check(lib().fdtd_set_tiling(self._h, variant, z_chunk))
 
     def set_fields(self, f: Optional[np.ndarray]):
         if f is None:
