@@ -155,6 +155,16 @@ int fdtd_set_probe(fdtd_solver *s, int comp, int i, int j, int k, int *id);
  * waiting.  Saturation of reduced storage is reported by fdtd_synchronize. */
 int fdtd_step(fdtd_solver *s, int n_steps);
 
+/* Advance several solvers at once: n_steps[i] (>= 0) steps for solvers[i],
+ * count >= 0, every solver distinct, all created on the same stream and set
+ * to the FUSED kernel.  Each block (up to T steps, ending on multiples of
+ * T) is issued as one persistent launch over the tiles of up to 12 solvers
+ * that share storage format, block length and tile shape, so small grids
+ * share the GPU instead of each under-filling it.  Results are bit-identical
+ * to fdtd_step on each solver alone.  Enqueues only (continuous batching:
+ * solvers may join or leave between calls). */
+int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps);
+
 /* Copy one component of the current state to host (float,
  * (nx+1)(ny+1)(nz+1), x fastest; decoded if stored in reduced precision).
  * Synchronises the stream. */

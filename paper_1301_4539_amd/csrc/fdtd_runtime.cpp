@@ -306,6 +306,39 @@ int read_ctrl(fdtd_solver *s, yee::Ctrl *out)
     return e ? hip_fail(e, "hipMemcpy(ctrl)") : FDTD_OK;
 }
 
+// Length of the next block: blocks end at absolute multiples of T.
+int next_block(const fdtd_solver *s, int left)
+{
+    const int len = s->T - (int)(s->steps % s->T);
+    return std::min(len, left);
+}
+
+// Launch arguments of the next block of solver s (tile geometry excluded).
+void fill_fused(const fdtd_solver *s, yee::FusedArgs *a)
+{
+    std::memset(a, 0, sizeof(*a));
+    a->L = s->L;
+    a->mat = s->mat;
+    a->coef = s->coef_d;
+    a->n_mat = s->n_mat;
+    a->chx = s->ch[0];
+    a->chy = s->ch[1];
+    a->chz = s->ch[2];
+    a->src = src_table(s);
+    a->probe = probe_table(s);
+    a->fin = s->fbuf[s->cur];
+    a->fout = s->fbuf[s->cur ^ 1];
+    a->step0 = s->steps;
+    a->sb = storage_block(s);
+}
+
+void advance(fdtd_solver *s, int len)
+{
+    s->cur ^= 1;
+    s->steps += len;
+    s->block += 1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -590,30 +623,75 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         s->steps += n_steps;
         return FDTD_OK;
     }
-    yee::FusedArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.L = s->L;
-    a.mat = s->mat;
-    a.coef = s->coef_d;
-    a.n_mat = s->n_mat;
-    a.chx = s->ch[0]; a.chy = s->ch[1]; a.chz = s->ch[2];
-    a.src = src;
-    a.probe = probe;
     int left = n_steps;
     while (left > 0) {
-        const int T = s->T;
-        int len = T - (int)(s->steps % T);          // end blocks on multiples of T
-        len = std::min(len, left);
-        a.fin = s->fbuf[s->cur];
-        a.fout = s->fbuf[s->cur ^ 1];
-        a.step0 = s->steps;
-        a.sb = storage_block(s);
+        const int len = next_block(s, left);
+        yee::FusedArgs a;
+        fill_fused(s, &a);
         const int shape = s->tiling > 0 ? s->tiling - 1 : auto_shape(s->storage, len);
         if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
-        s->cur ^= 1;
-        s->steps += len;
-        s->block += 1;
+        advance(s, len);
         left -= len;
+    }
+    return FDTD_OK;
+}
+
+int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
+{
+    if (!solvers || !n_steps || count < 0) return fail(FDTD_EINVAL, "NULL argument");
+    if (count == 0) return FDTD_OK;
+    const hipStream_t st = solvers[0] ? solvers[0]->st : nullptr;
+    std::vector<int> left(count);
+    for (int i = 0; i < count; ++i) {
+        fdtd_solver *s = solvers[i];
+        if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+        if (s->st != st) return fail(FDTD_EINVAL, "batched solvers must share one stream");
+        if (s->kernel == FDTD_KERNEL_PLAIN) return fail(FDTD_EINVAL, "batched steps use the fused kernel");
+        if (n_steps[i] < 0) return fail(FDTD_EINVAL, "negative step count");
+        for (int j = 0; j < i; ++j)
+            if (solvers[j] == s) return fail(FDTD_EINVAL, "a solver appears twice in the batch");
+        left[i] = n_steps[i];
+        int rc = ensure_probe_rows(s, s->steps + n_steps[i]);
+        if (rc) return rc;
+    }
+    // Each round advances every unfinished solve by its next block; solves
+    // with equal (storage, block length, tile shape) share launches.
+    std::vector<int> len(count), key(count), done(count);
+    for (;;) {
+        bool any = false;
+        for (int i = 0; i < count; ++i) {
+            done[i] = 0;
+            if (left[i] > 0) {
+                fdtd_solver *s = solvers[i];
+                len[i] = next_block(s, left[i]);
+                const int shape = s->tiling > 0 ? s->tiling - 1 : auto_shape(s->storage, len[i]);
+                key[i] = (s->storage * 8 + len[i]) * 8 + shape;
+                any = true;
+            } else {
+                done[i] = 1;
+            }
+        }
+        if (!any) break;
+        for (int i = 0; i < count; ++i) {
+            if (done[i]) continue;
+            yee::FusedArgs group[yee::MAX_BATCH];
+            int members[yee::MAX_BATCH];
+            int n = 0;
+            for (int j = i; j < count && n < yee::MAX_BATCH; ++j)
+                if (!done[j] && key[j] == key[i]) {
+                    fill_fused(solvers[j], &group[n]);
+                    members[n++] = j;
+                    done[j] = 1;
+                }
+            const fdtd_solver *s0 = solvers[i];
+            const int shape = key[i] % 8;
+            hipError_t e = yee::launch_fused_batch(s0->storage, len[i], group, n, shape, s0->zchunk, st);
+            if (e) return hip_fail(e, "batched step");
+            for (int q = 0; q < n; ++q) {
+                advance(solvers[members[q]], len[i]);
+                left[members[q]] -= len[i];
+            }
+        }
     }
     return FDTD_OK;
 }

@@ -74,8 +74,24 @@ template <> struct Buf<CodecBF16> : Buf16<CodecBF16> {};
 
 constexpr int MAX_LOCAL = 256;   // sources / probes per solver
 
+template <int NW>
+struct TileShared {
+    float4 coef[256];
+    float2 e[NW + 1][64];    // (Ex, Ez) of each wave's first row; slot NW stays zero
+    float2 h[NW + 1][64];    // (Hx, Hz) of each wave's last row, in slot w+1; slot 0 stays zero
+    int4 src[MAX_LOCAL];     // sources this workgroup computes: (comp, lane, row, plane)
+    int2 srcw[MAX_LOCAL];    // their (sample offset, n_samples)
+    int4 prb[MAX_LOCAL];     // probes this workgroup owns: (comp, lane, row, plane)
+    int prbid[MAX_LOCAL];
+    int nsrc, nprb;
+};
+
+// One tile (x-y tile x z chunk) of one solve: T steps of the owned region.
+// `logical` is the tile index within the solve.  Starts and ends with every
+// thread of the workgroup in step, so a workgroup may run several tiles in a
+// row (the batched kernel does).
 template <int T, int RY, int NW, class Codec>
-__global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
+__device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical, TileShared<NW> &sm)
 {
     constexpr int OX = 64 - 2 * T;      // owned points per tile in x
     constexpr int NR = NW * RY;         // rows per tile
@@ -83,15 +99,9 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     using S = typename Codec::T;
     using B = Buf<Codec>;
     constexpr int ES = sizeof(S);
-
-    __shared__ float4 s_coef[256];
-    __shared__ float2 s_e[NW + 1][64];  // (Ex, Ez) of each wave's first row; slot NW stays zero
-    __shared__ float2 s_h[NW + 1][64];  // (Hx, Hz) of each wave's last row, in slot w+1; slot 0 stays zero
-    __shared__ int4 s_src[MAX_LOCAL];   // sources this workgroup computes: (comp, lane, row, plane)
-    __shared__ int2 s_srcw[MAX_LOCAL];  // their (sample offset, n_samples)
-    __shared__ int4 s_prb[MAX_LOCAL];   // probes this workgroup owns: (comp, lane, row, plane)
-    __shared__ int s_prbid[MAX_LOCAL];
-    __shared__ int s_nsrc, s_nprb;
+    float4 *const s_coef = sm.coef;
+    auto &s_e = sm.e;
+    auto &s_h = sm.h;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -100,11 +110,6 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
         s_e[NW][tid] = make_float2(0.0f, 0.0f);
         s_h[0][tid] = make_float2(0.0f, 0.0f);
     }
-
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous run of tiles so that halo re-reads hit its own L2.
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int logical = (b & 7) * (nb >> 3) + (b >> 3);
 
     float dn[6], up[6];
     if constexpr (Codec::scaled) {
@@ -126,7 +131,6 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     } else {
         for (int c = 0; c < 6; ++c) dn[c] = up[c] = 1.0f;
     }
-    if (logical >= a.nwg) return;   // uniform per workgroup; no barrier passed yet
 
     const Layout L = a.L;
     const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -149,8 +153,8 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
             const int4 d = a.src.pos[q];
             const int lx = d.y - xl, ry = d.z - yt;
             if (lx >= 0 && lx < 64 && ry >= 0 && ry < NR && d.w >= kb && d.w <= ke && ns < MAX_LOCAL) {
-                s_src[ns] = make_int4(d.x, lx, ry, d.w);
-                s_srcw[ns] = a.src.wave[q];
+                sm.src[ns] = make_int4(d.x, lx, ry, d.w);
+                sm.srcw[ns] = a.src.wave[q];
                 ++ns;
             }
         }
@@ -158,16 +162,16 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
             const int4 d = a.probe.pos[q];
             const int lx = d.y - xl, ry = d.z - yt;
             if (lx >= T && lx < T + OX && ry >= T && ry < T + OY && d.w >= z0 && d.w < z1 && np < MAX_LOCAL) {
-                s_prb[np] = make_int4(d.x, lx, ry, d.w);
-                s_prbid[np] = q;
+                sm.prb[np] = make_int4(d.x, lx, ry, d.w);
+                sm.prbid[np] = q;
                 ++np;
             }
         }
-        s_nsrc = ns;
-        s_nprb = np;
+        sm.nsrc = ns;
+        sm.nprb = np;
     }
     __syncthreads();
-    const int nsrc = s_nsrc, nprb = s_nprb;
+    const int nsrc = sm.nsrc, nprb = sm.nprb;
 
     // lane and row predicates
     const bool xin = x >= 0 && x <= nx;
@@ -309,8 +313,8 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
                 // ---- soft sources of step step0+t-1, on every tile computing the edge ----
                 const long long n = a.step0 + (t - 1);
                 for (int q = 0; q < nsrc; ++q) {
-                    const int4 d = s_src[q];
-                    const int2 wv = s_srcw[q];
+                    const int4 d = sm.src[q];
+                    const int2 wv = sm.srcw[q];
                     if (d.w != p || n >= wv.y || d.z / RY != w) continue;
                     const float val = a.src.samples[wv.x + n];
                     if (lane == d.y) {
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
                 // ---- probes, recorded by the owning tile only (planes outside
                 // [z0, z1) are this chunk's halo, where upper levels are incomplete) ----
                 for (int q = 0; q < nprb; ++q) {
-                    const int4 d = s_prb[q];
+                    const int4 d = sm.prb[q];
                     if (d.w != p || d.z / RY != w) continue;
                     if (lane == d.y) {
                         float v = 0.0f;
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
                                 v = d.x == 0 ? En[0][r] : d.x == 1 ? En[1][r] : d.x == 2 ? En[2][r]
                                   : d.x == 3 ? Hn[0][r] : d.x == 4 ? Hn[1][r] : Hn[2][r];
                             }
-                        a.probe.out[(n - a.probe.base) * a.probe.n + s_prbid[q]] = (double)v;
+                        a.probe.out[(n - a.probe.base) * a.probe.n + sm.prbid[q]] = (double)v;
                     }
                 }
                 // ---- rotate: level t's previous plane becomes level t+1's input ----
@@ -393,7 +397,6 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     int K = kb;
     const int kw = min(kb + T, ke);
     for (; K < kw; ++K) iterate(K, std::false_type{});
-#pragma unroll 2
     for (; K < ke; ++K) iterate(K, std::true_type{});
     for (; K <= ke + T; ++K) iterate(K, std::false_type{});
 #undef YEE_LOAD_PLANE
@@ -408,6 +411,34 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
         }
         const unsigned long long any = __ballot(flag != 0u);
         if (lane == 0 && any) atomicOr(&a.sb.ctrl->flag, 1u);
+    }
+    __syncthreads();   // LDS is reused by the next tile of a batched launch
+}
+
+template <int T, int RY, int NW, class Codec>
+__global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
+{
+    __shared__ TileShared<NW> sm;
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous run of tiles so that halo re-reads hit its own L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int logical = (b & 7) * (nb >> 3) + (b >> 3);
+    if (logical >= a.nwg) return;   // uniform per workgroup
+    fused_tile<T, RY, NW, Codec>(a, logical, sm);
+}
+
+// Several solves in one persistent launch: the workgroups stride over the
+// concatenated tile lists of up to MAX_BATCH solves (same storage format and
+// block length), so small grids that could not fill the GPU alone share it.
+template <int T, int RY, int NW, class Codec>
+__global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
+{
+    __shared__ TileShared<NW> sm;
+    const int total = a.start[a.n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        int i = 0;
+        while (i + 1 < a.n && item >= a.start[i + 1]) ++i;
+        fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], sm);
     }
 }
 
@@ -463,24 +494,64 @@ hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int T, class Codec>
-hipError_t launch_t(const FusedArgs &a, int variant, int zc, hipStream_t st)
+template <int T, int V, class Codec>
+hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t st)
 {
+    static_assert(sizeof(BatchArgs) <= 4000, "batch descriptors must fit the kernel argument segment");
+    constexpr Tiling tl = kTilings[T][V];
+    BatchArgs b;
+    b.n = n;
+    b.start[0] = 0;
+    int threads = 64 * tl.nw;
+    for (int i = 0; i < n; ++i) {
+        FusedArgs &a = b.s[i];
+        a = args[i];
+        geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+        a.nwg = a.ntx * a.nty * a.ntz;
+        b.start[i + 1] = b.start[i] + a.nwg;
+    }
+    // persistent: at most ~4 resident workgroups per CU, each striding over the work list
+    const int grid = std::min(b.start[n], 1024);
+    hipLaunchKernelGGL((yee_fused_batch<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, b);
+    return hipGetLastError();
+}
+
+template <int T, class Codec>
+hipError_t launch_t(const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st)
+{
+    if (batch) {
+        switch (variant) {
+        case 1: return launch_batch_tv<T, 1, Codec>(a, n, zc, st);
+        case 2: return launch_batch_tv<T, 2, Codec>(a, n, zc, st);
+        default: return launch_batch_tv<T, 0, Codec>(a, n, zc, st);
+        }
+    }
     switch (variant) {
-    case 1: return launch_tv<T, 1, Codec>(a, zc, st);
-    case 2: return launch_tv<T, 2, Codec>(a, zc, st);
-    default: return launch_tv<T, 0, Codec>(a, zc, st);
+    case 1: return launch_tv<T, 1, Codec>(*a, zc, st);
+    case 2: return launch_tv<T, 2, Codec>(*a, zc, st);
+    default: return launch_tv<T, 0, Codec>(*a, zc, st);
     }
 }
 
 template <class Codec>
-hipError_t launch_codec(int T, const FusedArgs &a, int variant, int zc, hipStream_t st)
+hipError_t launch_codec(int T, const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st)
 {
     switch (T) {
-    case 1: return launch_t<1, Codec>(a, variant, zc, st);
-    case 2: return launch_t<2, Codec>(a, variant, zc, st);
-    case 3: return launch_t<3, Codec>(a, variant, zc, st);
-    case 4: return launch_t<4, Codec>(a, variant, zc, st);
+    case 1: return launch_t<1, Codec>(a, n, batch, variant, zc, st);
+    case 2: return launch_t<2, Codec>(a, n, batch, variant, zc, st);
+    case 3: return launch_t<3, Codec>(a, n, batch, variant, zc, st);
+    case 4: return launch_t<4, Codec>(a, n, batch, variant, zc, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_any(int storage, int T, const FusedArgs *a, int n, bool batch, int variant, int zc,
+                      hipStream_t st)
+{
+    switch (storage) {
+    case 0: return launch_codec<CodecF32>(T, a, n, batch, variant, zc, st);
+    case 1: return launch_codec<CodecF16>(T, a, n, batch, variant, zc, st);
+    case 2: return launch_codec<CodecBF16>(T, a, n, batch, variant, zc, st);
     }
     return hipErrorInvalidValue;
 }
@@ -495,12 +566,14 @@ bool fused_fits(const Layout &L, int storage, int T)
 
 hipError_t launch_fused(int storage, int T, const FusedArgs &a, int variant, int zc, hipStream_t st)
 {
-    switch (storage) {
-    case 0: return launch_codec<CodecF32>(T, a, variant, zc, st);
-    case 1: return launch_codec<CodecF16>(T, a, variant, zc, st);
-    case 2: return launch_codec<CodecBF16>(T, a, variant, zc, st);
-    }
-    return hipErrorInvalidValue;
+    return launch_any(storage, T, &a, 1, false, variant, zc, st);
+}
+
+hipError_t launch_fused_batch(int storage, int T, const FusedArgs *args, int n, int variant, int zc,
+                              hipStream_t st)
+{
+    if (n < 1 || n > MAX_BATCH) return hipErrorInvalidValue;
+    return launch_any(storage, T, args, n, true, variant, zc, st);
 }
 
 }  // namespace yee

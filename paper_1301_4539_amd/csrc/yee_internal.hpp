@@ -70,6 +70,16 @@ struct FusedArgs {
     StorageBlock sb;
 };
 
+// Up to MAX_BATCH solves in one launch; start[i] is the first work item
+// (tile) of solve i, start[n] the total.  Passed by value as kernel
+// arguments (no device copy of the descriptors).
+constexpr int MAX_BATCH = 12;
+struct BatchArgs {
+    int n;
+    int start[MAX_BATCH + 1];
+    FusedArgs s[MAX_BATCH];
+};
+
 struct PlainArgs {
     Layout L;
     float *f;             // in-place FP32 fields
@@ -100,6 +110,10 @@ hipError_t launch_plain_step(const PlainArgs &a, const SourceTable &src, const P
 // variant: tile shape (0 = default; FP32 also has 1 and 2); zc: planes per
 // z chunk (0 = automatic).
 hipError_t launch_fused(int storage, int T, const FusedArgs &a, int variant, int zc, hipStream_t st);
+// One persistent launch over several solves sharing storage, T and shape;
+// each args[i] is complete except for its tile geometry, which is filled in.
+hipError_t launch_fused_batch(int storage, int T, const FusedArgs *args, int n, int variant, int zc,
+                              hipStream_t st);
 // false if a z chunk of this grid cannot be addressed with 32-bit offsets
 bool fused_fits(const Layout &L, int storage, int T);
 hipError_t launch_diag(int storage, const DiagArgs &a, double *out11, hipStream_t st);

@@ -57,6 +57,7 @@ def lib():
         L.fdtd_set_source.argtypes = [vp, i, i, i, i, vp, i, C.POINTER(i)]
         L.fdtd_set_probe.argtypes = [vp, i, i, i, i, C.POINTER(i)]
         L.fdtd_step.argtypes = [vp, i]
+        L.fdtd_step_batch.argtypes = [C.POINTER(vp), i, C.POINTER(i)]
         L.fdtd_read_fields.argtypes = [vp, i, vp]
         L.fdtd_read_probes.argtypes = [vp, vp, ll, i]
         L.fdtd_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
@@ -68,7 +69,7 @@ def lib():
         L.fdtd_last_error.restype = C.c_char_p
         L.fdtd_coefficients.argtypes = [C.POINTER(_Material), i, d, d, d, d, vp, vp]
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
-                     "fdtd_step", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
+                     "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients"):
             getattr(L, name).restype = i
         _lib = L
@@ -97,6 +98,14 @@ def coefficients(eps_r, sigma, dx, dy, dz, dt, mu_r=None):
     ch = np.zeros(3, np.float32)
     _check(lib().fdtd_coefficients(arr, n, dx, dy, dz, dt, out.ctypes.data, ch.ctypes.data))
     return out, ch
+
+
+def step_batch(solvers, n_steps):
+    """Advance solvers[i] by n_steps[i] steps in shared persistent launches."""
+    n = len(solvers)
+    hs = (C.c_void_p * max(n, 1))(*[s._h for s in solvers])
+    ns = (C.c_int * max(n, 1))(*[int(k) for k in n_steps])
+    _check(lib().fdtd_step_batch(hs, n, ns))
 
 
 def workspace_bytes(nx, ny, nz, storage=FP32):
