@@ -19,11 +19,17 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "G Yee cell-updates/s and % HBM roofline (FP32 vs FP16 store); p50/p99 latency"
+# Arrival rate of the serving run, frozen after one calibration on MI355X:
+# 0.7 x the saturated mixed throughput (122.7 G cell-updates/s with all 256
+# requests queued at once) / the mean work per request (9.81 G) = 8.75 req/s.
+SERVING_RATE = 8.75
 
 
 def kernel_source_hash() -> str:
@@ -95,6 +101,24 @@ def cpu_baseline(wl, budget_s=15.0):
                       f"operation-order oracle from zero fields, {oracle.threads()} OpenMP threads"}
 
 
+def serving_leg(rate, n, torch):
+    """256 requests (dims U{48..320}, 5-60 spheres, 200-3000 steps, FP32 or
+    FP16 storage, 8 probes) with Poisson arrivals at `rate`; returns the
+    summary of the continuous-batching engine."""
+    from paper_1301_4539_amd import serve, workload as W
+    reqs = W.serving_requests(n=n, rate=rate, seed=1004)
+    t0 = time.perf_counter()
+    wls = {r.rid: r.workload() for r in reqs}
+    print(f"[bench] serving: {n} request payloads built in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    eng = serve.Engine(serve.GpuBackend(wls, time_block=4), budget_bytes=24 << 30, max_slots=64, chunk=64)
+    rep = eng.run(reqs)
+    out = rep.summary()
+    out.update({"rate_req_per_s": rate, "budget_GiB": 24, "max_slots": 64, "chunk_steps": 64,
+                "mean_work_G": float(np.mean([r.nx * r.ny * r.nz * r.n_steps for r in reqs]) / 1e9)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +133,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP16 and latency measurements")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="storage of the timed run (the JSON line reports fp32)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the 256-request serving workload (Poisson arrivals, mixed FP32/FP16)")
+    ap.add_argument("--serving-rate", type=float, default=SERVING_RATE,
+                    help="Poisson arrival rate (requests/s) of the serving run")
+    ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -128,7 +157,6 @@ def main():
               f"(multi-GPU decomposition is design-only).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1301_4539_amd import fdtd, roofline, workload as W
 
@@ -218,6 +246,9 @@ def main():
                      "avg_launch_ms": t * 1e3 / launches, "launches": launches},
     }
     line.update(extras)
+    if not args.no_serving and not args.no_extras:
+        line["serving"] = serving_leg(args.serving_rate, args.serving_requests, torch)
+        print(f"[bench] serving: {line['serving']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

@@ -1,0 +1,178 @@
+"""Continuous-batching serving loop for FDTD solves.
+
+Requests (grid size, material layout, step count, storage format) arrive
+over time.  The engine admits them in arrival order while a slot is free and
+their device footprint fits the HBM budget, keeps their fields resident, and
+advances every admitted solve by a chunk of steps per tick through
+fdtd_step_batch, so small grids share persistent launches.  Solves admitted
+between ticks join the next tick; finished solves release their slot and
+memory.  Latency runs from arrival to the probe records being on the host.
+
+The scheduler is independent of the device: `GpuBackend` drives the HIP
+library; tests drive the same scheduler with a virtual-clock fake.
+(Co-scheduled solves share one memory system, as jobs sharing a node do in
+Sec. 2.4; batching them keeps the GPU full instead of time-slicing it.)
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Record:
+    rid: int
+    arrival: float
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    cell_updates: int = 0
+    storage: int = 0
+    probes: Optional[np.ndarray] = None
+    requeues: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+@dataclasses.dataclass
+class Report:
+    records: List[Record]
+    makespan: float
+    busy: float                  # time spent inside backend.step + sync
+    rejected: List[int]
+
+    def latencies(self) -> np.ndarray:
+        return np.array([r.latency for r in self.records if np.isfinite(r.finished)])
+
+    def summary(self) -> dict:
+        lat = self.latencies()
+        work = sum(r.cell_updates for r in self.records if np.isfinite(r.finished))
+        return {"requests": len(lat), "rejected": len(self.rejected),
+                "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+                "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+                "mean_s": float(lat.mean()) if len(lat) else None,
+                "throughput_G_per_s": work / self.makespan / 1e9 if self.makespan > 0 else None,
+                "makespan_s": self.makespan, "busy_frac": self.busy / self.makespan if self.makespan else None,
+                "requeues": sum(r.requeues for r in self.records)}
+
+
+class AdmissionError(RuntimeError):
+    """Raised by a backend when a solve cannot be allocated right now."""
+
+
+class Engine:
+    def __init__(self, backend, budget_bytes: int = 24 << 30, max_slots: int = 64, chunk: int = 64):
+        assert chunk > 0
+        self.b = backend
+        self.budget = budget_bytes
+        self.max_slots = max_slots
+        self.chunk = chunk
+
+    def run(self, requests) -> Report:
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting: collections.deque = collections.deque()
+        active: List[dict] = []
+        recs: Dict[int, Record] = {r.rid: Record(r.rid, r.arrival, storage=r.storage) for r in requests}
+        rejected = []
+        used = 0
+        busy = 0.0
+        t0 = self.b.now()
+        while pending or waiting or active:
+            now = self.b.now() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission: arrival order, while a slot and the memory budget allow
+            while waiting and len(active) < self.max_slots:
+                req = waiting[0]
+                fp = self.b.footprint(req)
+                if fp > self.budget:
+                    rejected.append(req.rid)
+                    waiting.popleft()
+                    continue
+                if used + fp > self.budget:
+                    break
+                try:
+                    h = self.b.create(req)
+                except AdmissionError:
+                    recs[req.rid].requeues += 1
+                    break                       # retry at the next tick
+                waiting.popleft()
+                used += fp
+                recs[req.rid].admitted = self.b.now() - t0
+                active.append({"req": req, "h": h, "left": req.n_steps, "fp": fp})
+            if not active:
+                if pending:
+                    self.b.wait_until(t0 + pending[0].arrival)
+                elif waiting:
+                    # nothing fits even on an idle device: the budget forbids it
+                    rejected.append(waiting.popleft().rid)
+                continue
+            counts = [min(a["left"], self.chunk) for a in active]
+            ts = self.b.now()
+            self.b.step([a["h"] for a in active], counts)
+            self.b.sync()
+            busy += self.b.now() - ts
+            still = []
+            for a, c in zip(active, counts):
+                a["left"] -= c
+                if a["left"] == 0:
+                    r = recs[a["req"].rid]
+                    r.probes = self.b.finish(a["h"], a["req"])
+                    r.finished = self.b.now() - t0
+                    r.cell_updates = a["req"].nx * a["req"].ny * a["req"].nz * a["req"].n_steps
+                    used -= a["fp"]
+                else:
+                    still.append(a)
+            active = still
+        done = [r for r in recs.values() if np.isfinite(r.finished)]
+        makespan = max((r.finished for r in done), default=0.0) - min((r.arrival for r in done), default=0.0)
+        return Report(sorted(recs.values(), key=lambda r: r.rid), makespan, busy, rejected)
+
+
+class GpuBackend:
+    """Drives the HIP library.  `workloads` maps request id to a pre-built
+    Workload (the request payload: grid, materials, sources, probes)."""
+
+    def __init__(self, workloads, time_block: int = 4):
+        import torch
+        from . import fdtd
+        self.fdtd = fdtd
+        self.torch = torch
+        self.wl = workloads
+        self.T = time_block
+
+    def now(self) -> float:
+        return time.perf_counter()
+
+    def wait_until(self, t: float):
+        d = t - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+
+    def footprint(self, req) -> int:
+        return self.fdtd.workspace_bytes(req.nx, req.ny, req.nz, req.storage) + 8 * 8 * (req.n_steps + 256)
+
+    def create(self, req):
+        try:
+            return self.fdtd.Solver.from_workload(self.wl[req.rid], kernel=self.fdtd.KERNEL_FUSED,
+                                                  time_block=self.T)
+        except (self.fdtd.FdtdError, self.torch.cuda.OutOfMemoryError) as e:
+            if isinstance(e, self.fdtd.FdtdError) and e.code != self.fdtd.ENOMEM:
+                raise
+            raise AdmissionError(str(e)) from e
+
+    def step(self, handles, counts):
+        self.fdtd.step_batch(handles, counts)
+
+    def sync(self):
+        self.torch.cuda.synchronize()
+
+    def finish(self, h, req) -> np.ndarray:
+        p = h.read_probes(0, req.n_steps)
+        h.close()
+        return p

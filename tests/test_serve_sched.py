@@ -1,0 +1,107 @@
+"""The serving scheduler on a fake device: a virtual clock advanced by a
+cost model (cell-updates / rate + per-tick overhead), no GPU."""
+import numpy as np
+import pytest
+
+from paper_1301_4539_amd import serve, workload as W
+
+
+class Fake:
+    def __init__(self, rate=1e9, overhead=1e-3, fail_once=()):
+        self.t = 0.0
+        self.rate, self.overhead = rate, overhead
+        self.fail_once = set(fail_once)
+        self.live = {}
+        self.max_live = 0
+        self.max_bytes = 0
+        self.order = []
+
+    def now(self):
+        return self.t
+
+    def wait_until(self, t):
+        self.t = max(self.t, t)
+
+    def footprint(self, req):
+        return req.nx * req.ny * req.nz * 49
+
+    def create(self, req):
+        if req.rid in self.fail_once:
+            self.fail_once.discard(req.rid)
+            raise serve.AdmissionError("fake allocation failure")
+        self.live[req.rid] = self.footprint(req)
+        self.max_live = max(self.max_live, len(self.live))
+        self.max_bytes = max(self.max_bytes, sum(self.live.values()))
+        self.order.append(req.rid)
+        return req
+
+    def step(self, handles, counts):
+        self.t += self.overhead + sum(h.nx * h.ny * h.nz * c for h, c in zip(handles, counts)) / self.rate
+
+    def sync(self):
+        pass
+
+    def finish(self, h, req):
+        del self.live[req.rid]
+        return np.full((req.n_steps, 8), float(req.rid))
+
+
+def _reqs(n=40, rate=20.0, seed=5):
+    return W.serving_requests(n=n, rate=rate, seed=seed, dim_lo=16, dim_hi=48, steps_lo=20, steps_hi=200)
+
+
+def test_all_complete_in_arrival_order_within_limits():
+    reqs = _reqs()
+    fake = Fake()
+    budget = 6 * 48 ** 3 * 49
+    rep = serve.Engine(fake, budget_bytes=budget, max_slots=4, chunk=16).run(reqs)
+    assert not rep.rejected
+    assert all(np.isfinite(r.finished) for r in rep.records)
+    assert fake.order == [r.rid for r in sorted(reqs, key=lambda r: (r.arrival, r.rid))]
+    assert fake.max_live <= 4 and fake.max_bytes <= budget
+    for r, q in zip(rep.records, sorted(reqs, key=lambda r: r.rid)):
+        assert r.admitted >= q.arrival - 1e-12
+        assert r.finished >= r.admitted + q.nx * q.ny * q.nz * q.n_steps / fake.rate - 1e-9
+        assert r.probes.shape == (q.n_steps, 8) and r.probes[0, 0] == q.rid
+    s = rep.summary()
+    lat = rep.latencies()
+    assert s["p50_s"] == float(np.percentile(lat, 50)) and s["p99_s"] == float(np.percentile(lat, 99))
+    assert s["requests"] == len(reqs)
+
+
+def test_continuous_batching_admits_while_others_run():
+    """A short request arriving while a long one runs joins at the next tick
+    and finishes first (not a run-to-completion queue)."""
+    long = W.Request(0, 0.0, 48, 48, 48, 5, 2000, W.FP32)
+    short = W.Request(1, 0.01, 16, 16, 16, 5, 40, W.FP32)
+    fake = Fake(rate=1e9)
+    rep = serve.Engine(fake, budget_bytes=1 << 40, max_slots=8, chunk=32).run([long, short])
+    r0, r1 = rep.records
+    assert r1.admitted < r0.finished
+    assert r1.finished < r0.finished
+
+
+def test_allocation_failure_requeues():
+    reqs = _reqs(n=10)
+    fake = Fake(fail_once={3, 7})
+    rep = serve.Engine(fake, budget_bytes=1 << 40, max_slots=3, chunk=16).run(reqs)
+    assert all(np.isfinite(r.finished) for r in rep.records)
+    assert rep.records[3].requeues == 1 and rep.records[7].requeues == 1
+    assert rep.summary()["requeues"] == 2
+
+
+def test_oversized_request_is_rejected_not_blocking():
+    reqs = [W.Request(0, 0.0, 100, 100, 100, 5, 10, W.FP32), W.Request(1, 0.0, 10, 10, 10, 5, 10, W.FP32)]
+    fake = Fake()
+    rep = serve.Engine(fake, budget_bytes=10 ** 6, max_slots=2, chunk=8).run(reqs)
+    assert rep.rejected == [0]
+    assert np.isfinite(rep.records[1].finished)
+
+
+def test_budget_limits_concurrency():
+    reqs = [W.Request(i, 0.0, 32, 32, 32, 5, 64, W.FP32) for i in range(6)]
+    fake = Fake()
+    fp = 32 ** 3 * 49
+    rep = serve.Engine(fake, budget_bytes=2 * fp, max_slots=64, chunk=16).run(reqs)
+    assert fake.max_live == 2
+    assert all(np.isfinite(r.finished) for r in rep.records)
