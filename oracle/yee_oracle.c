@@ -425,25 +425,30 @@ void orc_choose_scales(const float *m_prev, float a_max, int *s_out)
 static float quantize_array(int fmt, int s, size_t n, float *x, int *flag)
 {
     float mx = 0.0f;
+    int fl = 0;
     const float up = ldexpf(1.0f, s), down = ldexpf(1.0f, -s);
+    /* every element is independent; the maximum and the flag do not depend
+     * on the order of the reduction */
+    #pragma omp parallel for schedule(static) reduction(max : mx) reduction(| : fl)
     for (size_t p = 0; p < n; p++) {
         float y = x[p] * up;
         float r;
         if (fmt == 1) {
             uint16_t h = f32_to_f16_bits(y);
-            if ((h & 0x7fffu) == 0x7c00u) { h = (uint16_t)((h & 0x8000u) | 0x7bffu); *flag = 1; }
-            if ((h & 0x7fffu) > 0x7c00u) *flag = 1;
+            if ((h & 0x7fffu) == 0x7c00u) { h = (uint16_t)((h & 0x8000u) | 0x7bffu); fl = 1; }
+            if ((h & 0x7fffu) > 0x7c00u) fl = 1;
             r = f16_bits_to_f32(h);
         } else {
             uint16_t h = f32_to_bf16_bits(y);
-            if ((h & 0x7fffu) == 0x7f80u) { h = (uint16_t)((h & 0x8000u) | 0x7f7fu); *flag = 1; }
-            if ((h & 0x7fffu) > 0x7f80u) *flag = 1;
+            if ((h & 0x7fffu) == 0x7f80u) { h = (uint16_t)((h & 0x8000u) | 0x7f7fu); fl = 1; }
+            if ((h & 0x7fffu) > 0x7f80u) fl = 1;
             r = bf16_bits_to_f32(h);
         }
         x[p] = r * down;
         float a = fabsf(x[p]);
         if (a > mx) mx = a;
     }
+    if (fl) *flag = 1;
     return mx;
 }
 
@@ -459,8 +464,10 @@ void orc_quantize_state(int nx, int ny, int nz, int fmt, int upload, float a_max
         m[c] = m_stored[c];
         if (upload) {
             const float *x = f + (size_t)c * g.n;
-            m[c] = 0.0f;
-            for (size_t p = 0; p < g.n; p++) if (fabsf(x[p]) > m[c]) m[c] = fabsf(x[p]);
+            float mc = 0.0f;
+            #pragma omp parallel for schedule(static) reduction(max : mc)
+            for (size_t p = 0; p < g.n; p++) if (fabsf(x[p]) > mc) mc = fabsf(x[p]);
+            m[c] = mc;
         }
     }
     orc_choose_scales(m, a_max, scales);

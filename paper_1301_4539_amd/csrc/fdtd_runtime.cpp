@@ -90,6 +90,21 @@ bool e_interior(int nx, int ny, int nz, int c, int i, int j, int k)
     return false;
 }
 
+// Stored range of component c on row (j,k): true and [i0, i1) if the row holds
+// values (inside the component's range, and not tangential E on a wall).
+bool row_span(int nx, int ny, int nz, int c, int j, int k, int *i0, int *i1)
+{
+    switch (c) {
+    case 0: *i0 = 0; *i1 = nx; return j > 0 && j < ny && k > 0 && k < nz;
+    case 1: *i0 = 1; *i1 = nx; return j < ny && k > 0 && k < nz;
+    case 2: *i0 = 1; *i1 = nx; return k < nz && j > 0 && j < ny;
+    case 3: *i0 = 0; *i1 = nx + 1; return j < ny && k < nz;
+    case 4: *i0 = 0; *i1 = nx; return k < nz;
+    case 5: *i0 = 0; *i1 = nx; return j < ny;
+    }
+    return false;
+}
+
 // ---- reduced-storage codec on the host (upload and readback) ---------------
 uint16_t enc_f16(float y)
 {
@@ -498,54 +513,63 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
             return hip_fail(e, "zero fields");
         return FDTD_OK;
     }
-    // clean copy: zero outside each component's range and on PEC edges
-    std::vector<float> f(host, host + 6 * nbox);
-    for (int c = 0; c < 6; ++c)
-        for (int k = 0; k <= nz; ++k)
-            for (int j = 0; j <= ny; ++j)
-                for (int i = 0; i <= nx; ++i) {
-                    const size_t p = (size_t)c * nbox + i + (size_t)(nx + 1) * (j + (size_t)(ny + 1) * k);
-                    bool keep = in_range(nx, ny, nz, c, i, j, k);
-                    if (c < 3) keep = keep && e_interior(nx, ny, nz, c, i, j, k);
-                    if (!keep) f[p] = 0.0f;
-                }
-    std::vector<uint16_t> q;
+    // Stored values per component and row: positions outside the component's
+    // range and tangential E on the walls are zero.  Pass 1: maxima (for the
+    // reduced-storage scales); pass 2: clean, encode and upload plane by plane.
+    const size_t nplane = (size_t)(nx + 1) * (ny + 1);
+    float m[6] = {0, 0, 0, 0, 0, 0};
+    int sc[6] = {0, 0, 0, 0, 0, 0};
     if (s->storage != FDTD_FP32) {
-        float m[6];
-        for (int c = 0; c < 6; ++c) {
-            m[c] = 0.0f;
-            for (size_t p = 0; p < nbox; ++p) m[c] = std::max(m[c], std::fabs(f[c * nbox + p]));
-        }
-        int sc[6];
+        for (int c = 0; c < 6; ++c)
+            for (int k = 0; k <= nz; ++k)
+                for (int j = 0; j <= ny; ++j) {
+                    int i0, i1;
+                    if (!row_span(nx, ny, nz, c, j, k, &i0, &i1)) continue;
+                    const float *row = host + (size_t)c * nbox + (size_t)k * nplane + (size_t)j * (nx + 1);
+                    for (int i = i0; i < i1; ++i) m[c] = std::max(m[c], std::fabs(row[i]));
+                }
         choose_scales(m, s->a_max, sc);
-        q.resize(6 * nbox);
-        bool sat = false;
-        for (int c = 0; c < 6; ++c) {
-            const float upf = std::ldexp(1.0f, sc[c]), dnf = std::ldexp(1.0f, -sc[c]);
-            float mx = 0.0f;
-            for (size_t p = 0; p < nbox; ++p) {
-                uint16_t h = encode(s->storage, f[c * nbox + p] * upf, &sat);
-                q[c * nbox + p] = h;
-                const float v = std::fabs(decode(s->storage, h) * dnf);
-                if (v > mx) mx = v;           // NaN never compares greater
+    }
+    if ((e = hipMemsetAsync(s->fbuf[0], 0, s->d.fbytes, s->st))) return hip_fail(e, "hipMemset");
+    std::vector<float> pf(s->storage == FDTD_FP32 ? nplane : 0);
+    std::vector<uint16_t> pq(s->storage == FDTD_FP32 ? 0 : nplane);
+    float mx[6] = {0, 0, 0, 0, 0, 0};
+    bool sat = false;
+    for (int c = 0; c < 6; ++c) {
+        const float upf = std::ldexp(1.0f, sc[c]), dnf = std::ldexp(1.0f, -sc[c]);
+        for (int k = 0; k <= nz; ++k) {
+            const float *src = host + (size_t)c * nbox + (size_t)k * nplane;
+            for (int j = 0; j <= ny; ++j) {
+                int i0 = 0, i1 = 0;
+                const bool any = row_span(nx, ny, nz, c, j, k, &i0, &i1);
+                const size_t r = (size_t)j * (nx + 1);
+                for (int i = 0; i <= nx; ++i) {
+                    const float v = (any && i >= i0 && i < i1) ? src[r + i] : 0.0f;
+                    if (s->storage == FDTD_FP32) {
+                        pf[r + i] = v;
+                    } else {
+                        const uint16_t h = encode(s->storage, v * upf, &sat);
+                        pq[r + i] = h;
+                        const float d = std::fabs(decode(s->storage, h) * dnf);
+                        if (d > mx[c]) mx[c] = d;        // NaN never compares greater
+                    }
+                }
             }
+            const void *plane = s->storage == FDTD_FP32 ? (const void *)pf.data() : (const void *)pq.data();
+            e = hipMemcpy2DAsync(s->fbuf[0] + ((size_t)c * s->L.cstride + (size_t)k * s->L.kstride) * es,
+                                 (size_t)s->d.pitch * es, plane, (size_t)(nx + 1) * es, (size_t)(nx + 1) * es,
+                                 (size_t)(ny + 1), hipMemcpyHostToDevice, s->st);
+            if (!e) e = hipStreamSynchronize(s->st);         // the staging plane is reused
+            if (e) return hip_fail(e, "upload fields");
+        }
+    }
+    if (s->storage != FDTD_FP32) {
+        for (int c = 0; c < 6; ++c) {
             ctrl.scale[0][c] = sc[c];
-            std::memcpy(&ctrl.maxbits[0][c], &mx, 4);
+            std::memcpy(&ctrl.maxbits[0][c], &mx[c], 4);
         }
         ctrl.flag = sat ? 1u : 0u;
     }
-    const void *src = s->storage == FDTD_FP32 ? (const void *)f.data() : (const void *)q.data();
-    if ((e = hipMemsetAsync(s->fbuf[0], 0, s->d.fbytes, s->st))) return hip_fail(e, "hipMemset");
-    const size_t nplane = (size_t)(nx + 1) * (ny + 1);
-    for (int c = 0; c < 6; ++c)
-        for (int k = 0; k <= nz; ++k) {
-            e = hipMemcpy2DAsync(s->fbuf[0] + ((size_t)c * s->L.cstride + (size_t)k * s->L.kstride) * es,
-                                 (size_t)s->d.pitch * es,
-                                 (const char *)src + ((size_t)c * nbox + (size_t)k * nplane) * es,
-                                 (size_t)(nx + 1) * es, (size_t)(nx + 1) * es, (size_t)(ny + 1),
-                                 hipMemcpyHostToDevice, s->st);
-            if (e) return hip_fail(e, "upload fields");
-        }
     if ((e = hipMemcpyAsync(s->ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s->st)) ||
         (e = hipStreamSynchronize(s->st)))
         return hip_fail(e, "upload fields");

@@ -1,0 +1,90 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (fused kernel, T=4, automatic tile shape).
+
+Short runs from a seeded random state are compared element by element with
+the oracle (the oracle takes a few seconds per step at these sizes on the
+host cores).  Full-length runs are checked through properties that hold at
+any size: every kernel variant gives the same bits, and probes equal the
+field values they sample."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_4539_amd import fdtd, workload as W
+from tests import gpu_helpers as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_init(wl, seed):
+    rng = np.random.default_rng(seed)
+    f = rng.random((6, wl.nz + 1, wl.ny + 1, wl.nx + 1), dtype=np.float32)
+    f -= np.float32(0.5)
+    return G.pec_clean(wl, f)
+
+
+def _check(a, b, what):
+    msg = G.first_mismatch(a, b)
+    assert msg is None, f"{what}: {msg}"
+
+
+@pytest.mark.parametrize("name", ["spheres256", "spheres512"])
+def test_fullsize_fp32_short_run_bitexact(name):
+    wl = W.spheres256() if name == "spheres256" else W.spheres512()
+    steps = 8 if name == "spheres256" else 4
+    init = _random_init(wl, 11)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    try:
+        s.set_fields(init)
+        s.step(steps)
+        probes = s.read_probes(0, steps)
+        prob = oracle.Problem.from_workload(wl)
+        ref = init.copy()
+        ref_probes = prob.run_f32(ref, 0, steps)
+        for c in range(6):
+            _check(s.read_field(c), ref[c], f"{name} component {c}")
+        _check(probes, ref_probes, f"{name} probes")
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("fmt", [W.FP16, W.BF16])
+@pytest.mark.parametrize("grid", ["512", "1024x512x256"])
+def test_fullsize_reduced_storage_bitexact_with_emulation(fmt, grid):
+    wl = W.precision512(fmt, n_steps=4) if grid == "512" else W.precision1024(fmt, n_steps=4)
+    init = _random_init(wl, 12)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    try:
+        s.set_fields(init)
+        s.step(4)
+        prob = oracle.Problem.from_workload(wl)
+        ref = init.copy()
+        st = prob.quantize_upload(ref, fmt)
+        prob.run_q(ref, 0, 4, fmt, 4, st)
+        scales, sat = s.storage_state()
+        assert scales == list(st["scales"]) and not sat
+        for c in range(6):
+            _check(s.read_field(c), ref[c], f"{grid} fmt {fmt} component {c}")
+    finally:
+        s.close()
+
+
+def test_fullsize_1000_steps_fused_equals_plain():
+    """The benchmarked run (256^3, 1000 steps, T=4) against the plain
+    two-pass kernel: identical fields and probe traces."""
+    wl = W.spheres256()
+    outs = []
+    for kernel, T in ((fdtd.KERNEL_FUSED, 4), (fdtd.KERNEL_PLAIN, 1)):
+        s = fdtd.Solver.from_workload(wl, kernel=kernel, time_block=T)
+        try:
+            s.step(wl.n_steps)
+            outs.append((s.read_fields(), s.read_probes(0, wl.n_steps)))
+        finally:
+            s.close()
+    (f1, p1), (f2, p2) = outs
+    _check(f1, f2, "fields")
+    _check(p1, p2, "probes")
+    assert np.max(np.abs(f1[0:3])) > 1e-3
+    # the last probe row equals the final fields at the probe positions
+    for q, (c, i, j, k) in enumerate(wl.probes):
+        assert p1[-1, q] == float(f1[c, k, j, i])
