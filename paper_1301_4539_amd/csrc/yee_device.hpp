@@ -4,70 +4,94 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "yee_internal.hpp"
 
 namespace yee {
 
 // ---- storage codecs --------------------------------------------------------
 // A stored value q of component c represents q * 2^-s_c.  Encoding rounds
-// x * 2^s_c to nearest-even; a result beyond the largest finite value
-// saturates to +-max and raises the flag, a NaN raises the flag.
-// enc_max tracks the largest encoded magnitude (bits), excluding NaN.
+// y = x * 2^s_c to nearest-even after clamping y to +-(largest finite value):
+// for every finite y this equals rounding and then saturating what would
+// overflow.  Stores track the largest |y| (as bits; NaN compares above every
+// number); finish() turns it into the largest stored magnitude (rounding is
+// monotone, so max |Q(y)| = Q(max |y|)) and the saturation flag (|y| at or
+// above the first value that would round beyond the largest finite one, or
+// NaN).
 
 struct CodecF32 {
     using T = float;
     static constexpr bool scaled = false;
     __device__ static inline float load(const float *p, float) { return *p; }
-    __device__ static inline void store(float *p, float v, float, uint32_t &, uint32_t &) { *p = v; }
-    __device__ static inline float decode_mag(uint32_t, float) { return 0.0f; }
+    __device__ static inline void store(float *p, float v, float, uint32_t &) { *p = v; }
 };
 
 struct CodecF16 {
     using T = uint16_t;
     static constexpr bool scaled = true;
+    static constexpr float kMax = 65504.0f;        // largest finite binary16
+    static constexpr float kOver = 65520.0f;       // rounds to infinity from here on
     __device__ static inline float load(const uint16_t *p, float down)
     {
         return (float)__builtin_bit_cast(_Float16, *p) * down;
     }
-    __device__ static inline void store(uint16_t *p, float v, float up, uint32_t &mx, uint32_t &flag)
+    __device__ static inline uint16_t encode(float y)
     {
-        uint16_t h = __builtin_bit_cast(uint16_t, (_Float16)(v * up));
-        uint32_t a = h & 0x7fffu;
-        if (a == 0x7c00u) { h = (uint16_t)((h & 0x8000u) | 0x7bffu); a = 0x7bffu; flag = 1u; }
-        if (a > 0x7c00u) flag = 1u;
-        else mx = a > mx ? a : mx;
-        *p = h;
+        return __builtin_bit_cast(uint16_t, (_Float16)__builtin_amdgcn_fmed3f(y, -kMax, kMax));
     }
-    __device__ static inline float decode_mag(uint32_t a, float down)
+    __device__ static inline void store(uint16_t *p, float v, float up, uint32_t &mx)
     {
-        return (float)__builtin_bit_cast(_Float16, (uint16_t)a) * down;
+        const float y = v * up;
+        const uint32_t a = __builtin_bit_cast(uint32_t, y) & 0x7fffffffu;
+        mx = a > mx ? a : mx;
+        *p = encode(y);
+    }
+    __device__ static inline float stored_mag(float ymax)
+    {
+        return (float)__builtin_bit_cast(_Float16, encode(ymax));
     }
 };
 
 struct CodecBF16 {
     using T = uint16_t;
     static constexpr bool scaled = true;
+    static constexpr uint32_t kMaxBits = 0x7f7f0000u;   // largest finite bfloat16
+    static constexpr uint32_t kOverBits = 0x7f7f8000u;  // rounds to infinity from here on
     __device__ static inline float load(const uint16_t *p, float down)
     {
         return __builtin_bit_cast(float, (uint32_t)(*p) << 16) * down;
     }
-    __device__ static inline void store(uint16_t *p, float v, float up, uint32_t &mx, uint32_t &flag)
+    __device__ static inline uint16_t encode(float y)
     {
-        uint32_t u = __builtin_bit_cast(uint32_t, v * up);
-        uint16_t h;
-        if ((u & 0x7fffffffu) > 0x7f800000u) h = (uint16_t)((u >> 16) | 0x40u);
-        else h = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-        uint32_t a = h & 0x7fffu;
-        if (a == 0x7f80u) { h = (uint16_t)((h & 0x8000u) | 0x7f7fu); a = 0x7f7fu; flag = 1u; }
-        if (a > 0x7f80u) flag = 1u;
-        else mx = a > mx ? a : mx;
-        *p = h;
+        const float m = __builtin_bit_cast(float, kMaxBits);
+        const uint32_t u = __builtin_bit_cast(uint32_t, __builtin_amdgcn_fmed3f(y, -m, m));
+        return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
     }
-    __device__ static inline float decode_mag(uint32_t a, float down)
+    __device__ static inline void store(uint16_t *p, float v, float up, uint32_t &mx)
     {
-        return __builtin_bit_cast(float, a << 16) * down;
+        const float y = v * up;
+        const uint32_t a = __builtin_bit_cast(uint32_t, y) & 0x7fffffffu;
+        mx = a > mx ? a : mx;
+        *p = encode(y);
+    }
+    __device__ static inline float stored_mag(float ymax)
+    {
+        return __builtin_bit_cast(float, (uint32_t)encode(ymax) << 16);
     }
 };
+
+// Largest stored magnitude (times 2^-s via `down`) and saturation flag from
+// the largest |y| bits a thread saw.
+template <class Codec>
+__device__ inline void finish_max(uint32_t ybits, float down, float *m, bool *flag)
+{
+    if (ybits > 0x7f800000u) { *flag = true; *m = 0.0f; return; }         // NaN
+    const float ymax = __builtin_bit_cast(float, ybits);
+    if constexpr (std::is_same<Codec, CodecF16>::value) *flag = ymax >= CodecF16::kOver;
+    else *flag = ybits >= CodecBF16::kOverBits;
+    *m = Codec::stored_mag(ymax) * down;
+}
 
 // ---- scale rule --------------------------------------------------------------
 // s = 10 - ceil(log2 m), clamped to [-64, 64]; m = max(M_c, A), or the

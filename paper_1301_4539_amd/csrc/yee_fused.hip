@@ -49,8 +49,7 @@ template <> struct Buf<CodecF32> {
     {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
     }
-    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float, uint32_t &,
-                                        uint32_t &)
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float, uint32_t &)
     {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
     }
@@ -61,11 +60,10 @@ template <class Codec> struct Buf16 {
         const uint16_t q = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
         return Codec::load(&q, down);
     }
-    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float up, uint32_t &mx,
-                                        uint32_t &flag)
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float up, uint32_t &mx)
     {
         uint16_t q;
-        Codec::store(&q, v, up, mx, flag);
+        Codec::store(&q, v, up, mx);
         __builtin_amdgcn_raw_buffer_store_b16(q, r, vo, so, 0);
     }
 };
@@ -224,13 +222,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
 
     YEE_LOAD_PLANE(kb);
 
-    uint32_t mx[6] = {0u, 0u, 0u, 0u, 0u, 0u};
-    uint32_t flag = 0u;
+    uint32_t mx[6] = {0u, 0u, 0u, 0u, 0u, 0u};   // largest |value * 2^s| seen, as bits
 
     // One z step of the pipeline.  ALL: every time level is active and the
     // next plane is loaded (steady state), so no per-level branches remain.
-    auto iterate = [&](const int K, auto all_c) __attribute__((always_inline)) {
+    // INNER: every lane and row of the tile lies strictly inside the grid in
+    // x and y (no wall in reach), so only the plane tests remain in the masks.
+    auto iterate = [&](const int K, auto all_c, auto inner_c) __attribute__((always_inline)) {
         constexpr bool ALL = decltype(all_c)::value;
+        constexpr bool INNER = decltype(inner_c)::value;
         // Level 0 takes plane K; plane K-1 of level 0 becomes level 1's input.
         float Eo[3][RY], Ho[3][RY];
         int Mo[RY];
@@ -277,9 +277,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     const float dex_y = exu - Eo[0][r];
                     const float dey_x = eyr - Eo[1][r];
                     const float hz = __builtin_fmaf(-a.chx, dey_x, __builtin_fmaf(a.chy, dex_y, Ho[2][r]));
-                    Hn[0][r] = (xin && yin && y < ny && plt) ? hx : Ho[0][r];
-                    Hn[1][r] = (xlt && yin && plt) ? hy : Ho[1][r];
-                    Hn[2][r] = (xlt && y >= 0 && y < ny) ? hz : Ho[2][r];
+                    if constexpr (INNER) {
+                        Hn[0][r] = plt ? hx : Ho[0][r];
+                        Hn[1][r] = plt ? hy : Ho[1][r];
+                        Hn[2][r] = hz;
+                    } else {
+                        Hn[0][r] = (xin && yin && y < ny && plt) ? hx : Ho[0][r];
+                        Hn[1][r] = (xlt && yin && plt) ? hy : Ho[1][r];
+                        Hn[2][r] = (xlt && y >= 0 && y < ny) ? hz : Ho[2][r];
+                    }
                 }
                 // ---- Ampere: E^(t) at plane p from H^(t) at p and p-1 ----
                 if constexpr (NW > 1) {
@@ -306,9 +312,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     const float dhy_x = Hn[1][r] - hyl;
                     const float dhx_y = Hn[0][r] - hxd;
                     const float ez = __builtin_fmaf(-cf.z, dhx_y, __builtin_fmaf(cf.y, dhy_x, cf.x * Eo[2][r]));
-                    En[0][r] = (xlt && yint && pint) ? ex : Eo[0][r];
-                    En[1][r] = (xint && y >= 0 && y < ny && pint) ? ey : Eo[1][r];
-                    En[2][r] = (xint && yint && plt) ? ez : Eo[2][r];
+                    if constexpr (INNER) {
+                        En[0][r] = pint ? ex : Eo[0][r];
+                        En[1][r] = pint ? ey : Eo[1][r];
+                        En[2][r] = plt ? ez : Eo[2][r];
+                    } else {
+                        En[0][r] = (xlt && yint && pint) ? ex : Eo[0][r];
+                        En[1][r] = (xint && y >= 0 && y < ny && pint) ? ey : Eo[1][r];
+                        En[2][r] = (xint && yint && plt) ? ez : Eo[2][r];
+                    }
                 }
                 // ---- soft sources of step step0+t-1, on every tile computing the edge ----
                 const long long n = a.step0 + (t - 1);
@@ -384,8 +396,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     if (xown) {
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            B::store(rout, vo, so + c * (int)cs * ES, E[T][c][r], up[c], mx[c], flag);
-                            B::store(rout, vo, so + (3 + c) * (int)cs * ES, H[T][c][r], up[3 + c], mx[3 + c], flag);
+                            B::store(rout, vo, so + c * (int)cs * ES, E[T][c][r], up[c], mx[c]);
+                            B::store(rout, vo, so + (3 + c) * (int)cs * ES, H[T][c][r], up[3 + c], mx[3 + c]);
                         }
                     }
                 }
@@ -394,22 +406,34 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     };
 
     // warm-up (upper levels still empty), steady state, drain (lower levels done)
-    int K = kb;
-    const int kw = min(kb + T, ke);
-    for (; K < kw; ++K) iterate(K, std::false_type{});
-    for (; K < ke; ++K) iterate(K, std::true_type{});
-    for (; K <= ke + T; ++K) iterate(K, std::false_type{});
+    auto march = [&](auto inner_c) __attribute__((always_inline)) {
+        int K = kb;
+        const int kw = min(kb + T, ke);
+        for (; K < kw; ++K) iterate(K, std::false_type{}, inner_c);
+        for (; K < ke; ++K) iterate(K, std::true_type{}, inner_c);
+        for (; K <= ke + T; ++K) iterate(K, std::false_type{}, inner_c);
+    };
+    const bool inner = xl >= 1 && xl + 63 <= nx - 1 && yt >= 1 && yt + NR - 1 <= ny - 1;
+    if (inner) march(std::true_type{});
+    else march(std::false_type{});
 #undef YEE_LOAD_PLANE
 
     if constexpr (Codec::scaled) {
         // largest stored magnitude per component and the saturation flag
+        bool any = false;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            float m = Codec::decode_mag(mx[c], 1.0f / up[c]);
-            for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+            uint32_t b = mx[c];
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t ob = __shfl_xor(b, o, 64);
+                b = ob > b ? ob : b;
+            }
+            float m;
+            bool fl;
+            finish_max<Codec>(b, 1.0f / up[c], &m, &fl);
+            any = any || fl;
             if (lane == 0 && m > 0.0f) atomicMax(&a.sb.ctrl->maxbits[a.sb.slot_out][c], __float_as_uint(m));
         }
-        const unsigned long long any = __ballot(flag != 0u);
         if (lane == 0 && any) atomicOr(&a.sb.ctrl->flag, 1u);
     }
     __syncthreads();   // LDS is reused by the next tile of a batched launch
