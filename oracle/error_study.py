@@ -47,6 +47,29 @@ def study(n=48, steps=2000, every=250, spheres=12, fmts=(1, 2), Ts=(1, 2, 4), se
     return out
 
 
+def study_workload(name, steps=2000, every=250, fmts=(1, 2), T=4, log=print):
+    """FP64 reference and the reduced-storage emulations of one named
+    configuration, advanced side by side (no snapshots kept)."""
+    sys.path.insert(0, __file__.rsplit("/oracle/", 1)[0])
+    from paper_1301_4539_amd import workload as W
+    wl = {"precision512": W.precision512, "precision1024": W.precision1024}[name](W.FP16, n_steps=steps)
+    prob = Problem.from_workload(wl)
+    f64 = zero_fields(wl.nx, wl.ny, wl.nz)
+    runs = []
+    for fmt in fmts:
+        f = zero_fields(wl.nx, wl.ny, wl.nz, np.float32)
+        runs.append((fmt, f, prob.quantize_upload(f, fmt)))
+    out = {"workload": name, "grid": [wl.nx, wl.ny, wl.nz], "T": T, "steps": steps, "rel_l2": {}}
+    for s in range(0, steps, every):
+        prob.run_f64(f64, s, every)
+        for fmt, f, st in runs:
+            prob.run_q(f, s, every, fmt, T, st)
+            key = f"{'fp16' if fmt == 1 else 'bf16'}/T{T}"
+            out["rel_l2"].setdefault(key, []).append(W.rel_l2(f, f64))
+        log(f"{name} step {s + every}: " + " ".join(f"{k} {v[-1]:.3e}" for k, v in out["rel_l2"].items()))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=48)
@@ -56,8 +79,14 @@ def main():
     ap.add_argument("--T", default="1,2,4")
     ap.add_argument("--lossless", action="store_true")
     ap.add_argument("--json", default=None)
+    ap.add_argument("--workload", default=None, choices=["precision512", "precision1024"])
     a = ap.parse_args()
-    r = study(a.n, a.steps, a.every, a.spheres, Ts=tuple(int(t) for t in a.T.split(",")), lossless=a.lossless)
+    if a.workload:
+        r = study_workload(a.workload, a.steps, a.every, T=int(a.T.split(",")[-1]),
+                           log=lambda m: print(m, flush=True))
+    else:
+        r = study(a.n, a.steps, a.every, a.spheres, Ts=tuple(int(t) for t in a.T.split(",")),
+                  lossless=a.lossless)
     if a.json:
         with open(a.json, "w") as fh:
             json.dump(r, fh, indent=1)

@@ -24,7 +24,6 @@ struct CodecF32 {
     using T = float;
     static constexpr bool scaled = false;
     __device__ static inline float load(const float *p, float) { return *p; }
-    __device__ static inline void store(float *p, float v, float, uint32_t &) { *p = v; }
 };
 
 struct CodecF16 {
@@ -40,12 +39,13 @@ struct CodecF16 {
     {
         return __builtin_bit_cast(uint16_t, (_Float16)__builtin_amdgcn_fmed3f(y, -kMax, kMax));
     }
-    __device__ static inline void store(uint16_t *p, float v, float up, uint32_t &mx)
+    // Encode v * 2^s; fold |v * 2^s| into mx when `track` (owned values only).
+    __device__ static inline uint16_t encode_tracked(float v, float up, uint32_t &mx, bool track)
     {
         const float y = v * up;
         const uint32_t a = __builtin_bit_cast(uint32_t, y) & 0x7fffffffu;
-        mx = a > mx ? a : mx;
-        *p = encode(y);
+        mx = (track && a > mx) ? a : mx;
+        return encode(y);
     }
     __device__ static inline float stored_mag(float ymax)
     {
@@ -68,12 +68,13 @@ struct CodecBF16 {
         const uint32_t u = __builtin_bit_cast(uint32_t, __builtin_amdgcn_fmed3f(y, -m, m));
         return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
     }
-    __device__ static inline void store(uint16_t *p, float v, float up, uint32_t &mx)
+    // Encode v * 2^s; fold |v * 2^s| into mx when `track` (owned values only).
+    __device__ static inline uint16_t encode_tracked(float v, float up, uint32_t &mx, bool track)
     {
         const float y = v * up;
         const uint32_t a = __builtin_bit_cast(uint32_t, y) & 0x7fffffffu;
-        mx = a > mx ? a : mx;
-        *p = encode(y);
+        mx = (track && a > mx) ? a : mx;
+        return encode(y);
     }
     __device__ static inline float stored_mag(float ymax)
     {
@@ -118,17 +119,18 @@ __device__ inline void choose_scales(const float *mprev, float a_max, int *s)
 }
 
 // ---- cross-lane moves (wave64) ---------------------------------------------
-// DPP wave shifts: one VALU op, no LDS traffic.  Lanes with no source lane
-// (lane 63 for from_right, lane 0 for from_left) get 0; they are halo lanes.
+// DPP wave shifts: one VALU op (often folded into the subtraction that uses
+// it), no LDS traffic.  Lanes with no source lane (lane 63 for from_right,
+// lane 0 for from_left) read 0 (bound_ctrl); they are halo lanes.
 // Value held by lane+1 (wave_shl:1).
 __device__ inline float from_right(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
 // Value held by lane-1 (wave_shr:1).
 __device__ inline float from_left(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
 }
 
 }  // namespace yee

@@ -1,0 +1,617 @@
+// Fused, temporally blocked Yee kernel: one pass over HBM advances T steps.
+//
+// This is the GPU form of the cache-reuse ideas of Sec. 3: Ampere and
+// Faraday interleaved per sub-domain (Sec. 3.2), plane by plane along z
+// (Sec. 3.3), several time steps gathered per pass (Sec. 3.4, generalised
+// to T steps as the conclusion suggests).  On a GPU the "cache" is the
+// register file: a workgroup owns an x-y tile, marches z, and keeps T+1 time
+// levels of the six fields in registers; level t runs one plane behind level
+// t-1.  Overlapped tiles (a halo of T cells on every side in x and y, T
+// planes at both ends of a z chunk) replace the paper's surface routines:
+// halo cells are recomputed redundantly instead of being exchanged, so each
+// owned value depends only on data this workgroup computed itself, in the
+// same operation order as the plain kernel -- results are bit-identical for
+// every T and tile shape.
+//
+// Thread layout: lane = x (64 consecutive points, coalesced), each lane holds
+// RY consecutive rows in y, NW waves stack in y.  x neighbours move between
+// lanes with DPP wave shifts; the y neighbour across a wave boundary goes
+// through a small LDS slot.  Fields are read from buffer fin and the advanced
+// state is written to buffer fout (ping-pong): an in-place update would race
+// with neighbouring tiles still reading the old time level.
+//
+// Addressing: every array is read through a buffer resource based at the
+// chunk's first plane; the per-lane x offset lives in one VGPR and the plane
+// and row offsets are scalar, so a load costs one instruction.  Halo lanes
+// and rows outside the grid read clamped (in-grid) addresses: their values
+// only ever feed other halo values, never an owned output.
+
+#pragma once
+
+#include <algorithm>
+#include <type_traits>
+
+#include "yee_device.hpp"
+#include "yee_internal.hpp"
+
+namespace yee {
+
+namespace {
+
+constexpr int BUF_FLAGS = 0x00020000;   // raw (untyped) dword buffer, gfx9 word 3
+
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void *base, long long bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, BUF_FLAGS);
+}
+
+template <class Codec> struct Buf;
+template <> struct Buf<CodecF32> {
+    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, int vo, int so, float)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float, uint32_t &, bool)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+    }
+};
+template <class Codec> struct Buf16 {
+    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, int vo, int so, float down)
+    {
+        const uint16_t q = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+        return Codec::load(&q, down);
+    }
+    __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float up, uint32_t &mx,
+                                        bool own)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(Codec::encode_tracked(v, up, mx, own), r, vo, so, 0);
+    }
+};
+template <> struct Buf<CodecF16> : Buf16<CodecF16> {};
+template <> struct Buf<CodecBF16> : Buf16<CodecBF16> {};
+
+constexpr int MAX_LOCAL = 256;   // sources / probes per solver
+
+template <int T, int NW>
+struct TileShared {
+    float4 coef[256];
+    // (Ex, Ez) of each wave's first row, per time level 0..T-1, double-buffered
+    // by the parity of the z step that wrote it; slot NW stays zero
+    float2 e[2][T][NW + 1][64];
+    // (Hx, Hz) of each wave's last row, in slot w+1, double-buffered by level;
+    // slot 0 stays zero
+    float2 h[2][NW + 1][64];
+    int4 src[MAX_LOCAL];     // sources this workgroup computes: (comp, lane, row, plane)
+    int srcn[MAX_LOCAL];     // how many of this launch's T steps have a sample
+    float srcv[MAX_LOCAL][T];  // those samples, staged so the z march issues no
+                               // global loads besides the plane prefetch
+    int4 prb[MAX_LOCAL];     // probes this workgroup owns: (comp, lane, row, plane)
+    int prbid[MAX_LOCAL];
+    int nsrc, nprb;
+};
+
+// One tile (x-y tile x z chunk) of one solve: T steps of the owned region.
+// `logical` is the tile index within the solve.  Starts and ends with every
+// thread of the workgroup in step, so a workgroup may run several tiles in a
+// row (the batched kernel does).
+template <int T, int RY, int NW, class Codec>
+__device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical, TileShared<T, NW> &sm)
+{
+    constexpr int OX = 64 - 2 * T;      // owned points per tile in x
+    constexpr int NR = NW * RY;         // rows per tile
+    constexpr int OY = NR - 2 * T;      // owned rows per tile
+    using S = typename Codec::T;
+    using B = Buf<Codec>;
+    constexpr int ES = sizeof(S);
+    float4 *const s_coef = sm.coef;
+    auto &s_e = sm.e;
+    auto &s_h = sm.h;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int q = tid; q < a.n_mat; q += 64 * NW) s_coef[q] = a.coef[q];
+    if (tid < 64) {
+        for (int b = 0; b < 2; ++b) {
+            for (int t = 0; t < T; ++t) s_e[b][t][NW][tid] = make_float2(0.0f, 0.0f);
+            s_h[b][0][tid] = make_float2(0.0f, 0.0f);
+        }
+    }
+
+    float dn[6], up[6];
+    if constexpr (Codec::scaled) {
+        float mprev[6];
+        int s_in[6], s_out[6];
+        for (int c = 0; c < 6; ++c) {
+            mprev[c] = __uint_as_float(a.sb.ctrl->maxbits[a.sb.slot_in][c]);
+            s_in[c] = a.sb.ctrl->scale[a.sb.par][c];
+        }
+        choose_scales(mprev, a.sb.a_max, s_out);
+        for (int c = 0; c < 6; ++c) {   // uniform: keep them in scalar registers
+            dn[c] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                        __builtin_bit_cast(int, ldexpf(1.0f, -s_in[c]))));
+            up[c] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                        __builtin_bit_cast(int, ldexpf(1.0f, s_out[c]))));
+        }
+        if (logical == 0 && tid < 6) {
+            a.sb.ctrl->scale[a.sb.par ^ 1][tid] = s_out[tid];
+            a.sb.ctrl->maxbits[a.sb.slot_clear][tid] = 0u;
+        }
+    } else {
+        for (int c = 0; c < 6; ++c) dn[c] = up[c] = 1.0f;
+    }
+
+    const Layout L = a.L;
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int tx = logical % a.ntx;
+    const int rem = logical / a.ntx;
+    const int ty = rem % a.nty, tz = rem / a.nty;
+    const int x0 = tx * OX, y0 = ty * OY, z0 = tz * a.zc;
+    const int z1 = min(z0 + a.zc, nz + 1);
+    const int xl = x0 - T;              // x of lane 0
+    const int x = xl + lane;
+    const int yt = y0 - T;              // y of the tile's first row
+    const int yw = yt + w * RY;         // y of this wave's first row
+    const int kb = max(0, z0 - T);      // first plane the pipeline loads
+    const int ke = min(nz, z1 - 1 + T); // last plane the pipeline loads
+
+    // sources on points this tile computes, probes on points it owns
+    if (tid == 0) {
+        int ns = 0, np = 0;
+        for (int q = 0; q < a.src.n; ++q) {
+            const int4 d = a.src.pos[q];
+            const int lx = d.y - xl, ry = d.z - yt;
+            if (lx >= 0 && lx < 64 && ry >= 0 && ry < NR && d.w >= kb && d.w <= ke && ns < MAX_LOCAL) {
+                sm.src[ns] = make_int4(d.x, lx, ry, d.w);
+                const int2 wv = a.src.wave[q];     // (sample offset, n_samples)
+                const long long left = (long long)wv.y - a.step0;
+                const int nv = left < 0 ? 0 : (left > T ? T : (int)left);
+                sm.srcn[ns] = nv;
+                for (int t = 0; t < nv; ++t) sm.srcv[ns][t] = a.src.samples[wv.x + a.step0 + t];
+                ++ns;
+            }
+        }
+        for (int q = 0; q < a.probe.n; ++q) {
+            const int4 d = a.probe.pos[q];
+            const int lx = d.y - xl, ry = d.z - yt;
+            if (lx >= T && lx < T + OX && ry >= T && ry < T + OY && d.w >= z0 && d.w < z1 && np < MAX_LOCAL) {
+                sm.prb[np] = make_int4(d.x, lx, ry, d.w);
+                sm.prbid[np] = q;
+                ++np;
+            }
+        }
+        sm.nsrc = ns;
+        sm.nprb = np;
+    }
+    __syncthreads();
+    const int nsrc = sm.nsrc, nprb = sm.nprb;
+
+    // lane and row predicates
+    const bool xin = x >= 0 && x <= nx;
+    const bool xlt = x >= 0 && x < nx;
+    const bool xint = x > 0 && x < nx;
+    const bool xown = lane >= T && lane < T + OX && x <= nx;
+    const int xc = min(max(x, 0), nx);
+    const int vo = xc * ES;             // per-lane byte offset of the field arrays
+    const int vom = xc;                 // per-lane byte offset of the material index
+
+    // buffer resources based at this chunk's first plane
+    const long long cs = L.cstride, ks = L.kstride;
+    const __amdgpu_buffer_rsrc_t rin = rsrc(static_cast<const S *>(a.fin) + (long long)kb * ks,
+                                            (long long)(ke - kb + 1) * ks * ES);
+    const __amdgpu_buffer_rsrc_t rout = rsrc(static_cast<S *>(a.fout) + (long long)kb * ks,
+                                             (long long)(ke - kb + 1) * ks * ES);
+    const __amdgpu_buffer_rsrc_t rmat = rsrc(a.mat + (long long)kb * L.plane, (long long)(ke - kb + 1) * L.plane);
+    int rowoff[RY];                     // clamped row offsets (elements), uniform per wave
+#pragma unroll
+    for (int r = 0; r < RY; ++r) rowoff[r] = min(max(yw + r, 0), ny) * L.pitch;
+
+    float E[T + 1][3][RY], H[T + 1][3][RY];
+    // Material indices of the planes the levels are on, one byte per level:
+    // byte t of MP[r] is the index of plane K-t (level t's plane) in row r.
+    using MPack = typename std::conditional<(T >= 4), uint64_t, uint32_t>::type;
+    MPack MP[RY];
+#pragma unroll
+    for (int t = 0; t <= T; ++t)
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            if (t == 0) MP[r] = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) E[t][c][r] = H[t][c][r] = 0.0f;
+        }
+
+    // prefetched next level-0 plane
+    float PE[3][RY], PH[3][RY];
+    uint32_t PM[RY];
+
+#define YEE_LOAD_PLANE(KK)                                                                  \
+    do {                                                                                    \
+        const int pofs_ = ((KK) - kb) * (int)ks;                                            \
+        const int mofs_ = ((KK) - kb) * (int)L.plane;                                       \
+        _Pragma("unroll") for (int r = 0; r < RY; ++r) {                                    \
+            const int so_ = pofs_ + rowoff[r];                                              \
+            _Pragma("unroll") for (int c = 0; c < 3; ++c) {                                 \
+                PE[c][r] = B::load(rin, vo, (so_ + c * (int)cs) * ES, dn[c]);               \
+                PH[c][r] = B::load(rin, vo, (so_ + (3 + c) * (int)cs) * ES, dn[3 + c]);     \
+            }                                                                               \
+            PM[r] = __builtin_amdgcn_raw_buffer_load_b8(rmat, vom, mofs_ + rowoff[r], 0);   \
+        }                                                                                   \
+    } while (0)
+
+    YEE_LOAD_PLANE(kb);
+
+    uint32_t mx[6] = {0u, 0u, 0u, 0u, 0u, 0u};   // largest |value * 2^s| seen, as bits
+
+    // Store the owned part of level T, which holds plane q.  Every lane and row
+    // issues its stores, without branches: a value this tile does not own gets
+    // an offset 2^31 beyond its address, which the buffer range check drops.
+    // (Loads and stores share one completion counter; stores inside branches
+    // make the compiler's wait for the next plane's loads also wait for them.)
+    auto store_plane = [&](const int q) __attribute__((always_inline)) {
+        const int pofs = (q - kb) * (int)ks;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int row = w * RY + r;
+            const int y = yw + r;
+            const bool own = xown && row >= T && row < T + OY && y <= ny;
+            const int vs = own ? vo : (int)((uint32_t)vo | 0x80000000u);
+            const int so = (pofs + rowoff[r]) * ES;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                B::store(rout, vs, so + c * (int)cs * ES, E[T][c][r], up[c], mx[c], own);
+                B::store(rout, vs, so + (3 + c) * (int)cs * ES, H[T][c][r], up[3 + c], mx[3 + c], own);
+            }
+        }
+    };
+
+    // One z step of the pipeline.  ALL: every time level is active, the next
+    // plane is loaded and an owned plane is stored (steady state), so no
+    // per-level branches remain.
+    // INNER: every lane and row of the tile lies strictly inside the grid in
+    // x and y (no wall in reach), so only the plane tests remain in the masks.
+    auto iterate = [&](const int K, auto all_c, auto inner_c) __attribute__((always_inline)) {
+        constexpr bool ALL = decltype(all_c)::value;
+        constexpr bool INNER = decltype(inner_c)::value;
+        // Level 0 takes plane K; plane K-1 of level 0 becomes level 1's input.
+        float Eo[3][RY], Ho[3][RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            MP[r] = (MP[r] << 8) | (MPack)PM[r];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Eo[c][r] = E[0][c][r];
+                Ho[c][r] = H[0][c][r];
+                E[0][c][r] = PE[c][r];
+                H[0][c][r] = PH[c][r];
+            }
+        }
+        if (ALL || K + 1 <= ke) YEE_LOAD_PLANE(K + 1);
+        // The first row of this plane is the row above for wave w-1 at level 1
+        // in the next z step.
+        const int wb = K & 1, rb = wb ^ 1;   // exchange buffer written / read this step
+        if constexpr (NW > 1) s_e[wb][0][w][lane] = make_float2(E[0][0][0], E[0][2][0]);
+
+#pragma unroll
+        for (int t = 1; t <= T; ++t) {
+            const int p = K - t;                      // plane of time level t
+            // Level t is computed on planes [lo, hi]: its dependency cone.  Its
+            // values are exact on [kb+t, ke-t] (walls aside), and level t+1 needs
+            // one plane below that for its own first exact plane.
+            const int lo = kb > 0 ? kb + t - 1 : 0;
+            const int hi = ke < nz ? ke - t : nz;
+            if (ALL || (p >= lo && p <= hi)) {        // uniform over the workgroup
+                // steady steps keep every level off the z walls (0 < p < nz)
+                const bool plt = ALL || p < nz, pint = ALL || (p > 0 && p < nz);
+                // ---- Faraday: H^(t) at plane p from E^(t-1) at p and p+1 ----
+                // E^(t-1) at plane p was computed in the previous z step, so the
+                // row above comes from the other exchange buffer without a barrier.
+                const float2 eup = NW > 1 ? s_e[rb][t - 1][w + 1][lane] : make_float2(0.0f, 0.0f);
+                float Hn[3][RY];
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const int y = yw + r;
+                    const bool yin = y >= 0 && y <= ny;
+                    const float exu = r + 1 < RY ? Eo[0][(r + 1) % RY] : eup.x;
+                    const float ezu = r + 1 < RY ? Eo[2][(r + 1) % RY] : eup.y;
+                    const float ezr = from_right(Eo[2][r]);
+                    const float eyr = from_right(Eo[1][r]);
+                    const float dey_z = E[t - 1][1][r] - Eo[1][r];
+                    const float dez_y = ezu - Eo[2][r];
+                    const float hx = __builtin_fmaf(-a.chy, dez_y, __builtin_fmaf(a.chz, dey_z, Ho[0][r]));
+                    const float dez_x = ezr - Eo[2][r];
+                    const float dex_z = E[t - 1][0][r] - Eo[0][r];
+                    const float hy = __builtin_fmaf(-a.chz, dex_z, __builtin_fmaf(a.chx, dez_x, Ho[1][r]));
+                    const float dex_y = exu - Eo[0][r];
+                    const float dey_x = eyr - Eo[1][r];
+                    const float hz = __builtin_fmaf(-a.chx, dey_x, __builtin_fmaf(a.chy, dex_y, Ho[2][r]));
+                    if constexpr (INNER) {
+                        Hn[0][r] = plt ? hx : Ho[0][r];
+                        Hn[1][r] = plt ? hy : Ho[1][r];
+                        Hn[2][r] = hz;
+                    } else {
+                        Hn[0][r] = (xin && yin && y < ny && plt) ? hx : Ho[0][r];
+                        Hn[1][r] = (xlt && yin && plt) ? hy : Ho[1][r];
+                        Hn[2][r] = (xlt && y >= 0 && y < ny) ? hz : Ho[2][r];
+                    }
+                }
+                // ---- Ampere: E^(t) at plane p from H^(t) at p and p-1 ----
+                // Consecutive levels alternate buffers (also across z steps), so
+                // one barrier per level orders both the write and the reuse.
+                const int hb = (T & 1) ? ((K + t) & 1) : (t & 1);
+                if constexpr (NW > 1) {
+                    s_h[hb][w + 1][lane] = make_float2(Hn[0][RY - 1], Hn[2][RY - 1]);
+                    __syncthreads();
+                }
+                const float2 hdn = NW > 1 ? s_h[hb][w][lane] : make_float2(0.0f, 0.0f);
+                float En[3][RY];
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const int y = yw + r;
+                    const bool yint = y > 0 && y < ny;
+                    const float hxd = r > 0 ? Hn[0][(r + RY - 1) % RY] : hdn.x;
+                    const float hzd = r > 0 ? Hn[2][(r + RY - 1) % RY] : hdn.y;
+                    const float hzl = from_left(Hn[2][r]);
+                    const float hyl = from_left(Hn[1][r]);
+                    const float4 cf = s_coef[(uint32_t)(MP[r] >> (8 * t)) & 0xffu];
+                    const float dhz_y = Hn[2][r] - hzd;
+                    const float dhy_z = Hn[1][r] - H[t][1][r];
+                    const float ex = __builtin_fmaf(-cf.w, dhy_z, __builtin_fmaf(cf.z, dhz_y, cf.x * Eo[0][r]));
+                    const float dhx_z = Hn[0][r] - H[t][0][r];
+                    const float dhz_x = Hn[2][r] - hzl;
+                    const float ey = __builtin_fmaf(-cf.y, dhz_x, __builtin_fmaf(cf.w, dhx_z, cf.x * Eo[1][r]));
+                    const float dhy_x = Hn[1][r] - hyl;
+                    const float dhx_y = Hn[0][r] - hxd;
+                    const float ez = __builtin_fmaf(-cf.z, dhx_y, __builtin_fmaf(cf.y, dhy_x, cf.x * Eo[2][r]));
+                    if constexpr (INNER) {
+                        En[0][r] = pint ? ex : Eo[0][r];
+                        En[1][r] = pint ? ey : Eo[1][r];
+                        En[2][r] = plt ? ez : Eo[2][r];
+                    } else {
+                        En[0][r] = (xlt && yint && pint) ? ex : Eo[0][r];
+                        En[1][r] = (xint && y >= 0 && y < ny && pint) ? ey : Eo[1][r];
+                        En[2][r] = (xint && yint && plt) ? ez : Eo[2][r];
+                    }
+                }
+                // ---- soft sources of step step0+t-1, on every tile computing the edge ----
+                const long long n = a.step0 + (t - 1);
+                for (int q = 0; q < nsrc; ++q) {
+                    const int4 d = sm.src[q];
+                    if (d.w != p || t - 1 >= sm.srcn[q] || d.z / RY != w) continue;
+                    const float val = sm.srcv[q][t - 1];
+                    if (lane == d.y) {
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+                            if (r == d.z - w * RY) {
+                                if (d.x == 0) En[0][r] = En[0][r] + val;
+                                else if (d.x == 1) En[1][r] = En[1][r] + val;
+                                else En[2][r] = En[2][r] + val;
+                            }
+                    }
+                }
+                if constexpr (NW > 1) {
+                    if (t < T) s_e[wb][t < T ? t : 0][w][lane] = make_float2(En[0][0], En[2][0]);
+                }
+                // ---- probes, recorded by the owning tile only (planes outside
+                // [z0, z1) are this chunk's halo, where upper levels are incomplete) ----
+                for (int q = 0; q < nprb; ++q) {
+                    const int4 d = sm.prb[q];
+                    if (d.w != p || d.z / RY != w) continue;
+                    if (lane == d.y) {
+                        float v = 0.0f;
+#pragma unroll
+                        for (int r = 0; r < RY; ++r)
+                            if (r == d.z - w * RY) {
+                                v = d.x == 0 ? En[0][r] : d.x == 1 ? En[1][r] : d.x == 2 ? En[2][r]
+                                  : d.x == 3 ? Hn[0][r] : d.x == 4 ? Hn[1][r] : Hn[2][r];
+                            }
+                        a.probe.out[(n - a.probe.base) * a.probe.n + sm.prbid[q]] = (double)v;
+                    }
+                }
+                // ---- rotate: level t's previous plane becomes level t+1's input ----
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float et = E[t][c][r], ht = H[t][c][r];
+                        E[t][c][r] = En[c][r];
+                        H[t][c][r] = Hn[c][r];
+                        Eo[c][r] = et;
+                        Ho[c][r] = ht;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        Eo[c][r] = E[t][c][r];
+                        Ho[c][r] = H[t][c][r];
+                    }
+                }
+            }
+        }
+
+        // ---- store the owned part of level T (plane K-T) ----
+        if constexpr (ALL) store_plane(K - T);
+        else if (K - T >= z0 && K - T < z1) store_plane(K - T);
+        // With some levels idle, the per-level barriers no longer separate the
+        // exchange writes of this step from the reads of the next one.
+        if constexpr (!ALL && NW > 1) __syncthreads();
+    };
+
+    // warm-up (upper levels not yet in their cone), steady state (every level
+    // active, off the z walls, an owned plane to store and one to prefetch),
+    // drain
+    auto march = [&](auto inner_c) __attribute__((always_inline)) {
+        using F = std::false_type;
+        using Tr = std::true_type;
+        int K = kb;
+        const int kw = min(max(kb > 0 ? kb + 2 * T - 1 : T + 1, z0 + T), ke);
+        const int kend = ke < nz ? ke : nz + T;
+        for (; K < kw; ++K) iterate(K, F{}, inner_c);
+        // Drain every outstanding load and store once before the steady loop
+        // (s_waitcnt vmcnt(0)): the compiler's wait counts at the loop head
+        // then only account for the loop's own traffic.
+        __builtin_amdgcn_s_waitcnt(0x0f70);
+        for (; K < ke; ++K) iterate(K, Tr{}, inner_c);
+        for (; K <= kend; ++K) iterate(K, F{}, inner_c);
+    };
+    const bool inner = xl >= 1 && xl + 63 <= nx - 1 && yt >= 1 && yt + NR - 1 <= ny - 1;
+    if (inner) march(std::true_type{});
+    else march(std::false_type{});
+#undef YEE_LOAD_PLANE
+
+    if constexpr (Codec::scaled) {
+        // largest stored magnitude per component and the saturation flag
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            uint32_t b = mx[c];
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t ob = __shfl_xor(b, o, 64);
+                b = ob > b ? ob : b;
+            }
+            float m;
+            bool fl;
+            finish_max<Codec>(b, 1.0f / up[c], &m, &fl);
+            any = any || fl;
+            if (lane == 0 && m > 0.0f) atomicMax(&a.sb.ctrl->maxbits[a.sb.slot_out][c], __float_as_uint(m));
+        }
+        if (lane == 0 && any) atomicOr(&a.sb.ctrl->flag, 1u);
+    }
+    __syncthreads();   // LDS is reused by the next tile of a batched launch
+}
+
+template <int T, int RY, int NW, class Codec>
+__global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
+{
+    __shared__ TileShared<T, NW> sm;
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous run of tiles so that halo re-reads hit its own L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int logical = (b & 7) * (nb >> 3) + (b >> 3);
+    if (logical >= a.nwg) return;   // uniform per workgroup
+    fused_tile<T, RY, NW, Codec>(a, logical, sm);
+}
+
+// Several solves in one persistent launch: the workgroups stride over the
+// concatenated tile lists of up to MAX_BATCH solves (same storage format and
+// block length), so small grids that could not fill the GPU alone share it.
+template <int T, int RY, int NW, class Codec>
+__global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
+{
+    __shared__ TileShared<T, NW> sm;
+    const int total = a.start[a.n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        int i = 0;
+        while (i + 1 < a.n && item >= a.start[i + 1]) ++i;
+        fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], sm);
+    }
+}
+
+// ---- tilings ---------------------------------------------------------------
+// (RY rows per lane, NW waves) per time-block length; variant 0 is the default.
+struct Tiling { int ry, nw; };
+constexpr Tiling kTilings[5][3] = {
+    {},
+    {{4, 4}, {2, 8}, {2, 16}},    // T = 1
+    {{2, 16}, {4, 8}, {3, 12}},   // T = 2
+    {{2, 16}, {4, 8}, {3, 12}},   // T = 3
+    {{2, 16}, {4, 8}, {3, 12}},   // T = 4
+};
+
+int planes_fit(const Layout &L, int es)
+{
+    // a chunk's buffer resource spans (planes * kstride * es) bytes, below 2^31
+    long long p = ((1LL << 31) - 1) / ((long long)L.kstride * es);
+    return (int)std::min<long long>(p, 1 << 20);
+}
+
+void geometry_for(int T, int variant, int zc_req, int es, const Layout &L, int *ntx, int *nty, int *ntz, int *zc,
+                  int *threads)
+{
+    const Tiling tl = kTilings[T][variant];
+    const int OX = 64 - 2 * T, OY = tl.nw * tl.ry - 2 * T;
+    *ntx = (L.nx + 1 + OX - 1) / OX;
+    *nty = (L.ny + 1 + OY - 1) / OY;
+    int z = zc_req;
+    if (z <= 0) {
+        // chunks of ~64 planes, fewer when that leaves the GPU short of workgroups
+        const int per_plane = *ntx * *nty;
+        const int want = std::max(1, (1024 + per_plane - 1) / per_plane);
+        z = std::max(8 * T, std::min(64, (L.nz + 1 + want - 1) / want));
+    }
+    z = std::min(z, std::max(1, planes_fit(L, es) - 2 * T - 1));
+    z = std::max(1, std::min(z, L.nz + 1));
+    *zc = z;
+    *ntz = (L.nz + 1 + z - 1) / z;
+    *threads = 64 * tl.nw;
+}
+
+template <int T, int V, class Codec>
+hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
+{
+    constexpr Tiling tl = kTilings[T][V];
+    FusedArgs a = a0;
+    int threads;
+    geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+    a.nwg = a.ntx * a.nty * a.ntz;
+    const int grid = (a.nwg + 7) / 8 * 8;
+    hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int T, int V, class Codec>
+hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t st)
+{
+    static_assert(sizeof(BatchArgs) <= 4000, "batch descriptors must fit the kernel argument segment");
+    constexpr Tiling tl = kTilings[T][V];
+    BatchArgs b;
+    b.n = n;
+    b.start[0] = 0;
+    int threads = 64 * tl.nw;
+    for (int i = 0; i < n; ++i) {
+        FusedArgs &a = b.s[i];
+        a = args[i];
+        geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+        a.nwg = a.ntx * a.nty * a.ntz;
+        b.start[i + 1] = b.start[i] + a.nwg;
+    }
+    // persistent: at most ~4 resident workgroups per CU, each striding over the work list
+    const int grid = std::min(b.start[n], 1024);
+    hipLaunchKernelGGL((yee_fused_batch<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, b);
+    return hipGetLastError();
+}
+
+template <int T, class Codec>
+hipError_t launch_t(const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st)
+{
+    if (batch) {
+        switch (variant) {
+        case 1: return launch_batch_tv<T, 1, Codec>(a, n, zc, st);
+        case 2: return launch_batch_tv<T, 2, Codec>(a, n, zc, st);
+        default: return launch_batch_tv<T, 0, Codec>(a, n, zc, st);
+        }
+    }
+    switch (variant) {
+    case 1: return launch_tv<T, 1, Codec>(*a, zc, st);
+    case 2: return launch_tv<T, 2, Codec>(*a, zc, st);
+    default: return launch_tv<T, 0, Codec>(*a, zc, st);
+    }
+}
+
+template <class Codec>
+hipError_t launch_codec(int T, const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st)
+{
+    switch (T) {
+    case 1: return launch_t<1, Codec>(a, n, batch, variant, zc, st);
+    case 2: return launch_t<2, Codec>(a, n, batch, variant, zc, st);
+    case 3: return launch_t<3, Codec>(a, n, batch, variant, zc, st);
+    case 4: return launch_t<4, Codec>(a, n, batch, variant, zc, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+}  // namespace yee
