@@ -45,23 +45,29 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void *base, long long bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, BUF_FLAGS);
 }
 
+// Loads return the stored payload (Raw); decode() turns it into an FP32 field
+// value.  The prefetched plane is held raw and decoded only when it enters the
+// pipeline one z step later, so the decode does not wait for the load.
 template <class Codec> struct Buf;
 template <> struct Buf<CodecF32> {
-    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, int vo, int so, float)
+    using Raw = float;
+    __device__ static inline Raw load(__amdgpu_buffer_rsrc_t r, int vo, int so)
     {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
     }
+    __device__ static inline float decode(Raw v, float) { return v; }
     __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float, uint32_t &, bool)
     {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
     }
 };
 template <class Codec> struct Buf16 {
-    __device__ static inline float load(__amdgpu_buffer_rsrc_t r, int vo, int so, float down)
+    using Raw = uint16_t;
+    __device__ static inline Raw load(__amdgpu_buffer_rsrc_t r, int vo, int so)
     {
-        const uint16_t q = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
-        return Codec::load(&q, down);
+        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
     }
+    __device__ static inline float decode(Raw q, float down) { return Codec::load(&q, down); }
     __device__ static inline void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v, float up, uint32_t &mx,
                                         bool own)
     {
@@ -221,7 +227,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         }
 
     // prefetched next level-0 plane
-    float PE[3][RY], PH[3][RY];
+    typename B::Raw PE[3][RY], PH[3][RY];
     uint32_t PM[RY];
 
 #define YEE_LOAD_PLANE(KK)                                                                  \
@@ -231,8 +237,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         _Pragma("unroll") for (int r = 0; r < RY; ++r) {                                    \
             const int so_ = pofs_ + rowoff[r];                                              \
             _Pragma("unroll") for (int c = 0; c < 3; ++c) {                                 \
-                PE[c][r] = B::load(rin, vo, (so_ + c * (int)cs) * ES, dn[c]);               \
-                PH[c][r] = B::load(rin, vo, (so_ + (3 + c) * (int)cs) * ES, dn[3 + c]);     \
+                PE[c][r] = B::load(rin, vo, (so_ + c * (int)cs) * ES);                      \
+                PH[c][r] = B::load(rin, vo, (so_ + (3 + c) * (int)cs) * ES);                \
             }                                                                               \
             PM[r] = __builtin_amdgcn_raw_buffer_load_b8(rmat, vom, mofs_ + rowoff[r], 0);   \
         }                                                                                   \
@@ -281,8 +287,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
             for (int c = 0; c < 3; ++c) {
                 Eo[c][r] = E[0][c][r];
                 Ho[c][r] = H[0][c][r];
-                E[0][c][r] = PE[c][r];
-                H[0][c][r] = PH[c][r];
+                E[0][c][r] = B::decode(PE[c][r], dn[c]);
+                H[0][c][r] = B::decode(PH[c][r], dn[3 + c]);
             }
         }
         if (ALL || K + 1 <= ke) YEE_LOAD_PLANE(K + 1);
