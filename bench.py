@@ -111,10 +111,11 @@ def serving_leg(rate, n, torch):
     wls = {r.rid: r.workload() for r in reqs}
     print(f"[bench] serving: {n} request payloads built in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
-    eng = serve.Engine(serve.GpuBackend(wls, time_block=4), budget_bytes=24 << 30, max_slots=64, chunk=64)
+    eng = serve.Engine(serve.GpuBackend(wls), budget_bytes=24 << 30, max_slots=64, chunk=48)
     rep = eng.run(reqs)
     out = rep.summary()
-    out.update({"rate_req_per_s": rate, "budget_GiB": 24, "max_slots": 64, "chunk_steps": 64,
+    out.update({"rate_req_per_s": rate, "budget_GiB": 24, "max_slots": 64, "chunk_steps": 48,
+                "T_by_storage": {"fp32": serve.DEFAULT_T[0], "fp16": serve.DEFAULT_T[1]},
                 "mean_work_G": float(np.mean([r.nx * r.ny * r.nz * r.n_steps for r in reqs]) / 1e9)})
     return out
 
@@ -158,7 +159,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1301_4539_amd import fdtd, roofline, workload as W
+    from paper_1301_4539_amd import fdtd, roofline, serve, workload as W
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -193,18 +194,32 @@ def main():
         extras["latency_ms"] = {"solve": f"{wl.n_steps} steps", "p50": float(np.percentile(lat, 50)),
                                 "p99": float(np.percentile(lat, 99)), "n": len(lat)}
         s.close()
-        # FP16 storage, same workload and T
-        s16 = fdtd.Solver.from_workload(wl, storage=W.FP16, kernel=fdtd.KERNEL_FUSED, time_block=T)
-        s16.set_tiling(args.tiling, args.zchunk)
-        if args.warmup:
-            s16.step(args.warmup)
-        t16 = time_steps(s16, args.steps, torch, stream)
-        v16 = cells * args.steps / t16 / 1e9
-        a16 = roofline.algorithmic_bytes(2) * cells * args.steps / t16 / 1e9
-        extras["fp16_store"] = {"value": v16, "ratio_vs_fp32": v16 / value,
-                                "roofline_frac": a16 / roofline.HBM_PEAK_GBPS}
-        s16.close()
-        print(f"[bench] fp16: {v16:.2f} G cell-updates/s", file=sys.stderr, flush=True)
+
+        def rate(st, tb):
+            """G cell-updates/s of the fused kernel for storage st at time block tb."""
+            sx = fdtd.Solver.from_workload(wl, storage=st, kernel=fdtd.KERNEL_FUSED, time_block=tb)
+            try:
+                if args.warmup:
+                    sx.step(args.warmup)
+                return cells * args.steps / time_steps(sx, args.steps, torch, stream) / 1e9
+            finally:
+                sx.close()
+
+        # 16-bit storage, each at its fastest T (FP32 storage is compute-bound
+        # at T=4, 16-bit storage at T=3), and at matched T (4, and 1 where
+        # both forms are bandwidth-bound)
+        t16 = serve.DEFAULT_T[W.FP16]
+        v16 = rate(W.FP16, t16)
+        v16_4 = rate(W.FP16, 4) if t16 != 4 else v16
+        v32_1, v16_1 = rate(W.FP32, 1), rate(W.FP16, 1)
+        vbf = rate(W.BF16, serve.DEFAULT_T[W.BF16])
+        extras["fp16_store"] = {"value": v16, "T": t16, "ratio_vs_fp32": v16 / value,
+                                "roofline_frac": roofline.algorithmic_bytes(2) * v16 / roofline.HBM_PEAK_GBPS,
+                                "matched_T": {"T4": {"fp32": value, "fp16": v16_4, "ratio": v16_4 / value},
+                                              "T1": {"fp32": v32_1, "fp16": v16_1, "ratio": v16_1 / v32_1}}}
+        extras["bf16_store"] = {"value": vbf, "T": serve.DEFAULT_T[W.BF16], "ratio_vs_fp32": vbf / value}
+        print(f"[bench] fp16 (T={t16}): {v16:.2f} G cell-updates/s, x{v16 / value:.2f}; matched T=4 "
+              f"x{v16_4 / value:.2f}, T=1 x{v16_1 / v32_1:.2f}; bf16 {vbf:.2f}", file=sys.stderr, flush=True)
         # streaming-copy ceiling on this GPU (torch copy of 2 GiB)
         x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -305,13 +305,15 @@ yee::StorageBlock storage_block(const fdtd_solver *s)
     return b;
 }
 
-// Fastest tile shape per (storage, T) measured on MI355X with the 256^3
-// dielectric workload (shape indices of the fused kernel's tile table).
+// Fastest tile shape per (storage, T) measured on MI355X with the 256^3 and
+// 512^3 dielectric workloads (shape indices of the fused kernel's tile table:
+// 0 = 2 rows x 16 waves, 1 = 4 x 8, 2 = 3 x 12; 4 x 4, 2 x 8, 2 x 16 for T=1).
 int auto_shape(int storage, int T)
 {
-    static const int f32[5] = {0, 0, 2, 2, 0};
-    static const int f16[5] = {0, 0, 2, 2, 1};
-    return storage == FDTD_FP32 ? f32[T] : f16[T];
+    static const int f32[5] = {0, 2, 1, 1, 0};
+    static const int f16[5] = {0, 2, 0, 0, 0};
+    static const int bf16[5] = {0, 2, 0, 0, 1};
+    return storage == FDTD_FP32 ? f32[T] : storage == FDTD_FP16 ? f16[T] : bf16[T];
 }
 
 int read_ctrl(fdtd_solver *s, yee::Ctrl *out)

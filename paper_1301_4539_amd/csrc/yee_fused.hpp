@@ -95,6 +95,7 @@ struct TileShared {
     int4 prb[MAX_LOCAL];     // probes this workgroup owns: (comp, lane, row, plane)
     int prbid[MAX_LOCAL];
     int nsrc, nprb;
+    uint32_t vmax[6];        // largest |value * 2^s| per component over the tile, as bits
 };
 
 // One tile (x-y tile x z chunk) of one solve: T steps of the owned region.
@@ -189,6 +190,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         sm.nsrc = ns;
         sm.nprb = np;
     }
+    if (tid < 6) sm.vmax[tid] = 0u;
     __syncthreads();
     const int nsrc = sm.nsrc, nprb = sm.nprb;
 
@@ -468,8 +470,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
 #undef YEE_LOAD_PLANE
 
     if constexpr (Codec::scaled) {
-        // largest stored magnitude per component and the saturation flag
-        bool any = false;
+        // Largest stored magnitude per component and the saturation flag:
+        // reduce over the wave, then over the workgroup in LDS, and only then
+        // touch the six global words (one atomic per component per workgroup;
+        // per-wave atomics on the same six addresses serialise at the cache).
+        // The maxima are bit patterns of |y| >= 0, so unsigned order is float
+        // order, and a NaN (bits above infinity) wins and raises the flag.
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             uint32_t b = mx[c];
@@ -477,13 +483,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                 const uint32_t ob = __shfl_xor(b, o, 64);
                 b = ob > b ? ob : b;
             }
+            if (lane == 0 && b != 0u) atomicMax(&sm.vmax[c], b);
+        }
+        __syncthreads();
+        if (tid < 6) {
+            const uint32_t b = sm.vmax[tid];
             float m;
             bool fl;
-            finish_max<Codec>(b, 1.0f / up[c], &m, &fl);
-            any = any || fl;
-            if (lane == 0 && m > 0.0f) atomicMax(&a.sb.ctrl->maxbits[a.sb.slot_out][c], __float_as_uint(m));
+            float upc = up[0];
+#pragma unroll
+            for (int c = 1; c < 6; ++c) upc = tid == c ? up[c] : upc;
+            finish_max<Codec>(b, 1.0f / upc, &m, &fl);
+            if (m > 0.0f) atomicMax(&a.sb.ctrl->maxbits[a.sb.slot_out][tid], __float_as_uint(m));
+            if (fl) atomicOr(&a.sb.ctrl->flag, 1u);
         }
-        if (lane == 0 && any) atomicOr(&a.sb.ctrl->flag, 1u);
     }
     __syncthreads();   // LDS is reused by the next tile of a batched launch
 }
@@ -533,34 +546,63 @@ int planes_fit(const Layout &L, int es)
     return (int)std::min<long long>(p, 1 << 20);
 }
 
-void geometry_for(int T, int variant, int zc_req, int es, const Layout &L, int *ntx, int *nty, int *ntz, int *zc,
-                  int *threads)
+// Tile counts and z-chunk length.  `slots` is the number of workgroups the
+// GPU holds at once (0: unknown, as for the persistent batched launch).  With
+// slots known the chunk length minimises  rounds * (zc + 1.5 T):  a tile's
+// time grows with its planes plus the cone overhead at its two ends, and the
+// launch takes ceil(workgroups / slots) rounds -- a few workgroups spilling
+// into another round cost a whole round.
+void geometry_for(int T, int variant, int zc_req, int es, const Layout &L, int slots, int *ntx, int *nty, int *ntz,
+                  int *zc, int *threads)
 {
     const Tiling tl = kTilings[T][variant];
     const int OX = 64 - 2 * T, OY = tl.nw * tl.ry - 2 * T;
     *ntx = (L.nx + 1 + OX - 1) / OX;
     *nty = (L.ny + 1 + OY - 1) / OY;
+    const int zmax = std::max(1, planes_fit(L, es) - 2 * T - 1);
+    const int per_plane = *ntx * *nty;
     int z = zc_req;
-    if (z <= 0) {
+    if (z <= 0 && slots > 0) {
+        double best = 0.0;
+        for (int n = 1; n <= L.nz + 1; ++n) {
+            const int zz = (L.nz + 1 + n - 1) / n;
+            if (zz > zmax || (n > 1 && zz == (L.nz + 1 + n - 2) / (n - 1))) continue;
+            const long long wgs = (long long)per_plane * ((L.nz + 1 + zz - 1) / zz);
+            const double cost = (double)((wgs + slots - 1) / slots) * (zz + 1.5 * T);
+            if (z <= 0 || cost < best) { best = cost; z = zz; }
+            if (wgs > 64LL * slots) break;
+        }
+    } else if (z <= 0) {
         // chunks of ~64 planes, fewer when that leaves the GPU short of workgroups
-        const int per_plane = *ntx * *nty;
         const int want = std::max(1, (1024 + per_plane - 1) / per_plane);
         z = std::max(8 * T, std::min(64, (L.nz + 1 + want - 1) / want));
     }
-    z = std::min(z, std::max(1, planes_fit(L, es) - 2 * T - 1));
+    z = std::min(z, zmax);
     z = std::max(1, std::min(z, L.nz + 1));
     *zc = z;
     *ntz = (L.nz + 1 + z - 1) / z;
     *threads = 64 * tl.nw;
 }
 
+// Workgroups of this kernel the current device holds at once (all CUs).
+template <class K>
+int resident_slots(K kernel, int threads)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) return 0;
+    return cus * per_cu;
+}
+
 template <int T, int V, class Codec>
 hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
 {
     constexpr Tiling tl = kTilings[T][V];
+    static const int slots = resident_slots(yee_fused<T, tl.ry, tl.nw, Codec>, 64 * tl.nw);
     FusedArgs a = a0;
     int threads;
-    geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+    geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
     a.nwg = a.ntx * a.nty * a.ntz;
     const int grid = (a.nwg + 7) / 8 * 8;
     hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, a);
@@ -579,7 +621,7 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
     for (int i = 0; i < n; ++i) {
         FusedArgs &a = b.s[i];
         a = args[i];
-        geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+        geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, 0, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
         a.nwg = a.ntx * a.nty * a.ntz;
         b.start[i + 1] = b.start[i] + a.nwg;
     }

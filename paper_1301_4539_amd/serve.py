@@ -134,17 +134,25 @@ class Engine:
         return Report(sorted(recs.values(), key=lambda r: r.rid), makespan, busy, rejected)
 
 
+# Steps per HBM pass used for each storage format (the fastest on MI355X:
+# FP32 storage is compute-bound at 4, 16-bit storage at 3).  A solve is
+# bit-identical alone and in the mix when every chunk is a multiple of its T.
+DEFAULT_T = {0: 4, 1: 3, 2: 3}
+
+
 class GpuBackend:
     """Drives the HIP library.  `workloads` maps request id to a pre-built
-    Workload (the request payload: grid, materials, sources, probes)."""
+    Workload (the request payload: grid, materials, sources, probes);
+    `time_block` is one T for every solve or a map storage -> T."""
 
-    def __init__(self, workloads, time_block: int = 4):
+    def __init__(self, workloads, time_block=None):
         import torch
         from . import fdtd
         self.fdtd = fdtd
         self.torch = torch
         self.wl = workloads
-        self.T = time_block
+        tb = DEFAULT_T if time_block is None else time_block
+        self.T = dict(tb) if isinstance(tb, dict) else {k: int(tb) for k in DEFAULT_T}
 
     def now(self) -> float:
         return time.perf_counter()
@@ -160,7 +168,7 @@ class GpuBackend:
     def create(self, req):
         try:
             return self.fdtd.Solver.from_workload(self.wl[req.rid], kernel=self.fdtd.KERNEL_FUSED,
-                                                  time_block=self.T)
+                                                  time_block=self.T[req.storage])
         except (self.fdtd.FdtdError, self.torch.cuda.OutOfMemoryError) as e:
             if isinstance(e, self.fdtd.FdtdError) and e.code != self.fdtd.ENOMEM:
                 raise

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 def test_serving_mix_equals_alone():
     reqs = W.serving_requests(n=10, rate=200.0, seed=77, dim_lo=24, dim_hi=72, steps_lo=40, steps_hi=160)
     wls = {r.rid: r.workload() for r in reqs}
-    eng = serve.Engine(serve.GpuBackend(wls, time_block=4), budget_bytes=1 << 30, max_slots=6, chunk=16)
+    eng = serve.Engine(serve.GpuBackend(wls), budget_bytes=1 << 30, max_slots=6, chunk=24)
     rep = eng.run(reqs)
     assert not rep.rejected
     s = rep.summary()
@@ -20,7 +20,7 @@ def test_serving_mix_equals_alone():
     assert any(r.storage == W.FP16 for r in reqs) and any(r.storage == W.FP32 for r in reqs)
     for r in rep.records:
         wl = wls[r.rid]
-        solo = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+        solo = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=serve.DEFAULT_T[wl.storage])
         try:
             solo.step(wl.n_steps)
             ref = solo.read_probes(0, wl.n_steps)
