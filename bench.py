@@ -27,9 +27,9 @@ if ROOT not in sys.path:
 
 METRIC = "G Yee cell-updates/s and % HBM roofline (FP32 vs FP16 store); p50/p99 latency"
 # Arrival rate of the serving run, frozen after one calibration on MI355X:
-# 0.7 x the saturated mixed throughput (122.7 G cell-updates/s with all 256
-# requests queued at once) / the mean work per request (9.81 G) = 8.75 req/s.
-SERVING_RATE = 8.75
+# 0.7 x the saturated mixed throughput (173.2 G cell-updates/s with all 256
+# requests queued at once) / the mean work per request (9.81 G) = 12.4 req/s.
+SERVING_RATE = 12.4
 
 
 def kernel_source_hash() -> str:
@@ -217,6 +217,7 @@ def main():
                                 "roofline_frac": roofline.algorithmic_bytes(2) * v16 / roofline.HBM_PEAK_GBPS,
                                 "matched_T": {"T4": {"fp32": value, "fp16": v16_4, "ratio": v16_4 / value},
                                               "T1": {"fp32": v32_1, "fp16": v16_1, "ratio": v16_1 / v32_1}}}
+        extras["fp16_store"]["traffic"] = measured_traffic(wl.name, "fp16", t16)
         extras["bf16_store"] = {"value": vbf, "T": serve.DEFAULT_T[W.BF16], "ratio_vs_fp32": vbf / value}
         print(f"[bench] fp16 (T={t16}): {v16:.2f} G cell-updates/s, x{v16 / value:.2f}; matched T=4 "
               f"x{v16_4 / value:.2f}, T=1 x{v16_1 / v32_1:.2f}; bf16 {vbf:.2f}", file=sys.stderr, flush=True)
