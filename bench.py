@@ -221,6 +221,22 @@ def main():
         extras["bf16_store"] = {"value": vbf, "T": serve.DEFAULT_T[W.BF16], "ratio_vs_fp32": vbf / value}
         print(f"[bench] fp16 (T={t16}): {v16:.2f} G cell-updates/s, x{v16 / value:.2f}; matched T=4 "
               f"x{v16_4 / value:.2f}, T=1 x{v16_1 / v32_1:.2f}; bf16 {vbf:.2f}", file=sys.stderr, flush=True)
+        # a full solve from host buffers: create (material upload), upload of a
+        # host initial state, the solve, read-back of fields and probes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sx = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=T)
+        sx.set_fields(np.zeros((6, wl.nz + 1, wl.ny + 1, wl.nx + 1), np.float32))
+        sx.step(wl.n_steps)
+        sx.read_fields()
+        sx.read_probes(0, wl.n_steps)
+        sx.close()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        extras["pcie_inclusive"] = {"value": cells * wl.n_steps / dt / 1e9, "unit": "G cell-updates/s",
+                                    "wall_ms": dt * 1e3,
+                                    "what": f"create + set_fields(host) + {wl.n_steps} steps + read_fields + "
+                                            f"read_probes, FP32 T={T}"}
         # streaming-copy ceiling on this GPU (torch copy of 2 GiB)
         x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -217,6 +217,11 @@ struct fdtd_solver {
     // diagnostics scratch
     double *diag_part_d = nullptr;
     double *diag_out_d = nullptr;
+    // pinned host staging for uploads and read-backs: two buffers of one
+    // z-plane of all six components in device layout, used alternately so
+    // that host work on one plane overlaps the copy of the other
+    char *stage[2] = {nullptr, nullptr};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -314,6 +319,21 @@ int auto_shape(int storage, int T)
     static const int f16[5] = {0, 2, 0, 0, 0};
     static const int bf16[5] = {0, 2, 0, 0, 1};
     return storage == FDTD_FP32 ? f32[T] : storage == FDTD_FP16 ? f16[T] : bf16[T];
+}
+
+// Allocate the pinned staging buffers on first use (freed by fdtd_destroy).
+int ensure_staging(fdtd_solver *s)
+{
+    if (s->stage[0]) return FDTD_OK;
+    const size_t bytes = (size_t)s->L.kstride * elem_size(s->storage);
+    hipError_t e;
+    for (int b = 0; b < 2; ++b) {
+        if ((e = hipHostMalloc((void **)&s->stage[b], bytes, hipHostMallocDefault)))
+            return hip_fail(e, "hipHostMalloc(staging)");
+        if ((e = hipEventCreateWithFlags(&s->stage_ev[b], hipEventDisableTiming)))
+            return hip_fail(e, "hipEventCreate(staging)");
+    }
+    return FDTD_OK;
 }
 
 int read_ctrl(fdtd_solver *s, yee::Ctrl *out)
@@ -532,38 +552,49 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
                 }
         choose_scales(m, s->a_max, sc);
     }
+    if (int rc = ensure_staging(s)) return rc;
     if ((e = hipMemsetAsync(s->fbuf[0], 0, s->d.fbytes, s->st))) return hip_fail(e, "hipMemset");
-    std::vector<float> pf(s->storage == FDTD_FP32 ? nplane : 0);
-    std::vector<uint16_t> pq(s->storage == FDTD_FP32 ? 0 : nplane);
+    // One copy per z plane: the six components of plane k are contiguous on
+    // the device (kstride = 6 planes), so they are laid out in a pinned buffer
+    // exactly as on the device (pitched rows, zeros in the padding) and sent in
+    // one transfer; the other buffer is filled meanwhile.
     float mx[6] = {0, 0, 0, 0, 0, 0};
     bool sat = false;
+    float upf[6], dnf[6];
     for (int c = 0; c < 6; ++c) {
-        const float upf = std::ldexp(1.0f, sc[c]), dnf = std::ldexp(1.0f, -sc[c]);
-        for (int k = 0; k <= nz; ++k) {
+        upf[c] = std::ldexp(1.0f, sc[c]);
+        dnf[c] = std::ldexp(1.0f, -sc[c]);
+    }
+    const size_t pitch = (size_t)s->d.pitch;
+    for (int k = 0; k <= nz; ++k) {
+        const int b = k & 1;
+        if (k >= 2 && (e = hipEventSynchronize(s->stage_ev[b]))) return hip_fail(e, "upload fields");
+        char *buf = s->stage[b];
+        std::memset(buf, 0, (size_t)s->L.kstride * es);
+        for (int c = 0; c < 6; ++c) {
             const float *src = host + (size_t)c * nbox + (size_t)k * nplane;
             for (int j = 0; j <= ny; ++j) {
                 int i0 = 0, i1 = 0;
-                const bool any = row_span(nx, ny, nz, c, j, k, &i0, &i1);
-                const size_t r = (size_t)j * (nx + 1);
-                for (int i = 0; i <= nx; ++i) {
-                    const float v = (any && i >= i0 && i < i1) ? src[r + i] : 0.0f;
-                    if (s->storage == FDTD_FP32) {
-                        pf[r + i] = v;
-                    } else {
-                        const uint16_t h = encode(s->storage, v * upf, &sat);
-                        pq[r + i] = h;
-                        const float d = std::fabs(decode(s->storage, h) * dnf);
+                if (!row_span(nx, ny, nz, c, j, k, &i0, &i1)) continue;
+                const float *row = src + (size_t)j * (nx + 1);
+                const size_t at = (size_t)c * s->L.cstride + (size_t)j * pitch;
+                if (s->storage == FDTD_FP32) {
+                    std::memcpy((float *)buf + at + i0, row + i0, (size_t)(i1 - i0) * sizeof(float));
+                } else {
+                    uint16_t *q = (uint16_t *)buf + at;
+                    for (int i = i0; i < i1; ++i) {
+                        const uint16_t h = encode(s->storage, row[i] * upf[c], &sat);
+                        q[i] = h;
+                        const float d = std::fabs(decode(s->storage, h) * dnf[c]);
                         if (d > mx[c]) mx[c] = d;        // NaN never compares greater
                     }
                 }
             }
-            const void *plane = s->storage == FDTD_FP32 ? (const void *)pf.data() : (const void *)pq.data();
-            e = hipMemcpy2DAsync(s->fbuf[0] + ((size_t)c * s->L.cstride + (size_t)k * s->L.kstride) * es,
-                                 (size_t)s->d.pitch * es, plane, (size_t)(nx + 1) * es, (size_t)(nx + 1) * es,
-                                 (size_t)(ny + 1), hipMemcpyHostToDevice, s->st);
-            if (!e) e = hipStreamSynchronize(s->st);         // the staging plane is reused
-            if (e) return hip_fail(e, "upload fields");
         }
+        if ((e = hipMemcpyAsync(s->fbuf[0] + (size_t)k * s->L.kstride * es, buf, (size_t)s->L.kstride * es,
+                                hipMemcpyHostToDevice, s->st)) ||
+            (e = hipEventRecord(s->stage_ev[b], s->st)))
+            return hip_fail(e, "upload fields");
     }
     if (s->storage != FDTD_FP32) {
         for (int c = 0; c < 6; ++c) {
@@ -730,29 +761,42 @@ int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst)
     const size_t nbox = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
     const int es = elem_size(s->storage);
     hipError_t e;
-    std::vector<uint16_t> q;
-    void *dst = host_dst;
-    if (s->storage != FDTD_FP32) {
-        q.resize(nbox);
-        dst = q.data();
-    }
-    const size_t nplane = (size_t)(nx + 1) * (ny + 1);
-    e = hipSuccess;
-    for (int k = 0; k <= nz && !e; ++k)
-        e = hipMemcpy2DAsync((char *)dst + (size_t)k * nplane * es, (size_t)(nx + 1) * es,
-                             s->fbuf[s->cur] + ((size_t)comp * s->L.cstride + (size_t)k * s->L.kstride) * es,
-                             (size_t)s->d.pitch * es, (size_t)(nx + 1) * es, (size_t)(ny + 1),
-                             hipMemcpyDeviceToHost, s->st);
-    if (!e) e = hipStreamSynchronize(s->st);
-    if (e) return hip_fail(e, "read fields");
+    if (int rc = ensure_staging(s)) return rc;
+    float dnf = 1.0f;
     if (s->storage != FDTD_FP32) {
         yee::Ctrl c;
-        int rc = read_ctrl(s, &c);
-        if (rc) return rc;
-        const float dnf = std::ldexp(1.0f, -c.scale[s->block % 2][comp]);
-        for (size_t p = 0; p < nbox; ++p) host_dst[p] = decode(s->storage, q[p]) * dnf;
+        if (int rc = read_ctrl(s, &c)) return rc;
+        dnf = std::ldexp(1.0f, -c.scale[s->block % 2][comp]);
     }
-    return FDTD_OK;
+    // Plane k of the component is one contiguous pitched block on the device:
+    // copy it to a pinned buffer while the host unpacks the previous one.
+    const size_t nplane = (size_t)(nx + 1) * (ny + 1);
+    const size_t pbytes = (size_t)s->L.plane * es;
+    auto fetch = [&](int k) {
+        const int b = k & 1;
+        hipError_t r = hipMemcpyAsync(s->stage[b], s->fbuf[s->cur] + ((size_t)comp * s->L.cstride +
+                                      (size_t)k * s->L.kstride) * es, pbytes, hipMemcpyDeviceToHost, s->st);
+        return r ? r : hipEventRecord(s->stage_ev[b], s->st);
+    };
+    e = fetch(0);
+    for (int k = 0; k <= nz && !e; ++k) {
+        if (k < nz && (e = fetch(k + 1))) break;
+        if ((e = hipEventSynchronize(s->stage_ev[k & 1]))) break;
+        const char *buf = s->stage[k & 1];
+        float *out = host_dst + (size_t)k * nplane;
+        for (int j = 0; j <= ny; ++j) {
+            const size_t at = (size_t)j * s->d.pitch;
+            if (s->storage == FDTD_FP32) {
+                std::memcpy(out + (size_t)j * (nx + 1), (const float *)buf + at, (size_t)(nx + 1) * sizeof(float));
+            } else {
+                const uint16_t *q = (const uint16_t *)buf + at;
+                for (int i = 0; i <= nx; ++i) out[(size_t)j * (nx + 1) + i] = decode(s->storage, q[i]) * dnf;
+            }
+        }
+    }
+    if (!e) e = hipStreamSynchronize(s->st);
+    (void)nbox;
+    return e ? hip_fail(e, "read fields") : FDTD_OK;
 }
 
 int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int n_steps)
@@ -856,6 +900,10 @@ void fdtd_destroy(fdtd_solver *s)
     free_dev(s->probe_out_d);
     free_dev(s->diag_part_d);
     free_dev(s->diag_out_d);
+    for (int b = 0; b < 2; ++b) {
+        if (s->stage[b]) (void)hipHostFree(s->stage[b]);
+        if (s->stage_ev[b]) (void)hipEventDestroy(s->stage_ev[b]);
+    }
     delete s;
 }
 
