@@ -126,7 +126,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--T", type=int, default=4, help="steps per HBM pass of the fused kernel (1..4)")
-    ap.add_argument("--workload", default="spheres256", choices=["spheres256", "spheres512"])
+    ap.add_argument("--workload", default="spheres256", choices=["spheres256", "spheres512", "cavity402"])
     ap.add_argument("--tiling", type=int, default=0, help="fused-kernel tile variant (0 = auto, 1..3)")
     ap.add_argument("--zchunk", type=int, default=0, help="planes per z chunk (0 = automatic)")
     ap.add_argument("--solves", type=int, default=5, help="full solves for the latency percentiles")
@@ -163,7 +163,7 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    wl = W.spheres256() if args.workload == "spheres256" else W.spheres512()
+    wl = {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402}[args.workload]()
     cells = wl.cells
     T = args.T
 
@@ -268,7 +268,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "storage": "fp32",
-                   "kernel": "fused", "T": T, "materials": 16, "spheres": 40, "sources": len(wl.sources),
+                   "kernel": "fused", "T": T, "materials": len(wl.eps_r),
+                   "spheres": {"spheres256": 40, "spheres512": 200}.get(wl.name, 0), "sources": len(wl.sources),
                    "probes": len(wl.probes), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": roofline.HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / roofline.HBM_PEAK_GBPS,

@@ -28,9 +28,9 @@ def _check(a, b, what):
     assert msg is None, f"{what}: {msg}"
 
 
-@pytest.mark.parametrize("name", ["spheres256", "spheres512"])
+@pytest.mark.parametrize("name", ["spheres256", "spheres512", "cavity402"])
 def test_fullsize_fp32_short_run_bitexact(name):
-    wl = W.spheres256() if name == "spheres256" else W.spheres512()
+    wl = {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402}[name]()
     steps = 8 if name == "spheres256" else 4
     init = _random_init(wl, 11)
     s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
