@@ -119,8 +119,12 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz,
                 const uint8_t *mat_index, int storage,
                 void *device_workspace, size_t workspace_bytes, void *hip_stream);
 
-/* Kernel family (fdtd_kernel) and steps per HBM pass T (1..4) for the FUSED
- * family.  Allowed before the first step and between steps. */
+/* Kernel family (fdtd_kernel) and steps per HBM pass T for the FUSED family:
+ * 1..4, or 0 = automatic (the default after fdtd_create): 4 for FP32
+ * storage and 3 for FP16/BF16 storage, the fastest on MI355X, lowered for
+ * grids whose planes are too large for that T.  Allowed before the first
+ * step and between steps.  Results do not depend on T for FP32 storage; for
+ * FP16/BF16 storage, T sets where values are re-quantised (every T steps). */
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
 
 /* Tile shape of the FUSED kernel -- variant 0 = chosen per storage format and

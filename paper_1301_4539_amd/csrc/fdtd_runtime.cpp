@@ -182,7 +182,7 @@ struct fdtd_solver {
     double dx = 0, dy = 0, dz = 0, dt = 0;
     int storage = FDTD_FP32;
     int kernel = FDTD_KERNEL_AUTO;
-    int T = 2;
+    int T = 1;                          // set by fdtd_create (automatic) or fdtd_set_kernel
     int tiling = 0;                     // fused-kernel tile shape: 0 = auto, 1..3 = explicit
     int zchunk = 0;                     // planes per z chunk (0 = automatic)
     hipStream_t st = nullptr;
@@ -321,6 +321,16 @@ int auto_shape(int storage, int T)
     return storage == FDTD_FP32 ? f32[T] : storage == FDTD_FP16 ? f16[T] : bf16[T];
 }
 
+// Fastest steps per pass on MI355X for the storage format (FP32 storage is
+// compute-bound at 4, 16-bit storage at 3), lowered while the grid's planes
+// are too large for the fused kernel's addressing.
+int auto_T(const fdtd_solver *s)
+{
+    int T = s->storage == FDTD_FP32 ? 4 : 3;
+    while (T > 1 && !yee::fused_fits(s->L, s->storage, T)) --T;
+    return T;
+}
+
 // Allocate the pinned staging buffers on first use (freed by fdtd_destroy).
 int ensure_staging(fdtd_solver *s)
 {
@@ -446,6 +456,7 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy,
     s->L.plane = s->d.plane;
     s->L.cstride = s->d.plane;
     s->L.kstride = s->d.kstride;
+    s->T = auto_T(s);
 
     hipError_t e;
     if (device_workspace) {
@@ -496,7 +507,8 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
 {
     if (!s) return fail(FDTD_EINVAL, "solver is NULL");
     if (kernel < 0 || kernel > 2) return fail(FDTD_EINVAL, "bad kernel family");
-    if (time_block < 1 || time_block > 4) return fail(FDTD_EINVAL, "time_block must be 1..4");
+    if (time_block < 0 || time_block > 4) return fail(FDTD_EINVAL, "time_block must be 0 (automatic) or 1..4");
+    if (time_block == 0) time_block = auto_T(s);
     if (kernel == FDTD_KERNEL_PLAIN && s->storage != FDTD_FP32)
         return fail(FDTD_EINVAL, "the plain kernel needs FP32 storage");
     if (kernel != FDTD_KERNEL_PLAIN && !yee::fused_fits(s->L, s->storage, time_block))

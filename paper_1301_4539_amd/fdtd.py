@@ -116,7 +116,7 @@ class Solver:
     """One FDTD solve on the GPU.  Arrays use the (nz+1, ny+1, nx+1) node box."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, dt, eps_r, sigma, mat=None, storage=FP32,
-                 kernel=KERNEL_AUTO, time_block=2, mu_r=None, torch_workspace=True, stream=None):
+                 kernel=KERNEL_AUTO, time_block=0, mu_r=None, torch_workspace=True, stream=None):
         import torch
         self.nx, self.ny, self.nz = nx, ny, nz
         self.storage = storage
@@ -144,7 +144,7 @@ class Solver:
         self.set_kernel(kernel, time_block)
 
     @classmethod
-    def from_workload(cls, wl, storage=None, kernel=KERNEL_AUTO, time_block=2, **kw):
+    def from_workload(cls, wl, storage=None, kernel=KERNEL_AUTO, time_block=0, **kw):
         s = cls(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.dt, wl.eps_r, wl.sigma, wl.mat,
                 storage=wl.storage if storage is None else storage, kernel=kernel, time_block=time_block, **kw)
         for q, (c, i, j, k) in enumerate(wl.sources):

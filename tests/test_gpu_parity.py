@@ -94,6 +94,26 @@ def test_reduced_storage_bitexact_with_emulation(fmt, T):
     _assert_same(p, po, "probes")
 
 
+@pytest.mark.parametrize("fmt,T", [(W.FP32, 4), (W.FP16, 3), (W.BF16, 3)])
+def test_automatic_time_block(fmt, T):
+    """Without an explicit T the solver uses the fastest form: 4 steps per
+    pass for FP32 storage, 3 for 16-bit storage (the re-quantisation points
+    of the 16-bit emulation pin which T ran)."""
+    wl = ragged(n_steps=36, storage=fmt)
+    s = fdtd.Solver.from_workload(wl)
+    try:
+        s.step(36)
+        f, p = s.read_fields(), s.read_probes(0, 36)
+    finally:
+        s.close()
+    if fmt == W.FP32:
+        fo, po = G.oracle_f32(wl, 36)
+    else:
+        fo, po, _ = G.oracle_q(wl, 36, fmt, T)
+    _assert_same(f, fo, "fields")
+    _assert_same(p, po, "probes")
+
+
 @pytest.mark.parametrize("fmt", [W.FP16, W.BF16])
 def test_reduced_storage_upload_roundtrip(fmt):
     wl = W.cavity32()
