@@ -343,21 +343,14 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     }
                 }
                 // ---- Ampere: E^(t) at plane p from H^(t) at p and p-1 ----
+                // Only row 0 needs the H row of the wave below: rows 1..RY-1 are
+                // updated before the level's barrier, row 0 after it.
                 // Consecutive levels alternate buffers (also across z steps), so
                 // one barrier per level orders both the write and the reuse.
-                const int hb = (T & 1) ? ((K + t) & 1) : (t & 1);
-                if constexpr (NW > 1) {
-                    s_h[hb][w + 1][lane] = make_float2(Hn[0][RY - 1], Hn[2][RY - 1]);
-                    __syncthreads();
-                }
-                const float2 hdn = NW > 1 ? s_h[hb][w][lane] : make_float2(0.0f, 0.0f);
                 float En[3][RY];
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
+                auto e_row = [&](const int r, const float hxd, const float hzd) __attribute__((always_inline)) {
                     const int y = yw + r;
                     const bool yint = y > 0 && y < ny;
-                    const float hxd = r > 0 ? Hn[0][(r + RY - 1) % RY] : hdn.x;
-                    const float hzd = r > 0 ? Hn[2][(r + RY - 1) % RY] : hdn.y;
                     const float hzl = from_left(Hn[2][r]);
                     const float hyl = from_left(Hn[1][r]);
                     const float4 cf = s_coef[(uint32_t)(MP[r] >> (8 * t)) & 0xffu];
@@ -379,6 +372,17 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                         En[1][r] = (xint && y >= 0 && y < ny && pint) ? ey : Eo[1][r];
                         En[2][r] = (xint && yint && plt) ? ez : Eo[2][r];
                     }
+                };
+                const int hb = (T & 1) ? ((K + t) & 1) : (t & 1);
+                if constexpr (NW > 1) s_h[hb][w + 1][lane] = make_float2(Hn[0][RY - 1], Hn[2][RY - 1]);
+#pragma unroll
+                for (int r = 1; r < RY; ++r) e_row(r, Hn[0][r - 1], Hn[2][r - 1]);
+                if constexpr (NW > 1) {
+                    __syncthreads();
+                    const float2 hdn = s_h[hb][w][lane];
+                    e_row(0, hdn.x, hdn.y);
+                } else {
+                    e_row(0, 0.0f, 0.0f);
                 }
                 // ---- soft sources of step step0+t-1, on every tile computing the edge ----
                 const long long n = a.step0 + (t - 1);
