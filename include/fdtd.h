@@ -74,7 +74,9 @@ enum fdtd_component { FDTD_EX = 0, FDTD_EY = 1, FDTD_EZ = 2, FDTD_HX = 3, FDTD_H
  * step (the standard loop of Sec. 2.2; FP32 storage only).  FUSED: one pass
  * over HBM advances T steps, H and E interleaved plane by plane along z
  * with T time levels pipelined in registers (Sec. 3.2-3.4).  AUTO picks
- * FUSED. */
+ * FUSED, or PLAIN for grids whose z-planes are too large for the fused
+ * kernel's chunk addressing (6 components x T+1 planes above 2 GiB; FP32
+ * storage only -- fdtd_create rejects 16-bit storage for such grids). */
 enum fdtd_kernel { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_PLAIN = 1, FDTD_KERNEL_FUSED = 2 };
 
 typedef struct {
@@ -108,7 +110,9 @@ size_t fdtd_workspace_bytes(int nx, int ny, int nz, int storage);
  *   table         n_materials entries (1..256), copied
  *   mat_index     host, nx*ny*nz bytes, x fastest (i + nx*(j + ny*k)); every
  *                 entry < n_materials (scanned; else FDTD_EINVAL); NULL = all 0
- *   storage       fdtd_storage
+ *   storage       fdtd_storage; FP16/BF16 need z-planes small enough for the
+ *                 fused kernel (6 (nx+1) (ny+1) 2 bytes x 4 planes < 2 GiB),
+ *                 else FDTD_EINVAL
  *   device_workspace  NULL: the library allocates; else at least
  *                 fdtd_workspace_bytes(...) bytes of device memory, 256-byte
  *                 aligned, owned by the caller

@@ -346,6 +346,19 @@ int ensure_staging(fdtd_solver *s)
     return FDTD_OK;
 }
 
+// Staging buffers above 64 MiB (grids with very large planes) are not kept
+// pinned between calls.
+void release_large_staging(fdtd_solver *s)
+{
+    if (!s->stage[0] || (size_t)s->L.kstride * elem_size(s->storage) <= (64u << 20)) return;
+    for (int b = 0; b < 2; ++b) {
+        (void)hipHostFree(s->stage[b]);
+        (void)hipEventDestroy(s->stage_ev[b]);
+        s->stage[b] = nullptr;
+        s->stage_ev[b] = nullptr;
+    }
+}
+
 int read_ctrl(fdtd_solver *s, yee::Ctrl *out)
 {
     hipError_t e = hipMemcpyAsync(out, s->ctrl, sizeof(yee::Ctrl), hipMemcpyDeviceToHost, s->st);
@@ -457,6 +470,10 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy,
     s->L.cstride = s->d.plane;
     s->L.kstride = s->d.kstride;
     s->T = auto_T(s);
+    if (!yee::fused_fits(s->L, storage, 1) && storage != FDTD_FP32) {
+        delete s;
+        return fail(FDTD_EINVAL, "grid planes too large for the fused kernel, and the plain kernel needs FP32 storage");
+    }
 
     hipError_t e;
     if (device_workspace) {
@@ -509,9 +526,11 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
     if (kernel < 0 || kernel > 2) return fail(FDTD_EINVAL, "bad kernel family");
     if (time_block < 0 || time_block > 4) return fail(FDTD_EINVAL, "time_block must be 0 (automatic) or 1..4");
     if (time_block == 0) time_block = auto_T(s);
+    if (kernel == FDTD_KERNEL_AUTO)   // AUTO lowers T to what the grid allows (plain if nothing fits)
+        while (time_block > 1 && !yee::fused_fits(s->L, s->storage, time_block)) --time_block;
     if (kernel == FDTD_KERNEL_PLAIN && s->storage != FDTD_FP32)
         return fail(FDTD_EINVAL, "the plain kernel needs FP32 storage");
-    if (kernel != FDTD_KERNEL_PLAIN && !yee::fused_fits(s->L, s->storage, time_block))
+    if (kernel == FDTD_KERNEL_FUSED && !yee::fused_fits(s->L, s->storage, time_block))
         return fail(FDTD_EINVAL, "grid planes too large for the fused kernel; use the plain kernel");
     s->kernel = kernel;
     s->T = time_block;
@@ -618,6 +637,7 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
     if ((e = hipMemcpyAsync(s->ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s->st)) ||
         (e = hipStreamSynchronize(s->st)))
         return hip_fail(e, "upload fields");
+    release_large_staging(s);
     return FDTD_OK;
 }
 
@@ -678,7 +698,12 @@ int fdtd_step(fdtd_solver *s, int n_steps)
     const yee::SourceTable src = src_table(s);
     const yee::ProbeTable probe = probe_table(s);
     hipError_t e;
-    if (s->kernel == FDTD_KERNEL_PLAIN) {
+    // AUTO is the fused kernel, or the plain one for grids whose planes are
+    // too large for the fused kernel's chunk addressing (FP32 only: create
+    // rejects 16-bit storage for such grids).
+    const bool plain = s->kernel == FDTD_KERNEL_PLAIN ||
+                       (s->kernel == FDTD_KERNEL_AUTO && !yee::fused_fits(s->L, s->storage, 1));
+    if (plain) {
         yee::PlainArgs a;
         a.L = s->L;
         a.f = (float *)s->fbuf[s->cur];
@@ -698,6 +723,8 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         yee::FusedArgs a;
         fill_fused(s, &a);
         const int shape = s->tiling > 0 ? s->tiling - 1 : auto_shape(s->storage, len);
+        if (!yee::fused_fits(s->L, s->storage, len))      // never launch a chunk beyond its addressing
+            return fail(FDTD_EINVAL, "grid planes too large for the fused kernel at this T");
         if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
         advance(s, len);
         left -= len;
@@ -715,7 +742,8 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
         fdtd_solver *s = solvers[i];
         if (!s) return fail(FDTD_EINVAL, "solver is NULL");
         if (s->st != st) return fail(FDTD_EINVAL, "batched solvers must share one stream");
-        if (s->kernel == FDTD_KERNEL_PLAIN) return fail(FDTD_EINVAL, "batched steps use the fused kernel");
+        if (s->kernel == FDTD_KERNEL_PLAIN || !yee::fused_fits(s->L, s->storage, s->T))
+            return fail(FDTD_EINVAL, "batched steps use the fused kernel");
         if (n_steps[i] < 0) return fail(FDTD_EINVAL, "negative step count");
         for (int j = 0; j < i; ++j)
             if (solvers[j] == s) return fail(FDTD_EINVAL, "a solver appears twice in the batch");
@@ -808,7 +836,9 @@ int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst)
     }
     if (!e) e = hipStreamSynchronize(s->st);
     (void)nbox;
-    return e ? hip_fail(e, "read fields") : FDTD_OK;
+    if (e) return hip_fail(e, "read fields");
+    release_large_staging(s);
+    return FDTD_OK;
 }
 
 int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int n_steps)

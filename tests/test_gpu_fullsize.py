@@ -88,3 +88,31 @@ def test_fullsize_1000_steps_fused_equals_plain():
     # the last probe row equals the final fields at the probe positions
     for q, (c, i, j, k) in enumerate(wl.probes):
         assert p1[-1, q] == float(f1[c, k, j, i])
+
+
+def test_planes_too_large_for_the_fused_kernel_run_plain():
+    """4800 x 4800 x 2 cells in FP32: six components of one z-plane times T+1
+    planes exceed the fused kernel's 2 GiB chunk addressing even at T = 1.
+    Under AUTO the solver steps with the plain kernel, bit-exact with the
+    oracle.  In 16-bit storage (fused kernel only) planes that large are
+    rejected at create: 6800 x 6800."""
+    big = W.spheres(6800, 6800, 2, 0, 3, seed=22, n_sources=1, n_probes=0, rmin=1, rmax=2, name="wider")
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.Solver.from_workload(big, storage=W.FP16)
+    assert e.value.code == fdtd.EINVAL
+    del big
+    wl = W.spheres(4800, 4800, 2, 0, 3, seed=21, n_sources=1, n_probes=4, rmin=1, rmax=2, name="wide")
+    init = _random_init(wl, 13)
+    s = fdtd.Solver.from_workload(wl)
+    try:
+        s.set_fields(init)
+        s.step(3)
+        got = s.read_fields()
+        probes = s.read_probes(0, 3)
+    finally:
+        s.close()
+    prob = oracle.Problem.from_workload(wl)
+    ref = init.copy()
+    ref_probes = prob.run_f32(ref, 0, 3)
+    _check(got, ref, "wide grid")
+    _check(probes, ref_probes, "wide grid probes")
