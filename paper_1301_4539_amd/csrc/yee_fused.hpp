@@ -16,9 +16,11 @@
 // Thread layout: lane = x (64 consecutive points, coalesced), each lane holds
 // RY consecutive rows in y, NW waves stack in y.  x neighbours move between
 // lanes with DPP wave shifts; the y neighbour across a wave boundary goes
-// through a small LDS slot.  Fields are read from buffer fin and the advanced
-// state is written to buffer fout (ping-pong): an in-place update would race
-// with neighbouring tiles still reading the old time level.
+// through LDS, with one barrier per time level.  Each level computes only
+// the planes of its dependency cone within the chunk.  Fields are read from
+// buffer fin and the advanced state is written to buffer fout (ping-pong):
+// an in-place update would race with neighbouring tiles still reading the
+// old time level.
 //
 // Addressing: every array is read through a buffer resource based at the
 // chunk's first plane; the per-lane x offset lives in one VGPR and the plane
