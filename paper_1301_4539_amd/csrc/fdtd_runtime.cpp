@@ -310,26 +310,8 @@ yee::StorageBlock storage_block(const fdtd_solver *s)
     return b;
 }
 
-// Fastest tile shape per (storage, T) measured on MI355X with the 256^3 and
-// 512^3 dielectric workloads (shape indices of the fused kernel's tile table:
-// 0 = 2 rows x 16 waves, 1 = 4 x 8, 2 = 3 x 12; 4 x 4, 2 x 8, 2 x 16 for T=1).
-int auto_shape(int storage, int T)
-{
-    static const int f32[5] = {0, 2, 1, 1, 0};
-    static const int f16[5] = {0, 2, 0, 0, 0};
-    static const int bf16[5] = {0, 2, 0, 0, 1};
-    return storage == FDTD_FP32 ? f32[T] : storage == FDTD_FP16 ? f16[T] : bf16[T];
-}
 
-// Fastest steps per pass on MI355X for the storage format (FP32 storage is
-// compute-bound at 4, 16-bit storage at 3), lowered while the grid's planes
-// are too large for the fused kernel's addressing.
-int auto_T(const fdtd_solver *s)
-{
-    int T = s->storage == FDTD_FP32 ? 4 : 3;
-    while (T > 1 && !yee::fused_fits(s->L, s->storage, T)) --T;
-    return T;
-}
+int auto_T(const fdtd_solver *s) { return yee::fastest_T(s->L, s->storage); }
 
 // Allocate the pinned staging buffers on first use (freed by fdtd_destroy).
 int ensure_staging(fdtd_solver *s)
@@ -722,7 +704,7 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         const int len = next_block(s, left);
         yee::FusedArgs a;
         fill_fused(s, &a);
-        const int shape = s->tiling > 0 ? s->tiling - 1 : auto_shape(s->storage, len);
+        const int shape = s->tiling > 0 ? s->tiling - 1 : yee::auto_shape(s->storage, len);
         if (!yee::fused_fits(s->L, s->storage, len))      // never launch a chunk beyond its addressing
             return fail(FDTD_EINVAL, "grid planes too large for the fused kernel at this T");
         if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
@@ -761,7 +743,7 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
             if (left[i] > 0) {
                 fdtd_solver *s = solvers[i];
                 len[i] = next_block(s, left[i]);
-                const int shape = s->tiling > 0 ? s->tiling - 1 : auto_shape(s->storage, len[i]);
+                const int shape = s->tiling > 0 ? s->tiling - 1 : yee::auto_shape(s->storage, len[i]);
                 key[i] = (s->storage * 8 + len[i]) * 8 + shape;
                 any = true;
             } else {
@@ -798,7 +780,6 @@ int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst)
     if (!s || !host_dst) return fail(FDTD_EINVAL, "NULL argument");
     if (comp < 0 || comp > 5) return fail(FDTD_EINVAL, "bad component");
     const int nx = s->L.nx, ny = s->L.ny, nz = s->L.nz;
-    const size_t nbox = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
     const int es = elem_size(s->storage);
     hipError_t e;
     if (int rc = ensure_staging(s)) return rc;
@@ -835,7 +816,6 @@ int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst)
         }
     }
     if (!e) e = hipStreamSynchronize(s->st);
-    (void)nbox;
     if (e) return hip_fail(e, "read fields");
     release_large_staging(s);
     return FDTD_OK;

@@ -25,6 +25,27 @@ hipError_t launch_any(int storage, int T, const FusedArgs *a, int n, bool batch,
 
 }  // namespace
 
+// Fastest tile shape per (storage, T) measured on MI355X with the 256^3 and
+// 512^3 dielectric workloads (shape indices of the fused kernel's tile table:
+// 0 = 2 rows x 16 waves, 1 = 4 x 8, 2 = 3 x 12; 4 x 4, 2 x 8, 2 x 16 for T=1).
+int auto_shape(int storage, int T)
+{
+    static const int f32[5] = {0, 2, 1, 1, 0};
+    static const int f16[5] = {0, 2, 0, 0, 0};
+    static const int bf16[5] = {0, 2, 0, 0, 1};
+    return storage == 0 ? f32[T] : storage == 1 ? f16[T] : bf16[T];
+}
+
+// Fastest steps per pass on MI355X for the storage format (FP32 storage is
+// compute-bound at 4, 16-bit storage at 3), lowered while the grid's planes
+// are too large for the fused kernel's addressing.
+int fastest_T(const Layout &L, int storage)
+{
+    int T = storage == 0 ? 4 : 3;
+    while (T > 1 && !fused_fits(L, storage, T)) --T;
+    return T;
+}
+
 bool fused_fits(const Layout &L, int storage, int T)
 {
     // a chunk's buffer resource spans (planes * kstride * es) bytes, below 2^31

@@ -116,6 +116,10 @@ hipError_t launch_fused_batch(int storage, int T, const FusedArgs *args, int n, 
                               hipStream_t st);
 // false if a z chunk of this grid cannot be addressed with 32-bit offsets
 bool fused_fits(const Layout &L, int storage, int T);
+// Tile shape (index into the fused kernel's table) and steps per pass chosen
+// when the caller does not: measured fastest on MI355X.
+int auto_shape(int storage, int T);
+int fastest_T(const Layout &L, int storage);
 hipError_t launch_diag(int storage, const DiagArgs &a, double *out11, hipStream_t st);
 int diag_blocks(const Layout &L);
 
