@@ -164,8 +164,9 @@ int fdtd_set_probe(fdtd_solver *s, int comp, int i, int j, int k, int *id);
 int fdtd_step(fdtd_solver *s, int n_steps);
 
 /* Advance several solvers at once: n_steps[i] (>= 0) steps for solvers[i],
- * count >= 0, every solver distinct, all created on the same stream and set
- * to the FUSED kernel.  Each block (up to T steps, ending on multiples of
+ * count >= 0, every solver distinct, all created on the same stream, none
+ * set to the PLAIN kernel and none with planes too large for the FUSED one
+ * (else FDTD_EINVAL).  Each block (up to T steps, ending on multiples of
  * T) is issued as one persistent launch over the tiles of up to 12 solvers
  * that share storage format, block length and tile shape, so small grids
  * share the GPU instead of each under-filling it.  Results are bit-identical
