@@ -54,6 +54,20 @@ def lib():
         L.orc_energy_f32.restype = C.c_double
         L.orc_threads.restype = _i
         L.orc_divergence_f64.argtypes = [_i, _i, _i, C.c_double, C.c_double, C.c_double, _dp, _u8, _dp, _dp, _dp]
+        L.orc_graded_coefficients.argtypes = [_i, _dp, _dp, C.c_double, _i, _i, _i, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_h_half_graded_f64.argtypes = [_i, _i, _i, _dp, _dp]
+        L.orc_e_half_graded_f64.argtypes = [_i, _i, _i, _dp, _dp, _u8, _dp]
+        L.orc_h_half_graded_f32.argtypes = [_i, _i, _i, _fp, _fp]
+        L.orc_e_half_graded_f32.argtypes = [_i, _i, _i, _fp, _fp, _u8, _fp]
+        L.orc_run_graded_f64.argtypes = [_i, _i, _i, _dp, _dp, _dp, _u8, _dp, _l, _i, _i, _ip, _dp, _i, _i, _ip,
+                                         _dp]
+        L.orc_run_graded_f64.restype = _i
+        L.orc_run_graded_f32.argtypes = [_i, _i, _i, _fp, _fp, _fp, _u8, _fp, _l, _i, _i, _ip, _fp, _i, _i, _ip,
+                                         _dp]
+        L.orc_run_graded_f32.restype = _i
+        L.orc_energy_graded_f64.argtypes = [_i, _i, _i, _dp, _dp, _dp, _dp, _dp, _u8, _dp]
+        L.orc_energy_graded_f64.restype = C.c_double
+        L.orc_divergence_graded_f64.argtypes = [_i, _i, _i, _dp, _dp, _dp, _dp, _u8, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -68,6 +82,20 @@ def coefficients(eps_r, sigma, dt, dx, dy, dz):
     return coef, ch
 
 
+def graded_coefficients(eps_r, sigma, dt, dx, dy, dz):
+    """Graded spacing (per-index primal cell sizes dx (nx,), dy (ny,), dz (nz,)):
+    (cag (n_mat, 2) = Ca, G; hc and ec: x, y and z arrays concatenated,
+    (nx+1)+(ny+1)+(nz+1) values) in float64."""
+    eps_r = np.ascontiguousarray(eps_r, dtype=np.float64)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    dx, dy, dz = (np.ascontiguousarray(a, dtype=np.float64) for a in (dx, dy, dz))
+    n = len(dx) + len(dy) + len(dz) + 3
+    cag, hc, ec = np.zeros((len(eps_r), 2)), np.zeros(n), np.zeros(n)
+    lib().orc_graded_coefficients(len(eps_r), eps_r, sigma, dt, len(dx), len(dy), len(dz), dx, dy, dz,
+                                  cag, hc, ec)
+    return cag, hc, ec
+
+
 def zero_fields(nx, ny, nz, dtype=np.float64):
     return np.zeros((6, nz + 1, ny + 1, nx + 1), dtype=dtype)
 
@@ -80,7 +108,7 @@ class Problem:
     """A grid, its material table and per-cell indices, sources and probes."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, dt, eps_r, sigma, mat,
-                 sources=(), waveforms=None, probes=()):
+                 sources=(), waveforms=None, probes=(), spacing=None):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.dx, self.dy, self.dz, self.dt = dx, dy, dz, dt
         self.eps_r = np.ascontiguousarray(eps_r, dtype=np.float64)
@@ -96,11 +124,19 @@ class Problem:
             self.wave64 = np.ascontiguousarray(np.asarray(waveforms, dtype=np.float64).reshape(len(self.src), -1))
         self.wave32 = self.wave64.astype(np.float32)
         self.probe = _points(probes)
+        # graded spacing: per-index primal cell sizes (dx (nx,), dy (ny,), dz (nz,))
+        self.graded = spacing is not None
+        if self.graded:
+            self.sx, self.sy, self.sz = (np.ascontiguousarray(a, dtype=np.float64) for a in spacing)
+            assert (len(self.sx), len(self.sy), len(self.sz)) == (nx, ny, nz)
+            self.cag64, self.hc64, self.ec64 = graded_coefficients(self.eps_r, self.sigma, dt,
+                                                                   self.sx, self.sy, self.sz)
+            self.cag32, self.hc32, self.ec32 = (a.astype(np.float32) for a in (self.cag64, self.hc64, self.ec64))
 
     @classmethod
     def from_workload(cls, wl):
         return cls(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.dt, wl.eps_r, wl.sigma, wl.mat,
-                   wl.sources, wl.waveforms, wl.probes)
+                   wl.sources, wl.waveforms, wl.probes, spacing=getattr(wl, "spacing", None))
 
     @property
     def a_max(self) -> float:
@@ -110,9 +146,14 @@ class Problem:
         """Advance f (float64, in place); returns probes (n_steps, n_probe) float64."""
         assert f.dtype == np.float64 and f.flags.c_contiguous
         out = np.zeros((n_steps, max(len(self.probe), 1)))
-        rc = lib().orc_run_f64(self.nx, self.ny, self.nz, self.ch64, self.coef64, self.mat, f, step0, n_steps,
-                               len(self.src), self.src, self.wave64, self.wave64.shape[1],
-                               len(self.probe), self.probe, out)
+        if self.graded:
+            rc = lib().orc_run_graded_f64(self.nx, self.ny, self.nz, self.hc64, self.cag64, self.ec64, self.mat, f,
+                                          step0, n_steps, len(self.src), self.src, self.wave64,
+                                          self.wave64.shape[1], len(self.probe), self.probe, out)
+        else:
+            rc = lib().orc_run_f64(self.nx, self.ny, self.nz, self.ch64, self.coef64, self.mat, f, step0,
+                                   n_steps, len(self.src), self.src, self.wave64, self.wave64.shape[1],
+                                   len(self.probe), self.probe, out)
         if rc:
             raise ValueError("bad source or probe descriptor")
         return out[:, :len(self.probe)]
@@ -120,9 +161,14 @@ class Problem:
     def run_f32(self, f, step0, n_steps):
         assert f.dtype == np.float32 and f.flags.c_contiguous
         out = np.zeros((n_steps, max(len(self.probe), 1)))
-        rc = lib().orc_run_f32(self.nx, self.ny, self.nz, self.ch32, self.coef32, self.mat, f, step0, n_steps,
-                               len(self.src), self.src, self.wave32, self.wave32.shape[1],
-                               len(self.probe), self.probe, out)
+        if self.graded:
+            rc = lib().orc_run_graded_f32(self.nx, self.ny, self.nz, self.hc32, self.cag32, self.ec32, self.mat, f,
+                                          step0, n_steps, len(self.src), self.src, self.wave32,
+                                          self.wave32.shape[1], len(self.probe), self.probe, out)
+        else:
+            rc = lib().orc_run_f32(self.nx, self.ny, self.nz, self.ch32, self.coef32, self.mat, f, step0,
+                                   n_steps, len(self.src), self.src, self.wave32, self.wave32.shape[1],
+                                   len(self.probe), self.probe, out)
         if rc:
             raise ValueError("bad source or probe descriptor")
         return out[:, :len(self.probe)]
@@ -131,6 +177,7 @@ class Problem:
         """Reduced-storage emulation.  state: dict with 'scales' (6 int32),
         'm_stored' (6 float32), 'flag' (1 int32), updated in place."""
         assert f.dtype == np.float32 and f.flags.c_contiguous
+        assert not self.graded, "reduced storage is emulated on uniform grids only"
         out = np.zeros((n_steps, max(len(self.probe), 1)))
         rc = lib().orc_run_q(self.nx, self.ny, self.nz, fmt, T, self.ch32, self.coef32, self.mat, f, step0,
                              n_steps, len(self.src), self.src, self.wave32, self.wave32.shape[1],
@@ -149,18 +196,36 @@ class Problem:
         return st
 
     def h_half_f64(self, f):
-        lib().orc_h_half_f64(self.nx, self.ny, self.nz, self.ch64, f)
+        if self.graded:
+            lib().orc_h_half_graded_f64(self.nx, self.ny, self.nz, self.hc64, f)
+        else:
+            lib().orc_h_half_f64(self.nx, self.ny, self.nz, self.ch64, f)
 
     def e_half_f64(self, f):
-        lib().orc_e_half_f64(self.nx, self.ny, self.nz, self.coef64, self.mat, f)
+        if self.graded:
+            lib().orc_e_half_graded_f64(self.nx, self.ny, self.nz, self.cag64, self.ec64, self.mat, f)
+        else:
+            lib().orc_e_half_f64(self.nx, self.ny, self.nz, self.coef64, self.mat, f)
 
     def h_half_f32(self, f):
-        lib().orc_h_half_f32(self.nx, self.ny, self.nz, self.ch32, f)
+        if self.graded:
+            lib().orc_h_half_graded_f32(self.nx, self.ny, self.nz, self.hc32, f)
+        else:
+            lib().orc_h_half_f32(self.nx, self.ny, self.nz, self.ch32, f)
 
     def e_half_f32(self, f):
-        lib().orc_e_half_f32(self.nx, self.ny, self.nz, self.coef32, self.mat, f)
+        if self.graded:
+            lib().orc_e_half_graded_f32(self.nx, self.ny, self.nz, self.cag32, self.ec32, self.mat, f)
+        else:
+            lib().orc_e_half_f32(self.nx, self.ny, self.nz, self.coef32, self.mat, f)
 
     def energy(self, f):
+        """Discrete energy (FP64): in units of eps0*dx*dy*dz on uniform grids,
+        of eps0 (volumes in m^3) on graded ones."""
+        if self.graded:
+            f = np.ascontiguousarray(f, dtype=np.float64)
+            return lib().orc_energy_graded_f64(self.nx, self.ny, self.nz, self.sx, self.sy, self.sz, self.hc64,
+                                               self.eps_r, self.mat, f)
         if f.dtype == np.float64:
             return lib().orc_energy_f64(self.nx, self.ny, self.nz, self.ch64, self.eps_r, self.mat, f)
         return lib().orc_energy_f32(self.nx, self.ny, self.nz, self.ch32, self.eps_r, self.mat, f)
@@ -170,8 +235,12 @@ class Problem:
         f = np.ascontiguousarray(f, dtype=np.float64)
         de = np.zeros((self.nz + 1, self.ny + 1, self.nx + 1))
         dh = np.zeros((self.nz, self.ny, self.nx))
-        lib().orc_divergence_f64(self.nx, self.ny, self.nz, self.dx, self.dy, self.dz,
-                                 self.eps_r, self.mat, f, de, dh)
+        if self.graded:
+            lib().orc_divergence_graded_f64(self.nx, self.ny, self.nz, self.sx, self.sy, self.sz,
+                                            self.eps_r, self.mat, f, de, dh)
+        else:
+            lib().orc_divergence_f64(self.nx, self.ny, self.nz, self.dx, self.dy, self.dz,
+                                     self.eps_r, self.mat, f, de, dh)
         return de, dh
 
 

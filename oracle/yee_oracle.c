@@ -600,6 +600,307 @@ void orc_divergence_f64(int nx, int ny, int nz, double dx, double dy, double dz,
             }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Graded (non-uniform) spacing.                                              */
+/*                                                                          */
+/* The paper's loop takes the spacing from one-dimensional per-index        */
+/* coefficient arrays (dy(j), dz(k) in Sec. 2.2).  With primal cell sizes    */
+/* dx[i] (i < nx), dy[j], dz[k], Stokes' theorem on a primal face gives the  */
+/* Faraday update with primal sizes, and on the dual face around an E edge   */
+/* the Ampere update with dual sizes d'[idx] = (d[idx-1] + d[idx]) / 2 at    */
+/* interior nodes:                                                           */
+/*   hc_d[idx] = c dt / d[idx]          idx < n_d      (0 at idx = n_d)      */
+/*   ec_d[idx] = c dt / d'[idx]         0 < idx < n_d  (0 on the walls)      */
+/*   per material: a = sigma dt / (2 eps0 eps_r),                            */
+/*                 Ca = (1 - a) / (1 + a),  G = (1 / eps_r) / (1 + a)        */
+/*   Hx <- Hx + hc_z[k] (Ey(k+1) - Ey(k)) - hc_y[j] (Ez(j+1) - Ez(j))        */
+/*   Ex <- Ca Ex + G ec_y[j] (Hz(j) - Hz(j-1)) - G ec_z[k] (Hy(k) - Hy(k-1)) */
+/* and cyclic.  The FP32 mode forms each E coefficient as one float product  */
+/* cb = G * ec_d[idx] and then follows the uniform mode's fmaf order; the H  */
+/* update is the uniform one with per-index coefficients.                    */
+/* hc and ec hold the x, y and z arrays one after another:                   */
+/* (nx+1) + (ny+1) + (nz+1) values.                                          */
+/* ------------------------------------------------------------------------ */
+void orc_graded_coefficients(int n_mat, const double *eps_r, const double *sigma, double dt,
+                             int nx, int ny, int nz, const double *dx, const double *dy, const double *dz,
+                             double *cag /* n_mat x {Ca, G} */, double *hc, double *ec)
+{
+    for (int m = 0; m < n_mat; m++) {
+        double a = (sigma[m] * dt) / (2.0 * EPS0 * eps_r[m]);
+        cag[2 * m + 0] = (1.0 - a) / (1.0 + a);
+        cag[2 * m + 1] = (1.0 / eps_r[m]) / (1.0 + a);
+    }
+    const int n[3] = {nx, ny, nz};
+    const double *d[3] = {dx, dy, dz};
+    int off = 0;
+    for (int ax = 0; ax < 3; ax++) {
+        for (int q = 0; q <= n[ax]; q++) {
+            hc[off + q] = q < n[ax] ? (C0 * dt) / d[ax][q] : 0.0;
+            ec[off + q] = (q > 0 && q < n[ax]) ? (C0 * dt) / ((d[ax][q - 1] + d[ax][q]) / 2.0) : 0.0;
+        }
+        off += n[ax] + 1;
+    }
+}
+
+void orc_h_half_graded_f64(int nx, int ny, int nz, const double *hc, double *f)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const double *hcx = hc, *hcy = hc + nx + 1, *hcz = hc + nx + 1 + ny + 1;
+    const double *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    double *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                if (in_range(&g, HX, i, j, k))
+                    hx[p] = hx[p] + hcz[k] * (ey[p + g.sz] - ey[p]) - hcy[j] * (ez[p + g.sy] - ez[p]);
+                if (in_range(&g, HY, i, j, k))
+                    hy[p] = hy[p] + hcx[i] * (ez[p + 1] - ez[p]) - hcz[k] * (ex[p + g.sz] - ex[p]);
+                if (in_range(&g, HZ, i, j, k))
+                    hz[p] = hz[p] + hcy[j] * (ex[p + g.sy] - ex[p]) - hcx[i] * (ey[p + 1] - ey[p]);
+            }
+}
+
+void orc_e_half_graded_f64(int nx, int ny, int nz, const double *cag, const double *ec, const uint8_t *mat,
+                           double *f)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const double *ecx = ec, *ecy = ec + nx + 1, *ecz = ec + nx + 1 + ny + 1;
+    double *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    const double *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                int m = (i < nx && j < ny && k < nz) ? mat[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)] : 0;
+                const double ca = cag[2 * m], gm = cag[2 * m + 1];
+                if (e_interior(&g, EX, i, j, k))
+                    ex[p] = ca * ex[p] + gm * ecy[j] * (hz[p] - hz[p - g.sy]) - gm * ecz[k] * (hy[p] - hy[p - g.sz]);
+                if (e_interior(&g, EY, i, j, k))
+                    ey[p] = ca * ey[p] + gm * ecz[k] * (hx[p] - hx[p - g.sz]) - gm * ecx[i] * (hz[p] - hz[p - 1]);
+                if (e_interior(&g, EZ, i, j, k))
+                    ez[p] = ca * ez[p] + gm * ecx[i] * (hy[p] - hy[p - 1]) - gm * ecy[j] * (hx[p] - hx[p - g.sy]);
+            }
+}
+
+void orc_h_half_graded_f32(int nx, int ny, int nz, const float *hc, float *f)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const float *hcx = hc, *hcy = hc + nx + 1, *hcz = hc + nx + 1 + ny + 1;
+    const float *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    float *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                if (in_range(&g, HX, i, j, k)) {
+                    float dey_z = ey[p + g.sz] - ey[p];
+                    float dez_y = ez[p + g.sy] - ez[p];
+                    hx[p] = fmaf(-hcy[j], dez_y, fmaf(hcz[k], dey_z, hx[p]));
+                }
+                if (in_range(&g, HY, i, j, k)) {
+                    float dez_x = ez[p + 1] - ez[p];
+                    float dex_z = ex[p + g.sz] - ex[p];
+                    hy[p] = fmaf(-hcz[k], dex_z, fmaf(hcx[i], dez_x, hy[p]));
+                }
+                if (in_range(&g, HZ, i, j, k)) {
+                    float dex_y = ex[p + g.sy] - ex[p];
+                    float dey_x = ey[p + 1] - ey[p];
+                    hz[p] = fmaf(-hcx[i], dey_x, fmaf(hcy[j], dex_y, hz[p]));
+                }
+            }
+}
+
+void orc_e_half_graded_f32(int nx, int ny, int nz, const float *cag, const float *ec, const uint8_t *mat,
+                           float *f)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const float *ecx = ec, *ecy = ec + nx + 1, *ecz = ec + nx + 1 + ny + 1;
+    float *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    const float *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                int m = (i < nx && j < ny && k < nz) ? mat[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)] : 0;
+                const float ca = cag[2 * m], gm = cag[2 * m + 1];
+                if (e_interior(&g, EX, i, j, k)) {
+                    float cby = gm * ecy[j], cbz = gm * ecz[k];
+                    float dhz_y = hz[p] - hz[p - g.sy];
+                    float dhy_z = hy[p] - hy[p - g.sz];
+                    float t = ca * ex[p];
+                    t = fmaf(cby, dhz_y, t);
+                    ex[p] = fmaf(-cbz, dhy_z, t);
+                }
+                if (e_interior(&g, EY, i, j, k)) {
+                    float cbz = gm * ecz[k], cbx = gm * ecx[i];
+                    float dhx_z = hx[p] - hx[p - g.sz];
+                    float dhz_x = hz[p] - hz[p - 1];
+                    float t = ca * ey[p];
+                    t = fmaf(cbz, dhx_z, t);
+                    ey[p] = fmaf(-cbx, dhz_x, t);
+                }
+                if (e_interior(&g, EZ, i, j, k)) {
+                    float cbx = gm * ecx[i], cby = gm * ecy[j];
+                    float dhy_x = hy[p] - hy[p - 1];
+                    float dhx_y = hx[p] - hx[p - g.sy];
+                    float t = ca * ez[p];
+                    t = fmaf(cbx, dhy_x, t);
+                    ez[p] = fmaf(-cby, dhx_y, t);
+                }
+            }
+}
+
+int orc_run_graded_f64(int nx, int ny, int nz, const double *hc, const double *cag, const double *ec,
+                       const uint8_t *mat, double *f, long step0, int n_steps,
+                       int n_src, const int *src, const double *wave, int n_wave,
+                       int n_probe, const int *probe, double *probe_out)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    if (check_points(&g, n_src, src, 1) || check_points(&g, n_probe, probe, 0)) return -1;
+    for (int s = 0; s < n_steps; s++) {
+        long n = step0 + s;
+        orc_h_half_graded_f64(nx, ny, nz, hc, f);
+        orc_e_half_graded_f64(nx, ny, nz, cag, ec, mat, f);
+        for (int q = 0; q < n_src; q++) {
+            if (n < n_wave) {
+                const int *d = src + 4 * q;
+                f[(size_t)d[0] * g.n + at(&g, d[1], d[2], d[3])] += wave[(size_t)q * n_wave + n];
+            }
+        }
+        for (int q = 0; q < n_probe; q++) {
+            const int *d = probe + 4 * q;
+            probe_out[(size_t)s * n_probe + q] = f[(size_t)d[0] * g.n + at(&g, d[1], d[2], d[3])];
+        }
+    }
+    return 0;
+}
+
+int orc_run_graded_f32(int nx, int ny, int nz, const float *hc, const float *cag, const float *ec,
+                       const uint8_t *mat, float *f, long step0, int n_steps,
+                       int n_src, const int *src, const float *wave, int n_wave,
+                       int n_probe, const int *probe, double *probe_out)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    if (check_points(&g, n_src, src, 1) || check_points(&g, n_probe, probe, 0)) return -1;
+    for (int s = 0; s < n_steps; s++) {
+        long n = step0 + s;
+        orc_h_half_graded_f32(nx, ny, nz, hc, f);
+        orc_e_half_graded_f32(nx, ny, nz, cag, ec, mat, f);
+        for (int q = 0; q < n_src; q++) {
+            if (n < n_wave) {
+                const int *d = src + 4 * q;
+                size_t p = (size_t)d[0] * g.n + at(&g, d[1], d[2], d[3]);
+                f[p] = f[p] + wave[(size_t)q * n_wave + n];
+            }
+        }
+        for (int q = 0; q < n_probe; q++) {
+            const int *d = probe + 4 * q;
+            probe_out[(size_t)s * n_probe + q] = (double)f[(size_t)d[0] * g.n + at(&g, d[1], d[2], d[3])];
+        }
+    }
+    return 0;
+}
+
+/* Graded energy and divergence (FP64).  Dual sizes on the walls are half    */
+/* cells.  With V_e = (edge length) x (dual face area) for E and            */
+/* V_f = (face area) x (dual edge length) for H,                             */
+/*   W = 1/2 sum_e eps_r E_e^2 V_e + 1/2 sum_f H_f^{n-1/2} H_f^{n+1/2} V_f   */
+/* in units of eps0 (volumes in m^3) is conserved by a lossless PEC box;     */
+/*   div_e(node) = sum_d (eps_r E_d(node) - eps_r E_d(node - e_d)) / d'_d    */
+/*   div_h(cell) = sum_d (H_d(cell + e_d) - H_d(cell)) / d_d                 */
+/* stay constant without sources.                                            */
+static void dual_sizes(int n, const double *d, double *dd)
+{
+    for (int q = 0; q <= n; q++)
+        dd[q] = q == 0 ? d[0] / 2.0 : (q == n ? d[n - 1] / 2.0 : (d[q - 1] + d[q]) / 2.0);
+}
+
+double orc_energy_graded_f64(int nx, int ny, int nz, const double *dx, const double *dy, const double *dz,
+                             const double *hc, const double *eps_r, const uint8_t *mat, const double *f)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    double *tmp = (double *)malloc(6 * g.n * sizeof(double));
+    memcpy(tmp, f, 6 * g.n * sizeof(double));
+    orc_h_half_graded_f64(nx, ny, nz, hc, tmp);
+    double *dxd = (double *)malloc(((size_t)nx + ny + nz + 3) * sizeof(double));
+    double *dyd = dxd + nx + 1, *dzd = dyd + ny + 1;
+    dual_sizes(nx, dx, dxd);
+    dual_sizes(ny, dy, dyd);
+    dual_sizes(nz, dz, dzd);
+    double *plane = (double *)calloc((size_t)nz + 1, sizeof(double));
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++) {
+        double acc = 0.0;
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                const double ve[3] = {
+                    i < nx ? dx[i] * dyd[j] * dzd[k] : 0.0,
+                    j < ny ? dxd[i] * dy[j] * dzd[k] : 0.0,
+                    k < nz ? dxd[i] * dyd[j] * dz[k] : 0.0};
+                const double vh[3] = {
+                    (j < ny && k < nz) ? dxd[i] * dy[j] * dz[k] : 0.0,
+                    (i < nx && k < nz) ? dx[i] * dyd[j] * dz[k] : 0.0,
+                    (i < nx && j < ny) ? dx[i] * dy[j] * dzd[k] : 0.0};
+                for (int c = 0; c < 3; c++) {
+                    double v = f[(size_t)c * g.n + p];
+                    acc += 0.5 * edge_eps(&g, eps_r, mat, c, i, j, k) * v * v * ve[c];
+                }
+                for (int c = 0; c < 3; c++)
+                    if (in_range(&g, HX + c, i, j, k))
+                        acc += 0.5 * f[(size_t)(3 + c) * g.n + p] * tmp[(size_t)(3 + c) * g.n + p] * vh[c];
+            }
+        plane[k] = acc;
+    }
+    double w = 0.0;
+    for (int k = 0; k <= nz; k++) w += plane[k];
+    free(plane);
+    free(dxd);
+    free(tmp);
+    return w;
+}
+
+void orc_divergence_graded_f64(int nx, int ny, int nz, const double *dx, const double *dy, const double *dz,
+                               const double *eps_r, const uint8_t *mat, const double *f,
+                               double *div_e, double *div_h)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const double *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    const double *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    double *dxd = (double *)malloc(((size_t)nx + ny + nz + 3) * sizeof(double));
+    double *dyd = dxd + nx + 1, *dzd = dyd + ny + 1;
+    dual_sizes(nx, dx, dxd);
+    dual_sizes(ny, dy, dyd);
+    dual_sizes(nz, dz, dzd);
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                double d = 0.0;
+                if (i > 0 && i < nx && j > 0 && j < ny && k > 0 && k < nz) {
+                    d += (edge_eps(&g, eps_r, mat, EX, i, j, k) * ex[p]
+                          - edge_eps(&g, eps_r, mat, EX, i - 1, j, k) * ex[p - 1]) / dxd[i];
+                    d += (edge_eps(&g, eps_r, mat, EY, i, j, k) * ey[p]
+                          - edge_eps(&g, eps_r, mat, EY, i, j - 1, k) * ey[p - g.sy]) / dyd[j];
+                    d += (edge_eps(&g, eps_r, mat, EZ, i, j, k) * ez[p]
+                          - edge_eps(&g, eps_r, mat, EZ, i, j, k - 1) * ez[p - g.sz]) / dzd[k];
+                }
+                div_e[p] = d;
+                if (i < nx && j < ny && k < nz) {
+                    double dh = (hx[p + 1] - hx[p]) / dx[i] + (hy[p + g.sy] - hy[p]) / dy[j]
+                              + (hz[p + g.sz] - hz[p]) / dz[k];
+                    div_h[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)] = dh;
+                }
+            }
+    free(dxd);
+}
+
 /* Number of threads the parallel loops use (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>
