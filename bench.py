@@ -221,6 +221,18 @@ def main():
         extras["bf16_store"] = {"value": vbf, "T": serve.DEFAULT_T[W.BF16], "ratio_vs_fp32": vbf / value}
         print(f"[bench] fp16 (T={t16}): {v16:.2f} G cell-updates/s, x{v16 / value:.2f}; matched T=4 "
               f"x{v16_4 / value:.2f}, T=1 x{v16_1 / v32_1:.2f}; bf16 {vbf:.2f}", file=sys.stderr, flush=True)
+        # graded cell sizes (per-index coefficient arrays), FP32, automatic T and tile shape
+        wg = W.graded256()
+        sg = fdtd.Solver.from_workload(wg)
+        try:
+            if args.warmup:
+                sg.step(args.warmup)
+            vg = wg.cells * args.steps / time_steps(sg, args.steps, torch, stream) / 1e9
+        finally:
+            sg.close()
+        extras["graded_spacing"] = {"workload": wg.name, "value": vg, "unit": "G cell-updates/s",
+                                    "ratio_vs_uniform": vg / value}
+        print(f"[bench] graded spacing ({wg.name}): {vg:.2f} G cell-updates/s", file=sys.stderr, flush=True)
         # a full solve from host buffers: create (material upload), upload of a
         # host initial state, the solve, read-back of fields and probes
         torch.cuda.synchronize()

@@ -123,10 +123,27 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz,
                 const uint8_t *mat_index, int storage,
                 void *device_workspace, size_t workspace_bytes, void *hip_stream);
 
+/* Graded spacing: per-index cell sizes (metres) dx[nx], dy[ny], dz[nz]
+ * replace the uniform dx, dy, dz of fdtd_create.  The coefficients stay
+ * one-dimensional, as in the loop of Sec. 2.2: the Faraday update of a face
+ * uses c dt / (its cell sizes), and the Ampere update of an edge uses
+ * c dt / (dual sizes), a dual size being the mean of the two cells that meet
+ * at the node (Stokes' theorem on the dual face, Sec. 2.1).  Each E
+ * coefficient is formed in FP32 as G * (c dt / dual size) with
+ * G = (1/eps_r) / (1 + sigma dt / (2 eps0 eps_r)).
+ *   Sizes > 0 and finite; dt must satisfy the Courant bound of the smallest
+ *   size on each axis (else FDTD_ECFL; sufficient for such grids).  FP32
+ *   storage only (else FDTD_EINVAL); only before the first step
+ *   (FDTD_ESTATE); may be called again to replace the sizes.  Arrays are
+ *   copied.  Graded solvers run with fdtd_step (PLAIN or FUSED, any T);
+ *   fdtd_step_batch and fdtd_diagnostics reject them (FDTD_EINVAL). */
+int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const double *dz);
+
 /* Kernel family (fdtd_kernel) and steps per HBM pass T for the FUSED family:
  * 1..4, or 0 = automatic (the default after fdtd_create): 4 for FP32
- * storage and 3 for FP16/BF16 storage, the fastest on MI355X, lowered for
- * grids whose planes are too large for that T.  Allowed before the first
+ * storage, 3 for FP16/BF16 storage and for graded spacing, the fastest on
+ * MI355X, lowered for grids whose planes are too large for that T (an
+ * automatic T is chosen again by fdtd_set_spacing).  Allowed before the first
  * step and between steps.  Results do not depend on T for FP32 storage; for
  * FP16/BF16 storage, T sets where values are re-quantised (every T steps). */
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
@@ -210,6 +227,15 @@ const char *fdtd_last_error(void);
 int fdtd_coefficients(const fdtd_material *table, int n_materials,
                       double dx, double dy, double dz, double dt,
                       float *out, float *ch);
+
+/* FP32 coefficients of graded spacing (see fdtd_set_spacing): cag gets
+ * n_materials x {Ca, G}; gc gets, per node index of x (nx+1 entries), then
+ * y (ny+1), then z (nz+1), the pair {c dt / d[q] (0 at q = n),
+ * c dt / ((d[q-1] + d[q]) / 2) (0 at q = 0 and q = n)}, each rounded once
+ * from FP64.  Host-only; no device is needed. */
+int fdtd_graded_coefficients(const fdtd_material *table, int n_materials, int nx, int ny, int nz,
+                             const double *dx, const double *dy, const double *dz, double dt,
+                             float *cag, float *gc);
 
 #ifdef __cplusplus
 }

@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtd.so")
-SOURCES = ["yee_fused_f32.hip", "yee_fused_f16.hip", "yee_fused_bf16.hip", "fdtd_runtime.cpp",
-           "yee_plain.hip", "yee_fused.hip", "yee_diag.hip"]
+SOURCES = ["yee_fused_f32.hip", "yee_fused_f16.hip", "yee_fused_bf16.hip", "yee_fused_graded.hip",
+           "fdtd_runtime.cpp", "yee_plain.hip", "yee_fused.hip", "yee_diag.hip"]
 
 
 def hipcc_flags():
@@ -26,7 +26,7 @@ def hipcc_flags():
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose: bool = False, jobs: int = 7) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)

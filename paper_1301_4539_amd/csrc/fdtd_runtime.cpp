@@ -183,6 +183,7 @@ struct fdtd_solver {
     int storage = FDTD_FP32;
     int kernel = FDTD_KERNEL_AUTO;
     int T = 1;                          // set by fdtd_create (automatic) or fdtd_set_kernel
+    bool T_auto = true;                 // T chosen automatically (re-chosen by fdtd_set_spacing)
     int tiling = 0;                     // fused-kernel tile shape: 0 = auto, 1..3 = explicit
     int zchunk = 0;                     // planes per z chunk (0 = automatic)
     hipStream_t st = nullptr;
@@ -196,8 +197,12 @@ struct fdtd_solver {
     float coef_h[256 * 4];
     float ch[3];
     double eps_h[256];
+    double sig_h[256];
     float4 *coef_d = nullptr;
     double *eps_d = nullptr;
+    // graded spacing (fdtd_set_spacing): per-index (c dt / primal size,
+    // c dt / dual size) pairs, x then y then z; null while the grid is uniform
+    float2 *gc_d = nullptr;
     int cur = 0;
     long long steps = 0;
     long long block = 0;                // reduced-storage blocks run since the last upload
@@ -311,7 +316,7 @@ yee::StorageBlock storage_block(const fdtd_solver *s)
 }
 
 
-int auto_T(const fdtd_solver *s) { return yee::fastest_T(s->L, s->storage); }
+int auto_T(const fdtd_solver *s) { return yee::fastest_T(s->L, s->storage, s->gc_d != nullptr); }
 
 // Allocate the pinned staging buffers on first use (freed by fdtd_destroy).
 int ensure_staging(fdtd_solver *s)
@@ -366,6 +371,7 @@ void fill_fused(const fdtd_solver *s, yee::FusedArgs *a)
     a->chx = s->ch[0];
     a->chy = s->ch[1];
     a->chz = s->ch[2];
+    a->gc = s->gc_d;
     a->src = src_table(s);
     a->probe = probe_table(s);
     a->fin = s->fbuf[s->cur];
@@ -417,6 +423,39 @@ int fdtd_coefficients(const fdtd_material *table, int n_materials, double dx, do
     return FDTD_OK;
 }
 
+int fdtd_graded_coefficients(const fdtd_material *table, int n_materials, int nx, int ny, int nz,
+                             const double *dx, const double *dy, const double *dz, double dt,
+                             float *cag, float *gc)
+{
+    if (!table || !cag || !gc || !dx || !dy || !dz || n_materials < 1 || n_materials > 256)
+        return fail(FDTD_EINVAL, "NULL argument or bad table");
+    if (nx < 2 || ny < 2 || nz < 2 || !(dt > 0)) return fail(FDTD_EINVAL, "bad dimensions or dt");
+    for (int m = 0; m < n_materials; ++m) {
+        const double eps = table[m].eps_r, sig = table[m].sigma;
+        if (!(eps > 0) || !(sig >= 0) || table[m].mu_r != 1.0)
+            return fail(FDTD_EINVAL, "material " + std::to_string(m) + ": need eps_r > 0, sigma >= 0, mu_r = 1");
+        const double a = (sig * dt) / (2.0 * EPS0 * eps);
+        cag[2 * m + 0] = (float)((1.0 - a) / (1.0 + a));
+        cag[2 * m + 1] = (float)((1.0 / eps) / (1.0 + a));
+    }
+    const int n[3] = {nx, ny, nz};
+    const double *d[3] = {dx, dy, dz};
+    const double cdt = C0 * dt;
+    float *g = gc;
+    for (int ax = 0; ax < 3; ++ax) {
+        for (int q = 0; q < n[ax]; ++q)
+            if (!(d[ax][q] > 0) || !std::isfinite(d[ax][q])) return fail(FDTD_EINVAL, "cell sizes must be > 0");
+        // node q: primal factor of cell q (none past the last node), dual
+        // factor of the mean of cells q-1 and q (none on the walls)
+        for (int q = 0; q <= n[ax]; ++q) {
+            g[2 * q + 0] = q < n[ax] ? (float)(cdt / d[ax][q]) : 0.0f;
+            g[2 * q + 1] = (q > 0 && q < n[ax]) ? (float)(cdt / ((d[ax][q - 1] + d[ax][q]) / 2.0)) : 0.0f;
+        }
+        g += 2 * (n[ax] + 1);
+    }
+    return FDTD_OK;
+}
+
 int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy, double dz, double dt,
                 const fdtd_material *table, int n_materials, const uint8_t *mat_index, int storage,
                 void *device_workspace, size_t workspace_bytes, void *hip_stream)
@@ -441,7 +480,10 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy,
                 return fail(FDTD_EINVAL, "material index " + std::to_string(mat_index[q]) + " >= n_materials");
             }
     s->n_mat = n_materials;
-    for (int m = 0; m < n_materials; ++m) s->eps_h[m] = table[m].eps_r;
+    for (int m = 0; m < n_materials; ++m) {
+        s->eps_h[m] = table[m].eps_r;
+        s->sig_h[m] = table[m].sigma;
+    }
     s->dx = dx; s->dy = dy; s->dz = dz; s->dt = dt;
     s->storage = storage;
     s->st = (hipStream_t)hip_stream;
@@ -502,12 +544,58 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy,
     return FDTD_OK;
 }
 
+int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const double *dz)
+{
+    if (!s || !dx || !dy || !dz) return fail(FDTD_EINVAL, "NULL argument");
+    if (s->steps > 0) return fail(FDTD_ESTATE, "spacing must be set before the first step");
+    if (s->storage != FDTD_FP32) return fail(FDTD_EINVAL, "graded spacing needs FP32 storage");
+    const int nx = s->L.nx, ny = s->L.ny, nz = s->L.nz;
+    fdtd_material table[256];
+    for (int m = 0; m < s->n_mat; ++m) {
+        table[m].eps_r = s->eps_h[m];
+        table[m].mu_r = 1.0;
+        table[m].sigma = s->sig_h[m];
+    }
+    float cag[2 * 256];
+    std::vector<float> gc(2 * (size_t)(nx + ny + nz + 3));
+    int rc = fdtd_graded_coefficients(table, s->n_mat, nx, ny, nz, dx, dy, dz, s->dt, cag, gc.data());
+    if (rc) return rc;
+    // Courant bound of the smallest size per axis.  Sufficient: along an axis
+    // the second difference through node q (dual size = mean of cells q-1
+    // and q) has row sum 4 / (d[q-1] d[q]) <= 4 / min d^2, and the curl-curl
+    // operator of a tensor-product grid is bounded by the sum over axes.
+    const double mx = *std::min_element(dx, dx + nx), my = *std::min_element(dy, dy + ny),
+                 mz = *std::min_element(dz, dz + nz);
+    const double limit = 1.0 / (C0 * std::sqrt(1.0 / (mx * mx) + 1.0 / (my * my) + 1.0 / (mz * mz)));
+    if (s->dt > limit) return fail(FDTD_ECFL, "dt exceeds the Courant limit " + std::to_string(limit) +
+                                              " of the smallest cells");
+    float coef[256 * 4];
+    for (int m = 0; m < s->n_mat; ++m) {
+        coef[4 * m + 0] = cag[2 * m + 0];
+        coef[4 * m + 1] = cag[2 * m + 1];
+        coef[4 * m + 2] = coef[4 * m + 3] = 0.0f;
+    }
+    hipError_t e;
+    if (!s->gc_d && (e = hipMalloc(&s->gc_d, gc.size() * sizeof(float)))) {
+        s->gc_d = nullptr;
+        return hip_fail(e, "hipMalloc(graded coefficients)");
+    }
+    if ((e = hipMemcpyAsync(s->gc_d, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipMemcpyAsync(s->coef_d, coef, s->n_mat * sizeof(float4), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipStreamSynchronize(s->st)))
+        return hip_fail(e, "upload graded coefficients");
+    std::memcpy(s->coef_h, coef, s->n_mat * 4 * sizeof(float));
+    if (s->T_auto) s->T = auto_T(s);
+    return FDTD_OK;
+}
+
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
 {
     if (!s) return fail(FDTD_EINVAL, "solver is NULL");
     if (kernel < 0 || kernel > 2) return fail(FDTD_EINVAL, "bad kernel family");
     if (time_block < 0 || time_block > 4) return fail(FDTD_EINVAL, "time_block must be 0 (automatic) or 1..4");
-    if (time_block == 0) time_block = auto_T(s);
+    const bool automatic = time_block == 0;
+    if (automatic) time_block = auto_T(s);
     if (kernel == FDTD_KERNEL_AUTO)   // AUTO lowers T to what the grid allows (plain if nothing fits)
         while (time_block > 1 && !yee::fused_fits(s->L, s->storage, time_block)) --time_block;
     if (kernel == FDTD_KERNEL_PLAIN && s->storage != FDTD_FP32)
@@ -516,6 +604,7 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
         return fail(FDTD_EINVAL, "grid planes too large for the fused kernel; use the plain kernel");
     s->kernel = kernel;
     s->T = time_block;
+    s->T_auto = automatic;
     return FDTD_OK;
 }
 
@@ -693,6 +782,7 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         a.coef = s->coef_d;
         a.n_mat = s->n_mat;
         a.chx = s->ch[0]; a.chy = s->ch[1]; a.chz = s->ch[2];
+        a.gc = s->gc_d;
         for (int q = 0; q < n_steps; ++q) {
             if ((e = yee::launch_plain_step(a, src, probe, s->steps + q, s->st))) return hip_fail(e, "plain step");
         }
@@ -704,7 +794,7 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         const int len = next_block(s, left);
         yee::FusedArgs a;
         fill_fused(s, &a);
-        const int shape = s->tiling > 0 ? s->tiling - 1 : yee::auto_shape(s->storage, len);
+        const int shape = s->tiling > 0 ? s->tiling - 1 : yee::auto_shape(s->storage, len, s->gc_d != nullptr);
         if (!yee::fused_fits(s->L, s->storage, len))      // never launch a chunk beyond its addressing
             return fail(FDTD_EINVAL, "grid planes too large for the fused kernel at this T");
         if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
@@ -726,6 +816,7 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
         if (s->st != st) return fail(FDTD_EINVAL, "batched solvers must share one stream");
         if (s->kernel == FDTD_KERNEL_PLAIN || !yee::fused_fits(s->L, s->storage, s->T))
             return fail(FDTD_EINVAL, "batched steps use the fused kernel");
+        if (s->gc_d) return fail(FDTD_EINVAL, "graded-spacing solvers are stepped alone (fdtd_step)");
         if (n_steps[i] < 0) return fail(FDTD_EINVAL, "negative step count");
         for (int j = 0; j < i; ++j)
             if (solvers[j] == s) return fail(FDTD_EINVAL, "a solver appears twice in the batch");
@@ -837,6 +928,7 @@ int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int
 int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
 {
     if (!s || !out) return fail(FDTD_EINVAL, "NULL argument");
+    if (s->gc_d) return fail(FDTD_EINVAL, "diagnostics are for uniform spacing only");
     hipError_t e;
     if (!s->diag_part_d) {
         const size_t nb = (size_t)yee::diag_blocks(s->L);
@@ -915,6 +1007,7 @@ void fdtd_destroy(fdtd_solver *s)
     if (s->own_ws) free_dev(s->ws);
     free_dev(s->coef_d);
     free_dev(s->eps_d);
+    free_dev(s->gc_d);
     free_dev(s->src_pos_d);
     free_dev(s->src_wave_d);
     free_dev(s->samples_d);

@@ -9,12 +9,18 @@ namespace yee {
 hipError_t launch_fused_f32(int T, const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st);
 hipError_t launch_fused_f16(int T, const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st);
 hipError_t launch_fused_bf16(int T, const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st);
+hipError_t launch_fused_f32_graded(int T, const FusedArgs *a, int n, bool batch, int variant, int zc,
+                                   hipStream_t st);
 
 namespace {
 
 hipError_t launch_any(int storage, int T, const FusedArgs *a, int n, bool batch, int variant, int zc,
                       hipStream_t st)
 {
+    if (a->gc) {   // graded spacing: FP32 storage, one solve per launch
+        if (storage != 0 || batch) return hipErrorInvalidValue;
+        return launch_fused_f32_graded(T, a, n, batch, variant, zc, st);
+    }
     switch (storage) {
     case 0: return launch_fused_f32(T, a, n, batch, variant, zc, st);
     case 1: return launch_fused_f16(T, a, n, batch, variant, zc, st);
@@ -28,20 +34,24 @@ hipError_t launch_any(int storage, int T, const FusedArgs *a, int n, bool batch,
 // Fastest tile shape per (storage, T) measured on MI355X with the 256^3 and
 // 512^3 dielectric workloads (shape indices of the fused kernel's tile table:
 // 0 = 2 rows x 16 waves, 1 = 4 x 8, 2 = 3 x 12; 4 x 4, 2 x 8, 2 x 16 for T=1).
-int auto_shape(int storage, int T)
+// Graded spacing (FP32) was measured on its own 256^3 workload.
+int auto_shape(int storage, int T, bool graded)
 {
     static const int f32[5] = {0, 2, 1, 1, 0};
+    static const int f32g[5] = {0, 0, 1, 0, 2};
     static const int f16[5] = {0, 2, 0, 0, 0};
     static const int bf16[5] = {0, 2, 0, 0, 1};
-    return storage == 0 ? f32[T] : storage == 1 ? f16[T] : bf16[T];
+    if (storage == 0) return graded ? f32g[T] : f32[T];
+    return storage == 1 ? f16[T] : bf16[T];
 }
 
 // Fastest steps per pass on MI355X for the storage format (FP32 storage is
-// compute-bound at 4, 16-bit storage at 3), lowered while the grid's planes
+// compute-bound at 4, 16-bit storage at 3; graded spacing at 3, where its
+// extra registers push T = 4 into spills), lowered while the grid's planes
 // are too large for the fused kernel's addressing.
-int fastest_T(const Layout &L, int storage)
+int fastest_T(const Layout &L, int storage, bool graded)
 {
-    int T = storage == 0 ? 4 : 3;
+    int T = storage == 0 && !graded ? 4 : 3;
     while (T > 1 && !fused_fits(L, storage, T)) --T;
     return T;
 }

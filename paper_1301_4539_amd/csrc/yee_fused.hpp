@@ -22,6 +22,12 @@
 // an in-place update would race with neighbouring tiles still reading the
 // old time level.
 //
+// Graded spacing (GR): the c dt / size factors come from per-index arrays --
+// x per lane and y per row, both fixed for the tile and held in registers,
+// and z per plane, loaded with the plane prefetch and shifted through the
+// levels like the material indices.  An E coefficient is the material's G
+// times the dual-size factor, formed in FP32 before its fma.
+//
 // Addressing: every array is read through a buffer resource based at the
 // chunk's first plane; the per-lane x offset lives in one VGPR and the plane
 // and row offsets are scalar, so a load costs one instruction.  Halo lanes
@@ -41,6 +47,11 @@ namespace yee {
 namespace {
 
 constexpr int BUF_FLAGS = 0x00020000;   // raw (untyped) dword buffer, gfx9 word 3
+
+// Read-only data at wave-uniform addresses, read through the constant address
+// space so that the loads are scalar (s_load) and leave the vector memory
+// counter to the plane prefetch.
+typedef __attribute__((address_space(4))) const float ConstFloat;
 
 __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void *base, long long bytes)
 {
@@ -104,7 +115,7 @@ struct TileShared {
 // `logical` is the tile index within the solve.  Starts and ends with every
 // thread of the workgroup in step, so a workgroup may run several tiles in a
 // row (the batched kernel does).
-template <int T, int RY, int NW, class Codec>
+template <int T, int RY, int NW, class Codec, bool GR = false>
 __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical, TileShared<T, NW> &sm)
 {
     constexpr int OX = 64 - 2 * T;      // owned points per tile in x
@@ -216,6 +227,25 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
 #pragma unroll
     for (int r = 0; r < RY; ++r) rowoff[r] = min(max(yw + r, 0), ny) * L.pitch;
 
+    // graded spacing: (c dt / primal size, c dt / dual size) of this lane's x,
+    // of each row's y (uniform per wave) and of each level's z plane
+    float gxh = 0.0f, gxe = 0.0f, gyh[RY], gye[RY], gzh[T + 1], gze[T + 1];
+    float2 PZ = make_float2(0.0f, 0.0f);
+    ConstFloat *const gcu = (ConstFloat *)a.gc;   // pairs: element 2q, 2q+1
+    if constexpr (GR) {
+        const float2 gx = a.gc[xc];
+        gxh = gx.x;
+        gxe = gx.y;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int q = 2 * (nx + 1 + min(max(yw + r, 0), ny));
+            gyh[r] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, gcu[q])));
+            gye[r] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, gcu[q + 1])));
+        }
+#pragma unroll
+        for (int t = 0; t <= T; ++t) gzh[t] = gze[t] = 0.0f;
+    }
+
     float E[T + 1][3][RY], H[T + 1][3][RY];
     // Material indices of the planes the levels are on, one byte per level:
     // byte t of MP[r] is the index of plane K-t (level t's plane) in row r.
@@ -246,6 +276,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
             }                                                                               \
             PM[r] = __builtin_amdgcn_raw_buffer_load_b8(rmat, vom, mofs_ + rowoff[r], 0);   \
         }                                                                                   \
+        if constexpr (GR) PZ = make_float2(gcu[2 * (nx + ny + 2 + (KK))],                   \
+                                           gcu[2 * (nx + ny + 2 + (KK)) + 1]);              \
     } while (0)
 
     YEE_LOAD_PLANE(kb);
@@ -284,6 +316,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         constexpr bool INNER = decltype(inner_c)::value;
         // Level 0 takes plane K; plane K-1 of level 0 becomes level 1's input.
         float Eo[3][RY], Ho[3][RY];
+        if constexpr (GR) {
+#pragma unroll
+            for (int t = T; t > 0; --t) {
+                gzh[t] = gzh[t - 1];
+                gze[t] = gze[t - 1];
+            }
+            gzh[0] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, PZ.x)));
+            gze[0] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, PZ.y)));
+        }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             MP[r] = (MP[r] << 8) | (MPack)PM[r];
@@ -317,23 +358,25 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                 // row above comes from the other exchange buffer without a barrier.
                 const float2 eup = NW > 1 ? s_e[rb][t - 1][w + 1][lane] : make_float2(0.0f, 0.0f);
                 float Hn[3][RY];
+                const float chz = GR ? gzh[t] : a.chz;
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
                     const int y = yw + r;
                     const bool yin = y >= 0 && y <= ny;
+                    const float chx = GR ? gxh : a.chx, chy = GR ? gyh[r] : a.chy;
                     const float exu = r + 1 < RY ? Eo[0][(r + 1) % RY] : eup.x;
                     const float ezu = r + 1 < RY ? Eo[2][(r + 1) % RY] : eup.y;
                     const float ezr = from_right(Eo[2][r]);
                     const float eyr = from_right(Eo[1][r]);
                     const float dey_z = E[t - 1][1][r] - Eo[1][r];
                     const float dez_y = ezu - Eo[2][r];
-                    const float hx = __builtin_fmaf(-a.chy, dez_y, __builtin_fmaf(a.chz, dey_z, Ho[0][r]));
+                    const float hx = __builtin_fmaf(-chy, dez_y, __builtin_fmaf(chz, dey_z, Ho[0][r]));
                     const float dez_x = ezr - Eo[2][r];
                     const float dex_z = E[t - 1][0][r] - Eo[0][r];
-                    const float hy = __builtin_fmaf(-a.chz, dex_z, __builtin_fmaf(a.chx, dez_x, Ho[1][r]));
+                    const float hy = __builtin_fmaf(-chz, dex_z, __builtin_fmaf(chx, dez_x, Ho[1][r]));
                     const float dex_y = exu - Eo[0][r];
                     const float dey_x = eyr - Eo[1][r];
-                    const float hz = __builtin_fmaf(-a.chx, dey_x, __builtin_fmaf(a.chy, dex_y, Ho[2][r]));
+                    const float hz = __builtin_fmaf(-chx, dey_x, __builtin_fmaf(chy, dex_y, Ho[2][r]));
                     if constexpr (INNER) {
                         Hn[0][r] = plt ? hx : Ho[0][r];
                         Hn[1][r] = plt ? hy : Ho[1][r];
@@ -356,15 +399,21 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     const float hzl = from_left(Hn[2][r]);
                     const float hyl = from_left(Hn[1][r]);
                     const float4 cf = s_coef[(uint32_t)(MP[r] >> (8 * t)) & 0xffu];
+                    float cbx = cf.y, cby = cf.z, cbz = cf.w;
+                    if constexpr (GR) {   // cf.y holds G
+                        cbx = cf.y * gxe;
+                        cby = cf.y * gye[r];
+                        cbz = cf.y * gze[t];
+                    }
                     const float dhz_y = Hn[2][r] - hzd;
                     const float dhy_z = Hn[1][r] - H[t][1][r];
-                    const float ex = __builtin_fmaf(-cf.w, dhy_z, __builtin_fmaf(cf.z, dhz_y, cf.x * Eo[0][r]));
+                    const float ex = __builtin_fmaf(-cbz, dhy_z, __builtin_fmaf(cby, dhz_y, cf.x * Eo[0][r]));
                     const float dhx_z = Hn[0][r] - H[t][0][r];
                     const float dhz_x = Hn[2][r] - hzl;
-                    const float ey = __builtin_fmaf(-cf.y, dhz_x, __builtin_fmaf(cf.w, dhx_z, cf.x * Eo[1][r]));
+                    const float ey = __builtin_fmaf(-cbx, dhz_x, __builtin_fmaf(cbz, dhx_z, cf.x * Eo[1][r]));
                     const float dhy_x = Hn[1][r] - hyl;
                     const float dhx_y = Hn[0][r] - hxd;
-                    const float ez = __builtin_fmaf(-cf.z, dhx_y, __builtin_fmaf(cf.y, dhy_x, cf.x * Eo[2][r]));
+                    const float ez = __builtin_fmaf(-cby, dhx_y, __builtin_fmaf(cbx, dhy_x, cf.x * Eo[2][r]));
                     if constexpr (INNER) {
                         En[0][r] = pint ? ex : Eo[0][r];
                         En[1][r] = pint ? ey : Eo[1][r];
@@ -507,7 +556,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     __syncthreads();   // LDS is reused by the next tile of a batched launch
 }
 
-template <int T, int RY, int NW, class Codec>
+template <int T, int RY, int NW, class Codec, bool GR>
 __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
 {
     __shared__ TileShared<T, NW> sm;
@@ -516,7 +565,7 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     const int nb = gridDim.x, b = blockIdx.x;
     const int logical = (b & 7) * (nb >> 3) + (b >> 3);
     if (logical >= a.nwg) return;   // uniform per workgroup
-    fused_tile<T, RY, NW, Codec>(a, logical, sm);
+    fused_tile<T, RY, NW, Codec, GR>(a, logical, sm);
 }
 
 // Several solves in one persistent launch: the workgroups stride over the
@@ -601,17 +650,17 @@ int resident_slots(K kernel, int threads)
     return cus * per_cu;
 }
 
-template <int T, int V, class Codec>
+template <int T, int V, class Codec, bool GR>
 hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
 {
     constexpr Tiling tl = kTilings[T][V];
-    static const int slots = resident_slots(yee_fused<T, tl.ry, tl.nw, Codec>, 64 * tl.nw);
+    static const int slots = resident_slots(yee_fused<T, tl.ry, tl.nw, Codec, GR>, 64 * tl.nw);
     FusedArgs a = a0;
     int threads;
     geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
     a.nwg = a.ntx * a.nty * a.ntz;
     const int grid = (a.nwg + 7) / 8 * 8;
-    hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, a);
+    hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR>), dim3(grid), dim3(threads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -637,10 +686,12 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
     return hipGetLastError();
 }
 
-template <int T, class Codec>
+template <int T, class Codec, bool GR>
 hipError_t launch_t(const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st)
 {
-    if (batch) {
+    if constexpr (GR) {
+        if (batch) return hipErrorInvalidValue;   // batches are uniform-spacing solves
+    } else if (batch) {
         switch (variant) {
         case 1: return launch_batch_tv<T, 1, Codec>(a, n, zc, st);
         case 2: return launch_batch_tv<T, 2, Codec>(a, n, zc, st);
@@ -648,20 +699,20 @@ hipError_t launch_t(const FusedArgs *a, int n, bool batch, int variant, int zc, 
         }
     }
     switch (variant) {
-    case 1: return launch_tv<T, 1, Codec>(*a, zc, st);
-    case 2: return launch_tv<T, 2, Codec>(*a, zc, st);
-    default: return launch_tv<T, 0, Codec>(*a, zc, st);
+    case 1: return launch_tv<T, 1, Codec, GR>(*a, zc, st);
+    case 2: return launch_tv<T, 2, Codec, GR>(*a, zc, st);
+    default: return launch_tv<T, 0, Codec, GR>(*a, zc, st);
     }
 }
 
-template <class Codec>
+template <class Codec, bool GR = false>
 hipError_t launch_codec(int T, const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st)
 {
     switch (T) {
-    case 1: return launch_t<1, Codec>(a, n, batch, variant, zc, st);
-    case 2: return launch_t<2, Codec>(a, n, batch, variant, zc, st);
-    case 3: return launch_t<3, Codec>(a, n, batch, variant, zc, st);
-    case 4: return launch_t<4, Codec>(a, n, batch, variant, zc, st);
+    case 1: return launch_t<1, Codec, GR>(a, n, batch, variant, zc, st);
+    case 2: return launch_t<2, Codec, GR>(a, n, batch, variant, zc, st);
+    case 3: return launch_t<3, Codec, GR>(a, n, batch, variant, zc, st);
+    case 4: return launch_t<4, Codec, GR>(a, n, batch, variant, zc, st);
     }
     return hipErrorInvalidValue;
 }

@@ -59,9 +59,13 @@ struct FusedArgs {
     const void *fin;
     void *fout;
     const uint8_t *mat;
-    const float4 *coef;   // per material (Ca, Cbx, Cby, Cbz)
+    const float4 *coef;   // per material (Ca, Cbx, Cby, Cbz); graded spacing: (Ca, G, 0, 0)
     int n_mat;
     float chx, chy, chz;
+    // Graded spacing (null: uniform, chx..chz and coef's Cb apply).  Per node
+    // index, x (nx+1 entries) then y (ny+1) then z (nz+1): (c dt / primal
+    // cell size, c dt / dual cell size); an E coefficient is G * the second.
+    const float2 *gc;
     int ntx, nty, ntz, nwg;
     int zc;               // planes per z chunk
     long long step0;      // absolute step index advanced by time level 1
@@ -87,6 +91,7 @@ struct PlainArgs {
     const float4 *coef;
     int n_mat;
     float chx, chy, chz;
+    const float2 *gc;     // graded spacing, as in FusedArgs (null: uniform)
 };
 
 struct DiagArgs {
@@ -108,7 +113,7 @@ enum { DIAG_W = 11 };     // energy, div_e_sumsq, div_h_sumsq, div_e_max, div_h_
 hipError_t launch_plain_step(const PlainArgs &a, const SourceTable &src, const ProbeTable &probe,
                              long long step, hipStream_t st);
 // variant: tile shape (0 = default; FP32 also has 1 and 2); zc: planes per
-// z chunk (0 = automatic).
+// z chunk (0 = automatic).  a.gc set: graded spacing (FP32 storage only).
 hipError_t launch_fused(int storage, int T, const FusedArgs &a, int variant, int zc, hipStream_t st);
 // One persistent launch over several solves sharing storage, T and shape;
 // each args[i] is complete except for its tile geometry, which is filled in.
@@ -118,8 +123,8 @@ hipError_t launch_fused_batch(int storage, int T, const FusedArgs *args, int n, 
 bool fused_fits(const Layout &L, int storage, int T);
 // Tile shape (index into the fused kernel's table) and steps per pass chosen
 // when the caller does not: measured fastest on MI355X.
-int auto_shape(int storage, int T);
-int fastest_T(const Layout &L, int storage);
+int auto_shape(int storage, int T, bool graded = false);
+int fastest_T(const Layout &L, int storage, bool graded = false);
 hipError_t launch_diag(int storage, const DiagArgs &a, double *out11, hipStream_t st);
 int diag_blocks(const Layout &L);
 

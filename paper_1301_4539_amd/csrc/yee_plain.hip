@@ -3,6 +3,9 @@
 // node-box point updating all three components there).  FP32 storage only.
 // Each pass streams its fields from HBM once; the E pass also reads the
 // uint8 material index and looks the coefficients up in an LDS table.
+// With graded spacing (GR) the c dt / size factors come per index from the
+// one-dimensional arrays a.gc (primal sizes for H, dual sizes for E), and an
+// E coefficient is the material's G times the dual factor, one FP32 product.
 
 #include "yee_device.hpp"
 #include "yee_internal.hpp"
@@ -13,6 +16,7 @@ namespace {
 
 constexpr int BX = 64, BY = 4;
 
+template <bool GR>
 __global__ __launch_bounds__(BX *BY) void h_plain(PlainArgs a)
 {
     const int i = blockIdx.x * BX + threadIdx.x;
@@ -23,24 +27,31 @@ __global__ __launch_bounds__(BX *BY) void h_plain(PlainArgs a)
     float *ex = a.f, *ey = a.f + L.cstride, *ez = a.f + 2 * L.cstride;
     float *hx = a.f + 3 * L.cstride, *hy = a.f + 4 * L.cstride, *hz = a.f + 5 * L.cstride;
     const long long p = k * L.kstride + (long long)j * L.pitch + i;
+    float chx = a.chx, chy = a.chy, chz = a.chz;
+    if constexpr (GR) {
+        chx = a.gc[i].x;
+        chy = a.gc[L.nx + 1 + j].x;
+        chz = a.gc[L.nx + L.ny + 2 + k].x;
+    }
     // Faraday: H -= c dt curl E, z-difference term first, then y (cyclic).
     if (j < L.ny && k < L.nz) {
         float dey_z = ey[p + L.kstride] - ey[p];
         float dez_y = ez[p + L.pitch] - ez[p];
-        hx[p] = __builtin_fmaf(-a.chy, dez_y, __builtin_fmaf(a.chz, dey_z, hx[p]));
+        hx[p] = __builtin_fmaf(-chy, dez_y, __builtin_fmaf(chz, dey_z, hx[p]));
     }
     if (i < L.nx && k < L.nz) {
         float dez_x = ez[p + 1] - ez[p];
         float dex_z = ex[p + L.kstride] - ex[p];
-        hy[p] = __builtin_fmaf(-a.chz, dex_z, __builtin_fmaf(a.chx, dez_x, hy[p]));
+        hy[p] = __builtin_fmaf(-chz, dex_z, __builtin_fmaf(chx, dez_x, hy[p]));
     }
     if (i < L.nx && j < L.ny) {
         float dex_y = ex[p + L.pitch] - ex[p];
         float dey_x = ey[p + 1] - ey[p];
-        hz[p] = __builtin_fmaf(-a.chx, dey_x, __builtin_fmaf(a.chy, dex_y, hz[p]));
+        hz[p] = __builtin_fmaf(-chx, dey_x, __builtin_fmaf(chy, dex_y, hz[p]));
     }
 }
 
+template <bool GR>
 __global__ __launch_bounds__(BX *BY) void e_plain(PlainArgs a)
 {
     __shared__ float4 s_coef[256];
@@ -56,22 +67,28 @@ __global__ __launch_bounds__(BX *BY) void e_plain(PlainArgs a)
     const float *hx = a.f + 3 * L.cstride, *hy = a.f + 4 * L.cstride, *hz = a.f + 5 * L.cstride;
     const long long p = k * L.kstride + (long long)j * L.pitch + i;
     const float4 cf = s_coef[a.mat[k * L.plane + (long long)j * L.pitch + i]];   // owner cell's Ca, Cbx, Cby, Cbz
+    float cbx = cf.y, cby = cf.z, cbz = cf.w;
+    if constexpr (GR) {   // cf.y holds G
+        cbx = cf.y * a.gc[i].y;
+        cby = cf.y * a.gc[L.nx + 1 + j].y;
+        cbz = cf.y * a.gc[L.nx + L.ny + 2 + k].y;
+    }
     const bool kin = k > 0 && k < L.nz, jin = j > 0 && j < L.ny, iin = i > 0 && i < L.nx;
     // Ampere with loss: E = Ca E + Cb curl H on edges not tangential to a wall.
     if (i < L.nx && jin && kin) {
         float dhz_y = hz[p] - hz[p - L.pitch];
         float dhy_z = hy[p] - hy[p - L.kstride];
-        ex[p] = __builtin_fmaf(-cf.w, dhy_z, __builtin_fmaf(cf.z, dhz_y, cf.x * ex[p]));
+        ex[p] = __builtin_fmaf(-cbz, dhy_z, __builtin_fmaf(cby, dhz_y, cf.x * ex[p]));
     }
     if (j < L.ny && iin && kin) {
         float dhx_z = hx[p] - hx[p - L.kstride];
         float dhz_x = hz[p] - hz[p - 1];
-        ey[p] = __builtin_fmaf(-cf.y, dhz_x, __builtin_fmaf(cf.w, dhx_z, cf.x * ey[p]));
+        ey[p] = __builtin_fmaf(-cbx, dhz_x, __builtin_fmaf(cbz, dhx_z, cf.x * ey[p]));
     }
     if (k < L.nz && iin && jin) {
         float dhy_x = hy[p] - hy[p - 1];
         float dhx_y = hx[p] - hx[p - L.pitch];
-        ez[p] = __builtin_fmaf(-cf.z, dhx_y, __builtin_fmaf(cf.y, dhy_x, cf.x * ez[p]));
+        ez[p] = __builtin_fmaf(-cby, dhx_y, __builtin_fmaf(cbx, dhy_x, cf.x * ez[p]));
     }
 }
 
@@ -104,8 +121,13 @@ hipError_t launch_plain_step(const PlainArgs &a, const SourceTable &src, const P
 {
     dim3 block(BX, BY, 1);
     dim3 grid((a.L.nx + 1 + BX - 1) / BX, (a.L.ny + 1 + BY - 1) / BY, a.L.nz + 1);
-    hipLaunchKernelGGL(h_plain, grid, block, 0, st, a);
-    hipLaunchKernelGGL(e_plain, grid, block, 0, st, a);
+    if (a.gc) {
+        hipLaunchKernelGGL(h_plain<true>, grid, block, 0, st, a);
+        hipLaunchKernelGGL(e_plain<true>, grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL(h_plain<false>, grid, block, 0, st, a);
+        hipLaunchKernelGGL(e_plain<false>, grid, block, 0, st, a);
+    }
     if (src.n > 0) hipLaunchKernelGGL(src_plain, dim3(1), dim3(1), 0, st, a.f, a.L, src, step);
     if (probe.n > 0)
         hipLaunchKernelGGL(probe_plain, dim3((probe.n + 63) / 64), dim3(64), 0, st, (const float *)a.f, a.L,

@@ -68,9 +68,12 @@ def lib():
         L.fdtd_destroy.restype = None
         L.fdtd_last_error.restype = C.c_char_p
         L.fdtd_coefficients.argtypes = [C.POINTER(_Material), i, d, d, d, d, vp, vp]
+        L.fdtd_set_spacing.argtypes = [vp, vp, vp, vp]
+        L.fdtd_graded_coefficients.argtypes = [C.POINTER(_Material), i, i, i, i, vp, vp, vp, d, vp, vp]
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
-                     "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients"):
+                     "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
+                     "fdtd_graded_coefficients"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -98,6 +101,22 @@ def coefficients(eps_r, sigma, dx, dy, dz, dt, mu_r=None):
     ch = np.zeros(3, np.float32)
     _check(lib().fdtd_coefficients(arr, n, dx, dy, dz, dt, out.ctypes.data, ch.ctypes.data))
     return out, ch
+
+
+def _sizes(dx, dy, dz):
+    return tuple(np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (dx, dy, dz))
+
+
+def graded_coefficients(eps_r, sigma, dx, dy, dz, dt, mu_r=None):
+    """The library's FP32 graded-spacing tables: cag (n_mat, 2) = (Ca, G) and
+    gc ((nx+1)+(ny+1)+(nz+1), 2) = (c dt / primal size, c dt / dual size)."""
+    arr, n = _materials(eps_r, sigma, mu_r)
+    dx, dy, dz = _sizes(dx, dy, dz)
+    cag = np.zeros((n, 2), np.float32)
+    gc = np.zeros((len(dx) + len(dy) + len(dz) + 3, 2), np.float32)
+    _check(lib().fdtd_graded_coefficients(arr, n, len(dx), len(dy), len(dz), dx.ctypes.data, dy.ctypes.data,
+                                          dz.ctypes.data, dt, cag.ctypes.data, gc.ctypes.data))
+    return cag, gc
 
 
 def step_batch(solvers, n_steps):
@@ -151,12 +170,20 @@ class Solver:
             s.add_source(c, i, j, k, wl.waveforms[q].astype(np.float32))
         for (c, i, j, k) in wl.probes:
             s.add_probe(c, i, j, k)
+        if getattr(wl, "spacing", None) is not None:
+            s.set_spacing(*wl.spacing)
         if wl.init_fields is not None:
             s.set_fields(wl.init_fields.astype(np.float32))
         return s
 
     def set_kernel(self, kernel, time_block):
         _check(lib().fdtd_set_kernel(self._h, kernel, time_block))
+
+    def set_spacing(self, dx, dy, dz):
+        """Graded spacing: per-index cell sizes dx (nx,), dy (ny,), dz (nz,)."""
+        dx, dy, dz = _sizes(dx, dy, dz)
+        assert (len(dx), len(dy), len(dz)) == (self.nx, self.ny, self.nz)
+        _check(lib().fdtd_set_spacing(self._h, dx.ctypes.data, dy.ctypes.data, dz.ctypes.data))
 
     def set_tiling(self, variant=0, z_chunk=0):
         _check(lib().fdtd_set_tiling(self._h, variant, z_chunk))

@@ -16,6 +16,8 @@ structure of the configurations this library is benchmarked on:
 * ``spheres512`` -- 512^3, 200 spheres, three sources (Ex, Ey, Ez).
 * ``aniso1024`` -- 1024x512x256, same recipe as ``spheres512``.
 * ``serving``   -- 256 requests with random anisotropic grids.
+* ``graded256`` -- 256^3 with graded cell sizes (fine core, geometric growth
+  to coarse cells near the walls), otherwise as ``spheres256``.
 
 All randomness comes from splitmix64 (Steele, Lea, Flood 2014), drawn in a
 fixed order: material table, spheres (cx, cy, cz, radius, index), sources,
@@ -116,6 +118,9 @@ class Workload:
     n_steps: int
     init_fields: Optional[np.ndarray] = None   # (6, nz+1, ny+1, nx+1) float64
     storage: int = FP32
+    # graded spacing: per-index cell sizes (dx (nx,), dy (ny,), dz (nz,)) in
+    # metres; None = uniform dx, dy, dz
+    spacing: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
 
     @property
     def cells(self) -> int:
@@ -292,6 +297,38 @@ def cavity402(n_steps: int = 1300, seed: int = 1005, storage: int = FP32) -> Wor
     probes = seeded_probes(rng, n, n, n, 6)
     return Workload("cavity402", n, n, n, d, d, d, dt, eps, mu, sig, mat, srcs, waves, probes, n_steps,
                     storage=storage)
+
+
+def graded_sizes(n: int, d_fine: float, d_coarse: float, ratio: float, core: int) -> np.ndarray:
+    """Cell sizes along one axis: d_fine over the central `core` cells, growing
+    by `ratio` per cell outwards until d_coarse, then constant."""
+    q = np.arange(n) + 0.5 - n / 2.0
+    steps = np.maximum(0.0, np.abs(q) - core / 2.0)
+    return np.minimum(d_fine * ratio ** np.ceil(steps), d_coarse)
+
+
+def courant_dt_graded(sx: np.ndarray, sy: np.ndarray, sz: np.ndarray, frac: float = 0.99) -> float:
+    """frac times the Courant bound of the smallest cell size on each axis."""
+    return courant_dt(float(sx.min()), float(sy.min()), float(sz.min()), frac)
+
+
+def graded(n: int, n_spheres: int, n_steps: int, seed: int, d_fine: float = 0.5e-3,
+           d_coarse: float = 2e-3, ratio: float = 1.05, core: int = 64, name: str = "graded") -> Workload:
+    """The spheres recipe (spheres painted in index space) on a graded grid: fine
+    cells around the centre, where the Ez source sits, coarse cells near the
+    walls.  dt from the smallest cells; the waveform has 20 coarse cells per
+    vacuum wavelength."""
+    sz = graded_sizes(n, d_fine, d_coarse, ratio, core)
+    wl = spheres(n, n, n, n_spheres, n_steps, seed=seed, n_sources=1, name=name)
+    wl.dt = courant_dt_graded(sz, sz, sz)
+    wl.dx = wl.dy = wl.dz = d_coarse
+    wl.waveforms = np.tile(gaussian_sine(n_steps, wl.dt, d_coarse), (len(wl.sources), 1))
+    wl.spacing = (sz.copy(), sz.copy(), sz.copy())
+    return wl
+
+
+def graded256(n_steps: int = 1000) -> Workload:
+    return graded(256, 40, n_steps, seed=1006, name="graded256")
 
 
 @dataclasses.dataclass

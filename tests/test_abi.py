@@ -72,3 +72,25 @@ def test_coefficients_match_oracle_rounded_once():
         ref, ref_ch = oracle.coefficients(eps, sig, dt, *d)
         assert np.array_equal(ours, ref.astype(np.float32))
         assert np.array_equal(ch, ref_ch.astype(np.float32))
+
+
+def test_graded_coefficients_match_oracle_rounded_once():
+    rng = np.random.default_rng(1)
+    eps = np.concatenate([[1.0], rng.uniform(1, 12, 15)])
+    sig = np.concatenate([[0.0], rng.uniform(0, 0.05, 15)])
+    sx, sy, sz = (rng.uniform(0.4e-3, 2e-3, n) for n in (9, 5, 7))
+    dt = W.courant_dt_graded(sx, sy, sz)
+    cag, gc = fdtd.graded_coefficients(eps, sig, sx, sy, sz, dt)
+    ref_cag, ref_hc, ref_ec = oracle.graded_coefficients(eps, sig, dt, sx, sy, sz)
+    assert np.array_equal(cag, ref_cag.astype(np.float32))
+    assert np.array_equal(gc[:, 0], ref_hc.astype(np.float32))
+    assert np.array_equal(gc[:, 1], ref_ec.astype(np.float32))
+
+
+def test_graded_coefficients_reject_bad_sizes():
+    sx = np.full(4, 1e-3)
+    bad = sx.copy()
+    bad[2] = 0.0
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.graded_coefficients([1.0], [0.0], bad, sx, sx, 1e-12)
+    assert e.value.code == fdtd.EINVAL
