@@ -68,6 +68,15 @@ def lib():
         L.orc_energy_graded_f64.argtypes = [_i, _i, _i, _dp, _dp, _dp, _dp, _dp, _u8, _dp]
         L.orc_energy_graded_f64.restype = C.c_double
         L.orc_divergence_graded_f64.argtypes = [_i, _i, _i, _dp, _dp, _dp, _dp, _u8, _dp, _dp, _dp]
+        L.orc_cpml_coefficients.argtypes = [_i, _dp, _dp, C.c_double, _i, _i, _i, _dp, _dp, _dp, _i, _i,
+                                            C.c_double, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
+        L.orc_cpml_coefficients.restype = _i
+        L.orc_run_cpml_f64.argtypes = [_i, _i, _i, _i, _dp, _dp, _dp, _dp, _u8, _dp, _dp, _l, _i, _i, _ip, _dp,
+                                       _i, _i, _ip, _dp]
+        L.orc_run_cpml_f64.restype = _i
+        L.orc_run_cpml_f32.argtypes = [_i, _i, _i, _i, _fp, _fp, _fp, _fp, _u8, _fp, _fp, _l, _i, _i, _ip, _fp,
+                                       _i, _i, _ip, _dp]
+        L.orc_run_cpml_f32.restype = _i
         _lib = L
     return _lib
 
@@ -96,6 +105,23 @@ def graded_coefficients(eps_r, sigma, dt, dx, dy, dz):
     return cag, hc, ec
 
 
+def cpml_coefficients(eps_r, sigma, dt, dx, dy, dz, thickness, order=3, sigma_factor=1.0, kappa_max=1.0,
+                      alpha_max=0.0):
+    """CPML layers of `thickness` cells on every face over per-index cell sizes:
+    (cag (n_mat, 2), hc, ec with kappa folded in, cp ((nx+1)+(ny+1)+(nz+1), 6) =
+    b_h, a_h, c dt / d, b_e, a_e, c dt / d') in float64."""
+    eps_r = np.ascontiguousarray(eps_r, dtype=np.float64)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    dx, dy, dz = (np.ascontiguousarray(a, dtype=np.float64) for a in (dx, dy, dz))
+    n = len(dx) + len(dy) + len(dz) + 3
+    cag, hc, ec, cp = np.zeros((len(eps_r), 2)), np.zeros(n), np.zeros(n), np.zeros((n, 6))
+    rc = lib().orc_cpml_coefficients(len(eps_r), eps_r, sigma, dt, len(dx), len(dy), len(dz), dx, dy, dz,
+                                     thickness, order, sigma_factor, kappa_max, alpha_max, cag, hc, ec, cp)
+    if rc:
+        raise ValueError("CPML layers must leave an interior on every axis")
+    return cag, hc, ec, cp
+
+
 def zero_fields(nx, ny, nz, dtype=np.float64):
     return np.zeros((6, nz + 1, ny + 1, nx + 1), dtype=dtype)
 
@@ -108,7 +134,7 @@ class Problem:
     """A grid, its material table and per-cell indices, sources and probes."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, dt, eps_r, sigma, mat,
-                 sources=(), waveforms=None, probes=(), spacing=None):
+                 sources=(), waveforms=None, probes=(), spacing=None, cpml=None):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.dx, self.dy, self.dz, self.dt = dx, dy, dz, dt
         self.eps_r = np.ascontiguousarray(eps_r, dtype=np.float64)
@@ -132,11 +158,30 @@ class Problem:
             self.cag64, self.hc64, self.ec64 = graded_coefficients(self.eps_r, self.sigma, dt,
                                                                    self.sx, self.sy, self.sz)
             self.cag32, self.hc32, self.ec32 = (a.astype(np.float32) for a in (self.cag64, self.hc64, self.ec64))
+        # CPML layers (dict: thickness, order, sigma_factor, kappa_max, alpha_max) on top of
+        # the graded update (uniform sizes become per-index arrays)
+        self.cpml = dict(cpml) if cpml else None
+        if self.cpml:
+            if not self.graded:
+                self.graded = True
+                self.sx, self.sy, self.sz = np.full(nx, float(dx)), np.full(ny, float(dy)), np.full(nz, float(dz))
+            self.cag64, self.hc64, self.ec64, self.cp64 = cpml_coefficients(
+                self.eps_r, self.sigma, dt, self.sx, self.sy, self.sz, **self.cpml)
+            self.cag32, self.hc32, self.ec32, self.cp32 = (a.astype(np.float32) for a in
+                                                           (self.cag64, self.hc64, self.ec64, self.cp64))
+            self.reset_psi()
+
+    def reset_psi(self):
+        """Zero the CPML auxiliary state of both modes (12 arrays over the node box)."""
+        shape = (12, self.nz + 1, self.ny + 1, self.nx + 1)
+        self.psi64 = np.zeros(shape)
+        self.psi32 = np.zeros(shape, np.float32)
 
     @classmethod
     def from_workload(cls, wl):
         return cls(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.dt, wl.eps_r, wl.sigma, wl.mat,
-                   wl.sources, wl.waveforms, wl.probes, spacing=getattr(wl, "spacing", None))
+                   wl.sources, wl.waveforms, wl.probes, spacing=getattr(wl, "spacing", None),
+                   cpml=getattr(wl, "cpml", None))
 
     @property
     def a_max(self) -> float:
@@ -146,7 +191,12 @@ class Problem:
         """Advance f (float64, in place); returns probes (n_steps, n_probe) float64."""
         assert f.dtype == np.float64 and f.flags.c_contiguous
         out = np.zeros((n_steps, max(len(self.probe), 1)))
-        if self.graded:
+        if self.cpml:
+            rc = lib().orc_run_cpml_f64(self.nx, self.ny, self.nz, self.cpml["thickness"], self.hc64, self.cag64,
+                                        self.ec64, self.cp64, self.mat, f, self.psi64, step0, n_steps,
+                                        len(self.src), self.src, self.wave64, self.wave64.shape[1],
+                                        len(self.probe), self.probe, out)
+        elif self.graded:
             rc = lib().orc_run_graded_f64(self.nx, self.ny, self.nz, self.hc64, self.cag64, self.ec64, self.mat, f,
                                           step0, n_steps, len(self.src), self.src, self.wave64,
                                           self.wave64.shape[1], len(self.probe), self.probe, out)
@@ -161,7 +211,12 @@ class Problem:
     def run_f32(self, f, step0, n_steps):
         assert f.dtype == np.float32 and f.flags.c_contiguous
         out = np.zeros((n_steps, max(len(self.probe), 1)))
-        if self.graded:
+        if self.cpml:
+            rc = lib().orc_run_cpml_f32(self.nx, self.ny, self.nz, self.cpml["thickness"], self.hc32, self.cag32,
+                                        self.ec32, self.cp32, self.mat, f, self.psi32, step0, n_steps,
+                                        len(self.src), self.src, self.wave32, self.wave32.shape[1],
+                                        len(self.probe), self.probe, out)
+        elif self.graded:
             rc = lib().orc_run_graded_f32(self.nx, self.ny, self.nz, self.hc32, self.cag32, self.ec32, self.mat, f,
                                           step0, n_steps, len(self.src), self.src, self.wave32,
                                           self.wave32.shape[1], len(self.probe), self.probe, out)

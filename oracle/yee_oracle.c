@@ -901,6 +901,382 @@ void orc_divergence_graded_f64(int nx, int ny, int nz, const double *dx, const d
     free(dxd);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Convolutional PML (CPML) absorbing layers.                                */
+/*                                                                          */
+/* The paper cites the convolutional PML of Roden and Gedney (2000) as the   */
+/* radiation condition its production code implements (Sec. 3.3, Sec. 4.2),  */
+/* with one-dimensional coefficients so as not to add bandwidth.  The        */
+/* formulation here is that published CFS-CPML (also Taflove and Hagness,    */
+/* 3rd ed., Sec. 7.9-7.11).  In a layer of N                                 */
+/* cells on every face each spatial derivative d/du of the curl becomes     */
+/*   (1/kappa_u) d/du + psi_u,  psi_u <- b_u psi_u + a_u (difference along u) */
+/* with, at depth rho (cells, measured from the inner face of the layer),   */
+/*   x = rho / N,  sigma = sigma_max x^m,  kappa = 1 + (kappa_max - 1) x^m,   */
+/*   alpha = alpha_max (1 - x),                                              */
+/*   b = exp(-(sigma / kappa + alpha) dt / eps0),                             */
+/*   a = sigma (b - 1) / (kappa (sigma + kappa alpha))   (0 when sigma = 0),  */
+/*   sigma_max = sigma_factor * 0.8 (m + 1) / (eta0 d_out),                   */
+/* d_out being the outermost cell size of that face.  Depths: an H value at  */
+/* cell q (position q + 1/2) has rho = N - (q + 1/2) in the low layer and     */
+/* (q + 1/2) - (n - N) in the high one; an E value at node q has rho = N - q */
+/* and q - (n - N).  psi is kept where rho > 0: H cells q < N or q >= n - N,  */
+/* E nodes 0 < q < N or n - N < q < n.                                       */
+/*                                                                          */
+/* Coefficients are the graded ones with kappa folded in,                    */
+/*   hc[q] = c dt / (kappa_h(q) d[q]),  ec[q] = c dt / (kappa_e(q) d'[q]),     */
+/* so outside the layers the update is the graded one, and per axis and      */
+/* index cp holds {b_h, a_h, c dt / d[q], b_e, a_e, c dt / d'[q]}.          */
+/* One step: the graded H half-step, then each H value in a layer adds its    */
+/* psi terms in the order of its update (Hx: z then y, Hy: x then z, Hz: y   */
+/* then x), psi updated first:                                               */
+/*   psi = b psi + a diff;   Hx += (c dt/dz) psi_z,  Hx -= (c dt/dy) psi_y    */
+/* then the graded E half-step and likewise for interior E edges with the    */
+/* material factor G: Ex += G (c dt/dy') psi_y, Ex -= G (c dt/dz') psi_z.     */
+/* FP32 mode: psi = fmaf(b, psi, a * diff); field = fmaf(+-coef, psi, field), */
+/* the E coefficient formed as one float product G * (c dt / d').           */
+/* psi state: 12 arrays over the node box (component c, axis u), order       */
+/* (Hx,y) (Hx,z) (Hy,z) (Hy,x) (Hz,x) (Hz,y) (Ex,y) (Ex,z) (Ey,z) (Ey,x)     */
+/* (Ez,x) (Ez,y); only entries in a layer are used.                          */
+/* ------------------------------------------------------------------------ */
+enum { PS_HXY = 0, PS_HXZ, PS_HYZ, PS_HYX, PS_HZX, PS_HZY, PS_EXY, PS_EXZ, PS_EYZ, PS_EYX, PS_EZX, PS_EZY };
+
+static int cpml_h_in(int n, int N, int q) { return q < N || q >= n - N; }
+static int cpml_e_in(int n, int N, int q) { return (q > 0 && q < N) || (q > n - N && q < n); }
+
+int orc_cpml_coefficients(int n_mat, const double *eps_r, const double *sigma, double dt,
+                          int nx, int ny, int nz, const double *dx, const double *dy, const double *dz,
+                          int N, int m, double sigma_factor, double kappa_max, double alpha_max,
+                          double *cag, double *hc, double *ec, double *cp /* 6 per index */)
+{
+    const int n[3] = {nx, ny, nz};
+    const double *d[3] = {dx, dy, dz};
+    if (N < 1) return -1;
+    for (int ax = 0; ax < 3; ax++)
+        if (2 * N >= n[ax]) return -1;
+    orc_graded_coefficients(n_mat, eps_r, sigma, dt, nx, ny, nz, dx, dy, dz, cag, hc, ec);
+    const double eta0 = 1.0 / (EPS0 * C0);
+    int off = 0;
+    for (int ax = 0; ax < 3; ax++) {
+        const int nn = n[ax];
+        const double smax_lo = sigma_factor * 0.8 * (m + 1) / (eta0 * d[ax][0]);
+        const double smax_hi = sigma_factor * 0.8 * (m + 1) / (eta0 * d[ax][nn - 1]);
+        for (int q = 0; q <= nn; q++) {
+            double *c = cp + 6 * (size_t)(off + q);
+            for (int v = 0; v < 6; v++) c[v] = 0.0;
+            for (int half = 0; half < 2; half++) {        /* 0: H at q + 1/2, 1: E at node q */
+                if (half == 0 && q == nn) continue;
+                const double pos = half == 0 ? q + 0.5 : (double)q;
+                double rho = 0.0, smax = 0.0;
+                if (pos < N) { rho = N - pos; smax = smax_lo; }
+                else if (pos > nn - N) { rho = pos - (nn - N); smax = smax_hi; }
+                const int inside = half == 0 ? cpml_h_in(nn, N, q) : cpml_e_in(nn, N, q);
+                double kappa = 1.0, b = 0.0, a = 0.0;
+                if (rho > 0.0) {
+                    const double x = rho / N, xm = pow(x, m);
+                    const double sg = smax * xm, al = alpha_max * (1.0 - x);
+                    kappa = 1.0 + (kappa_max - 1.0) * xm;
+                    b = exp(-(sg / kappa + al) * dt / EPS0);
+                    a = sg > 0.0 ? sg * (b - 1.0) / (kappa * (sg + kappa * al)) : 0.0;
+                }
+                if (half == 0) {
+                    if (kappa != 1.0) hc[off + q] = (C0 * dt) / (kappa * d[ax][q]);
+                    c[0] = inside ? b : 0.0;
+                    c[1] = inside ? a : 0.0;
+                    c[2] = (C0 * dt) / d[ax][q];
+                } else if (q > 0 && q < nn) {
+                    const double dd = (d[ax][q - 1] + d[ax][q]) / 2.0;
+                    if (kappa != 1.0) ec[off + q] = (C0 * dt) / (kappa * dd);
+                    c[3] = inside ? b : 0.0;
+                    c[4] = inside ? a : 0.0;
+                    c[5] = (C0 * dt) / dd;
+                }
+            }
+        }
+        off += nn + 1;
+    }
+    return 0;
+}
+
+/* psi terms after the graded half-steps (see above), FP64 */
+static void cpml_h_f64(int nx, int ny, int nz, int N, const double *cp, double *f, double *psi)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const double *cx = cp, *cy = cp + 6 * ((size_t)nx + 1), *cz = cy + 6 * ((size_t)ny + 1);
+    const double *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    double *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                double *ps;
+                if (in_range(&g, HX, i, j, k)) {
+                    if (cpml_h_in(nz, N, k)) {
+                        ps = psi + PS_HXZ * g.n + p;
+                        *ps = cz[6 * k] * *ps + cz[6 * k + 1] * (ey[p + g.sz] - ey[p]);
+                        hx[p] += cz[6 * k + 2] * *ps;
+                    }
+                    if (cpml_h_in(ny, N, j)) {
+                        ps = psi + PS_HXY * g.n + p;
+                        *ps = cy[6 * j] * *ps + cy[6 * j + 1] * (ez[p + g.sy] - ez[p]);
+                        hx[p] -= cy[6 * j + 2] * *ps;
+                    }
+                }
+                if (in_range(&g, HY, i, j, k)) {
+                    if (cpml_h_in(nx, N, i)) {
+                        ps = psi + PS_HYX * g.n + p;
+                        *ps = cx[6 * i] * *ps + cx[6 * i + 1] * (ez[p + 1] - ez[p]);
+                        hy[p] += cx[6 * i + 2] * *ps;
+                    }
+                    if (cpml_h_in(nz, N, k)) {
+                        ps = psi + PS_HYZ * g.n + p;
+                        *ps = cz[6 * k] * *ps + cz[6 * k + 1] * (ex[p + g.sz] - ex[p]);
+                        hy[p] -= cz[6 * k + 2] * *ps;
+                    }
+                }
+                if (in_range(&g, HZ, i, j, k)) {
+                    if (cpml_h_in(ny, N, j)) {
+                        ps = psi + PS_HZY * g.n + p;
+                        *ps = cy[6 * j] * *ps + cy[6 * j + 1] * (ex[p + g.sy] - ex[p]);
+                        hz[p] += cy[6 * j + 2] * *ps;
+                    }
+                    if (cpml_h_in(nx, N, i)) {
+                        ps = psi + PS_HZX * g.n + p;
+                        *ps = cx[6 * i] * *ps + cx[6 * i + 1] * (ey[p + 1] - ey[p]);
+                        hz[p] -= cx[6 * i + 2] * *ps;
+                    }
+                }
+            }
+}
+
+static void cpml_e_f64(int nx, int ny, int nz, int N, const double *cp, const double *cag, const uint8_t *mat,
+                       double *f, double *psi)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const double *cx = cp, *cy = cp + 6 * ((size_t)nx + 1), *cz = cy + 6 * ((size_t)ny + 1);
+    double *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    const double *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                int m = (i < nx && j < ny && k < nz) ? mat[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)] : 0;
+                const double gm = cag[2 * m + 1];
+                double *ps;
+                if (e_interior(&g, EX, i, j, k)) {
+                    if (cpml_e_in(ny, N, j)) {
+                        ps = psi + PS_EXY * g.n + p;
+                        *ps = cy[6 * j + 3] * *ps + cy[6 * j + 4] * (hz[p] - hz[p - g.sy]);
+                        ex[p] += gm * cy[6 * j + 5] * *ps;
+                    }
+                    if (cpml_e_in(nz, N, k)) {
+                        ps = psi + PS_EXZ * g.n + p;
+                        *ps = cz[6 * k + 3] * *ps + cz[6 * k + 4] * (hy[p] - hy[p - g.sz]);
+                        ex[p] -= gm * cz[6 * k + 5] * *ps;
+                    }
+                }
+                if (e_interior(&g, EY, i, j, k)) {
+                    if (cpml_e_in(nz, N, k)) {
+                        ps = psi + PS_EYZ * g.n + p;
+                        *ps = cz[6 * k + 3] * *ps + cz[6 * k + 4] * (hx[p] - hx[p - g.sz]);
+                        ey[p] += gm * cz[6 * k + 5] * *ps;
+                    }
+                    if (cpml_e_in(nx, N, i)) {
+                        ps = psi + PS_EYX * g.n + p;
+                        *ps = cx[6 * i + 3] * *ps + cx[6 * i + 4] * (hz[p] - hz[p - 1]);
+                        ey[p] -= gm * cx[6 * i + 5] * *ps;
+                    }
+                }
+                if (e_interior(&g, EZ, i, j, k)) {
+                    if (cpml_e_in(nx, N, i)) {
+                        ps = psi + PS_EZX * g.n + p;
+                        *ps = cx[6 * i + 3] * *ps + cx[6 * i + 4] * (hy[p] - hy[p - 1]);
+                        ez[p] += gm * cx[6 * i + 5] * *ps;
+                    }
+                    if (cpml_e_in(ny, N, j)) {
+                        ps = psi + PS_EZY * g.n + p;
+                        *ps = cy[6 * j + 3] * *ps + cy[6 * j + 4] * (hx[p] - hx[p - g.sy]);
+                        ez[p] -= gm * cy[6 * j + 5] * *ps;
+                    }
+                }
+            }
+}
+
+/* FP32 operation order */
+static void cpml_h_f32(int nx, int ny, int nz, int N, const float *cp, float *f, float *psi)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const float *cx = cp, *cy = cp + 6 * ((size_t)nx + 1), *cz = cy + 6 * ((size_t)ny + 1);
+    const float *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    float *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                float *ps;
+                if (in_range(&g, HX, i, j, k)) {
+                    if (cpml_h_in(nz, N, k)) {
+                        ps = psi + PS_HXZ * g.n + p;
+                        float dey_z = ey[p + g.sz] - ey[p];
+                        *ps = fmaf(cz[6 * k], *ps, cz[6 * k + 1] * dey_z);
+                        hx[p] = fmaf(cz[6 * k + 2], *ps, hx[p]);
+                    }
+                    if (cpml_h_in(ny, N, j)) {
+                        ps = psi + PS_HXY * g.n + p;
+                        float dez_y = ez[p + g.sy] - ez[p];
+                        *ps = fmaf(cy[6 * j], *ps, cy[6 * j + 1] * dez_y);
+                        hx[p] = fmaf(-cy[6 * j + 2], *ps, hx[p]);
+                    }
+                }
+                if (in_range(&g, HY, i, j, k)) {
+                    if (cpml_h_in(nx, N, i)) {
+                        ps = psi + PS_HYX * g.n + p;
+                        float dez_x = ez[p + 1] - ez[p];
+                        *ps = fmaf(cx[6 * i], *ps, cx[6 * i + 1] * dez_x);
+                        hy[p] = fmaf(cx[6 * i + 2], *ps, hy[p]);
+                    }
+                    if (cpml_h_in(nz, N, k)) {
+                        ps = psi + PS_HYZ * g.n + p;
+                        float dex_z = ex[p + g.sz] - ex[p];
+                        *ps = fmaf(cz[6 * k], *ps, cz[6 * k + 1] * dex_z);
+                        hy[p] = fmaf(-cz[6 * k + 2], *ps, hy[p]);
+                    }
+                }
+                if (in_range(&g, HZ, i, j, k)) {
+                    if (cpml_h_in(ny, N, j)) {
+                        ps = psi + PS_HZY * g.n + p;
+                        float dex_y = ex[p + g.sy] - ex[p];
+                        *ps = fmaf(cy[6 * j], *ps, cy[6 * j + 1] * dex_y);
+                        hz[p] = fmaf(cy[6 * j + 2], *ps, hz[p]);
+                    }
+                    if (cpml_h_in(nx, N, i)) {
+                        ps = psi + PS_HZX * g.n + p;
+                        float dey_x = ey[p + 1] - ey[p];
+                        *ps = fmaf(cx[6 * i], *ps, cx[6 * i + 1] * dey_x);
+                        hz[p] = fmaf(-cx[6 * i + 2], *ps, hz[p]);
+                    }
+                }
+            }
+}
+
+static void cpml_e_f32(int nx, int ny, int nz, int N, const float *cp, const float *cag, const uint8_t *mat,
+                       float *f, float *psi)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    const float *cx = cp, *cy = cp + 6 * ((size_t)nx + 1), *cz = cy + 6 * ((size_t)ny + 1);
+    float *ex = f, *ey = f + g.n, *ez = f + 2 * g.n;
+    const float *hx = f + 3 * g.n, *hy = f + 4 * g.n, *hz = f + 5 * g.n;
+    #pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                size_t p = at(&g, i, j, k);
+                int m = (i < nx && j < ny && k < nz) ? mat[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)] : 0;
+                const float gm = cag[2 * m + 1];
+                float *ps;
+                if (e_interior(&g, EX, i, j, k)) {
+                    if (cpml_e_in(ny, N, j)) {
+                        ps = psi + PS_EXY * g.n + p;
+                        float dhz_y = hz[p] - hz[p - g.sy];
+                        *ps = fmaf(cy[6 * j + 3], *ps, cy[6 * j + 4] * dhz_y);
+                        ex[p] = fmaf(gm * cy[6 * j + 5], *ps, ex[p]);
+                    }
+                    if (cpml_e_in(nz, N, k)) {
+                        ps = psi + PS_EXZ * g.n + p;
+                        float dhy_z = hy[p] - hy[p - g.sz];
+                        *ps = fmaf(cz[6 * k + 3], *ps, cz[6 * k + 4] * dhy_z);
+                        ex[p] = fmaf(-(gm * cz[6 * k + 5]), *ps, ex[p]);
+                    }
+                }
+                if (e_interior(&g, EY, i, j, k)) {
+                    if (cpml_e_in(nz, N, k)) {
+                        ps = psi + PS_EYZ * g.n + p;
+                        float dhx_z = hx[p] - hx[p - g.sz];
+                        *ps = fmaf(cz[6 * k + 3], *ps, cz[6 * k + 4] * dhx_z);
+                        ey[p] = fmaf(gm * cz[6 * k + 5], *ps, ey[p]);
+                    }
+                    if (cpml_e_in(nx, N, i)) {
+                        ps = psi + PS_EYX * g.n + p;
+                        float dhz_x = hz[p] - hz[p - 1];
+                        *ps = fmaf(cx[6 * i + 3], *ps, cx[6 * i + 4] * dhz_x);
+                        ey[p] = fmaf(-(gm * cx[6 * i + 5]), *ps, ey[p]);
+                    }
+                }
+                if (e_interior(&g, EZ, i, j, k)) {
+                    if (cpml_e_in(nx, N, i)) {
+                        ps = psi + PS_EZX * g.n + p;
+                        float dhy_x = hy[p] - hy[p - 1];
+                        *ps = fmaf(cx[6 * i + 3], *ps, cx[6 * i + 4] * dhy_x);
+                        ez[p] = fmaf(gm * cx[6 * i + 5], *ps, ez[p]);
+                    }
+                    if (cpml_e_in(ny, N, j)) {
+                        ps = psi + PS_EZY * g.n + p;
+                        float dhx_y = hx[p] - hx[p - g.sy];
+                        *ps = fmaf(cy[6 * j + 3], *ps, cy[6 * j + 4] * dhx_y);
+                        ez[p] = fmaf(-(gm * cy[6 * j + 5]), *ps, ez[p]);
+                    }
+                }
+            }
+}
+
+int orc_run_cpml_f64(int nx, int ny, int nz, int N, const double *hc, const double *cag, const double *ec,
+                     const double *cp, const uint8_t *mat, double *f, double *psi, long step0, int n_steps,
+                     int n_src, const int *src, const double *wave, int n_wave,
+                     int n_probe, const int *probe, double *probe_out)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    if (check_points(&g, n_src, src, 1) || check_points(&g, n_probe, probe, 0)) return -1;
+    for (int s = 0; s < n_steps; s++) {
+        long n = step0 + s;
+        orc_h_half_graded_f64(nx, ny, nz, hc, f);
+        cpml_h_f64(nx, ny, nz, N, cp, f, psi);
+        orc_e_half_graded_f64(nx, ny, nz, cag, ec, mat, f);
+        cpml_e_f64(nx, ny, nz, N, cp, cag, mat, f, psi);
+        for (int q = 0; q < n_src; q++) {
+            if (n < n_wave) {
+                const int *d = src + 4 * q;
+                f[(size_t)d[0] * g.n + at(&g, d[1], d[2], d[3])] += wave[(size_t)q * n_wave + n];
+            }
+        }
+        for (int q = 0; q < n_probe; q++) {
+            const int *d = probe + 4 * q;
+            probe_out[(size_t)s * n_probe + q] = f[(size_t)d[0] * g.n + at(&g, d[1], d[2], d[3])];
+        }
+    }
+    return 0;
+}
+
+int orc_run_cpml_f32(int nx, int ny, int nz, int N, const float *hc, const float *cag, const float *ec,
+                     const float *cp, const uint8_t *mat, float *f, float *psi, long step0, int n_steps,
+                     int n_src, const int *src, const float *wave, int n_wave,
+                     int n_probe, const int *probe, double *probe_out)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    if (check_points(&g, n_src, src, 1) || check_points(&g, n_probe, probe, 0)) return -1;
+    for (int s = 0; s < n_steps; s++) {
+        long n = step0 + s;
+        orc_h_half_graded_f32(nx, ny, nz, hc, f);
+        cpml_h_f32(nx, ny, nz, N, cp, f, psi);
+        orc_e_half_graded_f32(nx, ny, nz, cag, ec, mat, f);
+        cpml_e_f32(nx, ny, nz, N, cp, cag, mat, f, psi);
+        for (int q = 0; q < n_src; q++) {
+            if (n < n_wave) {
+                const int *d = src + 4 * q;
+                size_t p = (size_t)d[0] * g.n + at(&g, d[1], d[2], d[3]);
+                f[p] = f[p] + wave[(size_t)q * n_wave + n];
+            }
+        }
+        for (int q = 0; q < n_probe; q++) {
+            const int *d = probe + 4 * q;
+            probe_out[(size_t)s * n_probe + q] = (double)f[(size_t)d[0] * g.n + at(&g, d[1], d[2], d[3])];
+        }
+    }
+    return 0;
+}
+
 /* Number of threads the parallel loops use (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>
