@@ -139,6 +139,33 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz,
  *   fdtd_step_batch and fdtd_diagnostics reject them (FDTD_EINVAL). */
 int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const double *dz);
 
+/* CPML absorbing layers of `thickness` cells inside every face of the box
+ * (0 removes them): the convolutional PML of Roden and Gedney that the paper
+ * cites as its radiation condition (Sec. 3.3, Sec. 4.2), in its CFS form.
+ * Every derivative d/du of the curl becomes (1/kappa_u) d/du + psi_u with
+ * the recursion psi_u <- b_u psi_u + a_u (difference along u), kept only in
+ * the layers; kappa is folded into the one-dimensional coefficients.  At
+ * depth rho cells into a layer, x = rho / thickness:
+ *   sigma = sigma_max x^order, kappa = 1 + (kappa_max - 1) x^order,
+ *   alpha = alpha_max (1 - x)  (S/m),  sigma_max = sigma_factor
+ *   0.8 (order + 1) / (eta0 d_out), d_out the outermost cell size of the face,
+ *   b = exp(-(sigma/kappa + alpha) dt / eps0),
+ *   a = sigma (b - 1) / (kappa (sigma + kappa alpha)).
+ * H values at cell q (position q + 1/2) and E values at node q take their
+ * depth from those positions.  After the (graded) update of a value in a
+ * layer, its psi terms are added in the order of its update (Hx: z then y,
+ * cyclically), each as psi = fmaf(b, psi, a * diff) then
+ * value = fmaf(+-c dt / d, psi, value) -- times the material's G for E.
+ *   thickness: 2 thickness < every one of nx, ny, nz; order 1..8;
+ *   sigma_factor >= 0, kappa_max >= 1, alpha_max >= 0 (else FDTD_EINVAL).
+ *   FP32 storage only; before the first step (FDTD_ESTATE); the layers run
+ *   on the PLAIN kernel family (AUTO selects it; FUSED is rejected,
+ *   FDTD_EINVAL); combines with fdtd_set_spacing in either order.  The psi
+ *   state starts at zero and is cleared by fdtd_set_fields.
+ *   fdtd_step_batch and fdtd_diagnostics reject solvers with layers. */
+int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor, double kappa_max,
+                  double alpha_max);
+
 /* Kernel family (fdtd_kernel) and steps per HBM pass T for the FUSED family:
  * 1..4, or 0 = automatic (the default after fdtd_create): 4 for FP32
  * storage, 3 for FP16/BF16 storage and for graded spacing, the fastest on
@@ -236,6 +263,17 @@ int fdtd_coefficients(const fdtd_material *table, int n_materials,
 int fdtd_graded_coefficients(const fdtd_material *table, int n_materials, int nx, int ny, int nz,
                              const double *dx, const double *dy, const double *dz, double dt,
                              float *cag, float *gc);
+
+/* FP32 tables of CPML layers over graded spacing (see fdtd_set_cpml): cag
+ * and gc as fdtd_graded_coefficients but with kappa folded into gc
+ * (c dt / (kappa d)); cp gets, per node index of x, then y, then z, the six
+ * values {b_h, a_h, c dt / d[q], b_e, a_e, c dt / d'[q]} of the H value at
+ * cell q and the E value at node q (b and a zero outside the layers), each
+ * rounded once from FP64.  Host-only; no device is needed. */
+int fdtd_cpml_coefficients(const fdtd_material *table, int n_materials, int nx, int ny, int nz,
+                           const double *dx, const double *dy, const double *dz, double dt,
+                           int thickness, int order, double sigma_factor, double kappa_max, double alpha_max,
+                           float *cag, float *gc, float *cp);
 
 #ifdef __cplusplus
 }

@@ -172,10 +172,23 @@ class Problem:
             self.reset_psi()
 
     def reset_psi(self):
-        """Zero the CPML auxiliary state of both modes (12 arrays over the node box)."""
-        shape = (12, self.nz + 1, self.ny + 1, self.nx + 1)
-        self.psi64 = np.zeros(shape)
-        self.psi32 = np.zeros(shape, np.float32)
+        """Zero the CPML auxiliary state of both modes (12 arrays over the node
+        box each, allocated when a mode first runs)."""
+        self._psi = {}
+
+    def _psi_of(self, dtype):
+        key = np.dtype(dtype).name
+        if key not in self._psi:
+            self._psi[key] = np.zeros((12, self.nz + 1, self.ny + 1, self.nx + 1), dtype)
+        return self._psi[key]
+
+    @property
+    def psi64(self):
+        return self._psi_of(np.float64)
+
+    @property
+    def psi32(self):
+        return self._psi_of(np.float32)
 
     @classmethod
     def from_workload(cls, wl):

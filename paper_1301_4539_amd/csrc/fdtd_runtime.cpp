@@ -177,6 +177,13 @@ void choose_scales(const float *m, float a_max, int *s)
 
 }  // namespace
 
+// CPML layer parameters (Roden and Gedney's CFS-CPML; see fdtd_set_cpml).
+struct CpmlParams {
+    int n = 0;                          // cells per layer; 0 = no layers
+    int order = 3;
+    double sigma_factor = 1.0, kappa_max = 1.0, alpha_max = 0.0;
+};
+
 struct fdtd_solver {
     yee::Layout L{};
     double dx = 0, dy = 0, dz = 0, dt = 0;
@@ -200,9 +207,16 @@ struct fdtd_solver {
     double sig_h[256];
     float4 *coef_d = nullptr;
     double *eps_d = nullptr;
-    // graded spacing (fdtd_set_spacing): per-index (c dt / primal size,
-    // c dt / dual size) pairs, x then y then z; null while the grid is uniform
+    // graded spacing (fdtd_set_spacing) and CPML layers (fdtd_set_cpml):
+    // per-index (c dt / (kappa primal size), c dt / (kappa dual size)) pairs,
+    // x then y then z; null while the grid is uniform without layers
     float2 *gc_d = nullptr;
+    std::vector<double> sizes[3];       // per-index cell sizes (empty: uniform dx, dy, dz)
+    CpmlParams pml;                     // layers (pml.n == 0: none)
+    float *cp_d = nullptr;              // per axis and index {b_h, a_h, c dt/d, b_e, a_e, c dt/d'}
+    float *psi_d = nullptr;             // CPML auxiliary state in the layers
+    size_t psi_bytes = 0;
+    long long psi_off[12] = {};
     int cur = 0;
     long long steps = 0;
     long long block = 0;                // reduced-storage blocks run since the last upload
@@ -387,6 +401,188 @@ void advance(fdtd_solver *s, int len)
     s->block += 1;
 }
 
+// Per-index tables of graded spacing (sizes d[axis][q], q < n[axis]) with
+// CPML layers of p.n cells folded in: cag = n_mat x {Ca, G}; gc = per axis
+// and node q {c dt / (kappa_h d[q]), c dt / (kappa_e d'[q])} (0 past the
+// last cell, and on the walls for the dual one); cp (if not null) = per axis
+// and node q {b_h, a_h, c dt / d[q], b_e, a_e, c dt / d'[q]}, the CFS-CPML
+// recursion coefficients of the H value at cell q and the E value at node q
+// (zero outside the layers).  Profiles at depth rho cells into a layer,
+// x = rho / n: sigma = sigma_max x^m, kappa = 1 + (kappa_max - 1) x^m,
+// alpha = alpha_max (1 - x), b = exp(-(sigma/kappa + alpha) dt / eps0),
+// a = sigma (b - 1) / (kappa (sigma + kappa alpha)), with
+// sigma_max = sigma_factor 0.8 (m + 1) / (eta0 d_out) for the outermost cell
+// size d_out of the face.  All in FP64, each table value rounded once.
+int graded_tables(const fdtd_material *table, int n_mat, const int n[3], const double *const d[3], double dt,
+                  const CpmlParams &p, float *cag, float *gc, float *cp)
+{
+    if (!table || !cag || !gc || n_mat < 1 || n_mat > 256) return fail(FDTD_EINVAL, "NULL argument or bad table");
+    if (n[0] < 2 || n[1] < 2 || n[2] < 2 || !(dt > 0)) return fail(FDTD_EINVAL, "bad dimensions or dt");
+    for (int m = 0; m < n_mat; ++m) {
+        const double eps = table[m].eps_r, sig = table[m].sigma;
+        if (!(eps > 0) || !(sig >= 0) || table[m].mu_r != 1.0)
+            return fail(FDTD_EINVAL, "material " + std::to_string(m) + ": need eps_r > 0, sigma >= 0, mu_r = 1");
+        const double a = (sig * dt) / (2.0 * EPS0 * eps);
+        cag[2 * m + 0] = (float)((1.0 - a) / (1.0 + a));
+        cag[2 * m + 1] = (float)((1.0 / eps) / (1.0 + a));
+    }
+    const int N = p.n;
+    if (N < 0 || (N > 0 && (p.order < 1 || p.order > 8 || !(p.sigma_factor >= 0) || !(p.kappa_max >= 1) ||
+                            !(p.alpha_max >= 0) || !std::isfinite(p.sigma_factor) || !std::isfinite(p.kappa_max) ||
+                            !std::isfinite(p.alpha_max))))
+        return fail(FDTD_EINVAL, "CPML: need order 1..8, sigma_factor >= 0, kappa_max >= 1, alpha_max >= 0");
+    const double cdt = C0 * dt;
+    const double eta0 = 1.0 / (EPS0 * C0);
+    int off = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int nn = n[ax];
+        const double *dd = d[ax];
+        if (!dd) return fail(FDTD_EINVAL, "NULL cell sizes");
+        if (N > 0 && 2 * N >= nn) return fail(FDTD_EINVAL, "CPML layers must leave an interior on every axis");
+        for (int q = 0; q < nn; ++q)
+            if (!(dd[q] > 0) || !std::isfinite(dd[q])) return fail(FDTD_EINVAL, "cell sizes must be > 0");
+        const double smax_lo = N > 0 ? p.sigma_factor * 0.8 * (p.order + 1) / (eta0 * dd[0]) : 0.0;
+        const double smax_hi = N > 0 ? p.sigma_factor * 0.8 * (p.order + 1) / (eta0 * dd[nn - 1]) : 0.0;
+        for (int q = 0; q <= nn; ++q) {
+            float *g = gc + 2 * (off + q);
+            float *c = cp ? cp + 6 * (off + q) : nullptr;
+            g[0] = g[1] = 0.0f;
+            if (c) for (int v = 0; v < 6; ++v) c[v] = 0.0f;
+            for (int half = 0; half < 2; ++half) {      // 0: H at cell q (q + 1/2), 1: E at node q
+                if (half == 0 && q == nn) continue;
+                if (half == 1 && (q == 0 || q == nn)) continue;
+                const double pos = half == 0 ? q + 0.5 : (double)q;
+                double rho = 0.0, smax = 0.0;
+                if (N > 0 && pos < N) { rho = N - pos; smax = smax_lo; }
+                else if (N > 0 && pos > nn - N) { rho = pos - (nn - N); smax = smax_hi; }
+                const bool inside = half == 0 ? (q < N || q >= nn - N) : ((q > 0 && q < N) || (q > nn - N && q < nn));
+                double kappa = 1.0, b = 0.0, a = 0.0;
+                if (rho > 0.0) {
+                    const double x = rho / N, xm = std::pow(x, p.order);
+                    const double sg = smax * xm, al = p.alpha_max * (1.0 - x);
+                    kappa = 1.0 + (p.kappa_max - 1.0) * xm;
+                    b = std::exp(-(sg / kappa + al) * dt / EPS0);
+                    a = sg > 0.0 ? sg * (b - 1.0) / (kappa * (sg + kappa * al)) : 0.0;
+                }
+                const double size = half == 0 ? dd[q] : (dd[q - 1] + dd[q]) / 2.0;
+                g[half] = (float)(kappa != 1.0 ? cdt / (kappa * size) : cdt / size);
+                if (c && N > 0 && inside) {
+                    c[3 * half + 0] = (float)b;
+                    c[3 * half + 1] = (float)a;
+                }
+                if (c) c[3 * half + 2] = (float)(cdt / size);
+            }
+        }
+        off += nn + 1;
+    }
+    return FDTD_OK;
+}
+
+// Courant bound of the smallest size per axis.  Sufficient: along an axis
+// the second difference through node q (dual size = mean of cells q-1 and
+// q) has row sum 4 / (d[q-1] d[q]) <= 4 / min d^2, the curl-curl operator of
+// a tensor-product grid is bounded by the sum over axes, and CPML stretching
+// (kappa >= 1) only lowers the coefficients.
+double graded_courant_limit(const int n[3], const double *const d[3])
+{
+    double sum = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const double m = *std::min_element(d[ax], d[ax] + n[ax]);
+        sum += 1.0 / (m * m);
+    }
+    return 1.0 / (C0 * std::sqrt(sum));
+}
+
+// Build and upload the per-index tables for cell sizes sz (empty: uniform)
+// and layers p; on success the solver adopts both.
+int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams &p)
+{
+    const int n[3] = {s->L.nx, s->L.ny, s->L.nz};
+    const double uni[3] = {s->dx, s->dy, s->dz};
+    std::vector<double> full[3];
+    const double *d[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        if (sz[ax].empty()) full[ax].assign(n[ax], uni[ax]);
+        else full[ax] = sz[ax];
+        d[ax] = full[ax].data();
+    }
+    fdtd_material table[256];
+    for (int m = 0; m < s->n_mat; ++m) {
+        table[m].eps_r = s->eps_h[m];
+        table[m].mu_r = 1.0;
+        table[m].sigma = s->sig_h[m];
+    }
+    const size_t nidx = (size_t)n[0] + n[1] + n[2] + 3;
+    float cag[2 * 256];
+    std::vector<float> gc(2 * nidx), cp(6 * nidx);
+    int rc = graded_tables(table, s->n_mat, n, d, s->dt, p, cag, gc.data(), cp.data());
+    if (rc) return rc;
+    const double limit = graded_courant_limit(n, d);
+    if (s->dt > limit)
+        return fail(FDTD_ECFL, "dt exceeds the Courant limit " + std::to_string(limit) + " of the smallest cells");
+    float coef[256 * 4];
+    for (int m = 0; m < s->n_mat; ++m) {
+        coef[4 * m + 0] = cag[2 * m + 0];
+        coef[4 * m + 1] = cag[2 * m + 1];
+        coef[4 * m + 2] = coef[4 * m + 3] = 0.0f;
+    }
+    // psi arrays: x-type 2n (ny+1)(nz+1), y-type 2n (nx+1)(nz+1), z-type 2n (nx+1)(ny+1)
+    long long off[12] = {};
+    size_t psi_bytes = 0;
+    if (p.n > 0) {
+        const long long per[3] = {2LL * p.n * (n[1] + 1) * (n[2] + 1), 2LL * p.n * (n[0] + 1) * (n[2] + 1),
+                                  2LL * p.n * (n[0] + 1) * (n[1] + 1)};
+        static const int axis_of[12] = {1, 2, 2, 0, 0, 1, 1, 2, 2, 0, 0, 1};   // PsiArray order
+        long long at = 0;
+        for (int q = 0; q < 12; ++q) {
+            off[q] = at;
+            at += per[axis_of[q]];
+        }
+        psi_bytes = (size_t)at * sizeof(float);
+    }
+    hipError_t e;
+    if (!s->gc_d && (e = hipMalloc(&s->gc_d, gc.size() * sizeof(float)))) {
+        s->gc_d = nullptr;
+        return hip_fail(e, "hipMalloc(graded coefficients)");
+    }
+    if (p.n > 0 && !s->cp_d && (e = hipMalloc(&s->cp_d, cp.size() * sizeof(float)))) {
+        s->cp_d = nullptr;
+        return hip_fail(e, "hipMalloc(CPML coefficients)");
+    }
+    if (psi_bytes != s->psi_bytes) {
+        free_dev(s->psi_d);
+        s->psi_d = nullptr;
+        s->psi_bytes = 0;
+        if (psi_bytes && (e = hipMalloc(&s->psi_d, psi_bytes))) {
+            s->psi_d = nullptr;
+            return hip_fail(e, "hipMalloc(CPML state)");
+        }
+        s->psi_bytes = psi_bytes;
+    }
+    if ((e = hipMemcpyAsync(s->gc_d, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipMemcpyAsync(s->coef_d, coef, s->n_mat * sizeof(float4), hipMemcpyHostToDevice, s->st)) ||
+        (p.n > 0 && (e = hipMemcpyAsync(s->cp_d, cp.data(), cp.size() * sizeof(float), hipMemcpyHostToDevice, s->st))) ||
+        (psi_bytes && (e = hipMemsetAsync(s->psi_d, 0, psi_bytes, s->st))) ||
+        (e = hipStreamSynchronize(s->st)))
+        return hip_fail(e, "upload graded coefficients");
+    std::memcpy(s->coef_h, coef, s->n_mat * 4 * sizeof(float));
+    for (int ax = 0; ax < 3; ++ax) s->sizes[ax] = sz[ax];
+    s->pml = p;
+    std::memcpy(s->psi_off, off, sizeof(off));
+    if (s->T_auto) s->T = auto_T(s);
+    return FDTD_OK;
+}
+
+yee::Cpml cpml_args(const fdtd_solver *s)
+{
+    yee::Cpml c;
+    c.n = s->pml.n;
+    c.cp = s->cp_d;
+    c.psi = s->psi_d;
+    std::memcpy(c.off, s->psi_off, sizeof(c.off));
+    return c;
+}
+
 }  // namespace
 
 extern "C" {
@@ -427,33 +623,27 @@ int fdtd_graded_coefficients(const fdtd_material *table, int n_materials, int nx
                              const double *dx, const double *dy, const double *dz, double dt,
                              float *cag, float *gc)
 {
-    if (!table || !cag || !gc || !dx || !dy || !dz || n_materials < 1 || n_materials > 256)
-        return fail(FDTD_EINVAL, "NULL argument or bad table");
-    if (nx < 2 || ny < 2 || nz < 2 || !(dt > 0)) return fail(FDTD_EINVAL, "bad dimensions or dt");
-    for (int m = 0; m < n_materials; ++m) {
-        const double eps = table[m].eps_r, sig = table[m].sigma;
-        if (!(eps > 0) || !(sig >= 0) || table[m].mu_r != 1.0)
-            return fail(FDTD_EINVAL, "material " + std::to_string(m) + ": need eps_r > 0, sigma >= 0, mu_r = 1");
-        const double a = (sig * dt) / (2.0 * EPS0 * eps);
-        cag[2 * m + 0] = (float)((1.0 - a) / (1.0 + a));
-        cag[2 * m + 1] = (float)((1.0 / eps) / (1.0 + a));
-    }
     const int n[3] = {nx, ny, nz};
     const double *d[3] = {dx, dy, dz};
-    const double cdt = C0 * dt;
-    float *g = gc;
-    for (int ax = 0; ax < 3; ++ax) {
-        for (int q = 0; q < n[ax]; ++q)
-            if (!(d[ax][q] > 0) || !std::isfinite(d[ax][q])) return fail(FDTD_EINVAL, "cell sizes must be > 0");
-        // node q: primal factor of cell q (none past the last node), dual
-        // factor of the mean of cells q-1 and q (none on the walls)
-        for (int q = 0; q <= n[ax]; ++q) {
-            g[2 * q + 0] = q < n[ax] ? (float)(cdt / d[ax][q]) : 0.0f;
-            g[2 * q + 1] = (q > 0 && q < n[ax]) ? (float)(cdt / ((d[ax][q - 1] + d[ax][q]) / 2.0)) : 0.0f;
-        }
-        g += 2 * (n[ax] + 1);
-    }
-    return FDTD_OK;
+    return graded_tables(table, n_materials, n, d, dt, CpmlParams(), cag, gc, nullptr);
+}
+
+int fdtd_cpml_coefficients(const fdtd_material *table, int n_materials, int nx, int ny, int nz,
+                           const double *dx, const double *dy, const double *dz, double dt,
+                           int thickness, int order, double sigma_factor, double kappa_max, double alpha_max,
+                           float *cag, float *gc, float *cp)
+{
+    if (!cp) return fail(FDTD_EINVAL, "NULL argument");
+    if (thickness < 1) return fail(FDTD_EINVAL, "CPML thickness must be >= 1");
+    CpmlParams p;
+    p.n = thickness;
+    p.order = order;
+    p.sigma_factor = sigma_factor;
+    p.kappa_max = kappa_max;
+    p.alpha_max = alpha_max;
+    const int n[3] = {nx, ny, nz};
+    const double *d[3] = {dx, dy, dz};
+    return graded_tables(table, n_materials, n, d, dt, p, cag, gc, cp);
 }
 
 int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy, double dz, double dt,
@@ -549,44 +739,27 @@ int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const d
     if (!s || !dx || !dy || !dz) return fail(FDTD_EINVAL, "NULL argument");
     if (s->steps > 0) return fail(FDTD_ESTATE, "spacing must be set before the first step");
     if (s->storage != FDTD_FP32) return fail(FDTD_EINVAL, "graded spacing needs FP32 storage");
-    const int nx = s->L.nx, ny = s->L.ny, nz = s->L.nz;
-    fdtd_material table[256];
-    for (int m = 0; m < s->n_mat; ++m) {
-        table[m].eps_r = s->eps_h[m];
-        table[m].mu_r = 1.0;
-        table[m].sigma = s->sig_h[m];
-    }
-    float cag[2 * 256];
-    std::vector<float> gc(2 * (size_t)(nx + ny + nz + 3));
-    int rc = fdtd_graded_coefficients(table, s->n_mat, nx, ny, nz, dx, dy, dz, s->dt, cag, gc.data());
-    if (rc) return rc;
-    // Courant bound of the smallest size per axis.  Sufficient: along an axis
-    // the second difference through node q (dual size = mean of cells q-1
-    // and q) has row sum 4 / (d[q-1] d[q]) <= 4 / min d^2, and the curl-curl
-    // operator of a tensor-product grid is bounded by the sum over axes.
-    const double mx = *std::min_element(dx, dx + nx), my = *std::min_element(dy, dy + ny),
-                 mz = *std::min_element(dz, dz + nz);
-    const double limit = 1.0 / (C0 * std::sqrt(1.0 / (mx * mx) + 1.0 / (my * my) + 1.0 / (mz * mz)));
-    if (s->dt > limit) return fail(FDTD_ECFL, "dt exceeds the Courant limit " + std::to_string(limit) +
-                                              " of the smallest cells");
-    float coef[256 * 4];
-    for (int m = 0; m < s->n_mat; ++m) {
-        coef[4 * m + 0] = cag[2 * m + 0];
-        coef[4 * m + 1] = cag[2 * m + 1];
-        coef[4 * m + 2] = coef[4 * m + 3] = 0.0f;
-    }
-    hipError_t e;
-    if (!s->gc_d && (e = hipMalloc(&s->gc_d, gc.size() * sizeof(float)))) {
-        s->gc_d = nullptr;
-        return hip_fail(e, "hipMalloc(graded coefficients)");
-    }
-    if ((e = hipMemcpyAsync(s->gc_d, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice, s->st)) ||
-        (e = hipMemcpyAsync(s->coef_d, coef, s->n_mat * sizeof(float4), hipMemcpyHostToDevice, s->st)) ||
-        (e = hipStreamSynchronize(s->st)))
-        return hip_fail(e, "upload graded coefficients");
-    std::memcpy(s->coef_h, coef, s->n_mat * 4 * sizeof(float));
-    if (s->T_auto) s->T = auto_T(s);
-    return FDTD_OK;
+    std::vector<double> sz[3] = {std::vector<double>(dx, dx + s->L.nx), std::vector<double>(dy, dy + s->L.ny),
+                                 std::vector<double>(dz, dz + s->L.nz)};
+    return apply_graded(s, sz, s->pml);
+}
+
+int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor, double kappa_max,
+                  double alpha_max)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (s->steps > 0) return fail(FDTD_ESTATE, "CPML layers must be set before the first step");
+    if (s->storage != FDTD_FP32) return fail(FDTD_EINVAL, "CPML layers need FP32 storage");
+    if (thickness < 0) return fail(FDTD_EINVAL, "negative CPML thickness");
+    if (thickness > 0 && s->kernel == FDTD_KERNEL_FUSED)
+        return fail(FDTD_EINVAL, "CPML layers run on the plain kernel; set kernel AUTO or PLAIN");
+    CpmlParams p;
+    p.n = thickness;
+    p.order = order;
+    p.sigma_factor = sigma_factor;
+    p.kappa_max = kappa_max;
+    p.alpha_max = alpha_max;
+    return apply_graded(s, s->sizes, p);
 }
 
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
@@ -602,6 +775,8 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
         return fail(FDTD_EINVAL, "the plain kernel needs FP32 storage");
     if (kernel == FDTD_KERNEL_FUSED && !yee::fused_fits(s->L, s->storage, time_block))
         return fail(FDTD_EINVAL, "grid planes too large for the fused kernel; use the plain kernel");
+    if (kernel == FDTD_KERNEL_FUSED && s->pml.n > 0)
+        return fail(FDTD_EINVAL, "CPML layers run on the plain kernel");
     s->kernel = kernel;
     s->T = time_block;
     s->T_auto = automatic;
@@ -630,6 +805,8 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
     std::memset(&ctrl, 0, sizeof(ctrl));
     s->cur = 0;
     s->block = 0;
+    if (s->psi_d && (e = hipMemsetAsync(s->psi_d, 0, s->psi_bytes, s->st)))
+        return hip_fail(e, "clear CPML state");
     if (!host) {
         if ((e = hipMemsetAsync(s->fbuf[0], 0, s->d.fbytes, s->st)) ||
             (e = hipMemcpyAsync(s->ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s->st)) ||
@@ -772,7 +949,7 @@ int fdtd_step(fdtd_solver *s, int n_steps)
     // AUTO is the fused kernel, or the plain one for grids whose planes are
     // too large for the fused kernel's chunk addressing (FP32 only: create
     // rejects 16-bit storage for such grids).
-    const bool plain = s->kernel == FDTD_KERNEL_PLAIN ||
+    const bool plain = s->kernel == FDTD_KERNEL_PLAIN || s->pml.n > 0 ||
                        (s->kernel == FDTD_KERNEL_AUTO && !yee::fused_fits(s->L, s->storage, 1));
     if (plain) {
         yee::PlainArgs a;
@@ -783,6 +960,7 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         a.n_mat = s->n_mat;
         a.chx = s->ch[0]; a.chy = s->ch[1]; a.chz = s->ch[2];
         a.gc = s->gc_d;
+        a.pml = cpml_args(s);
         for (int q = 0; q < n_steps; ++q) {
             if ((e = yee::launch_plain_step(a, src, probe, s->steps + q, s->st))) return hip_fail(e, "plain step");
         }
@@ -1008,6 +1186,8 @@ void fdtd_destroy(fdtd_solver *s)
     free_dev(s->coef_d);
     free_dev(s->eps_d);
     free_dev(s->gc_d);
+    free_dev(s->cp_d);
+    free_dev(s->psi_d);
     free_dev(s->src_pos_d);
     free_dev(s->src_wave_d);
     free_dev(s->samples_d);

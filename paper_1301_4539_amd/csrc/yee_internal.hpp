@@ -84,6 +84,22 @@ struct BatchArgs {
     FusedArgs s[MAX_BATCH];
 };
 
+// CPML absorbing layers of n cells on every face.  cp: per axis (x, y, z)
+// and node index q, 6 floats {b_h, a_h, c dt / d[q], b_e, a_e, c dt / d'[q]}
+// (H values at cell q, E values at node q).  psi: the auxiliary state, one
+// array per (component, derivative axis) in the order of PsiArray, kept only
+// in the layers: an index q along the derivative axis maps to the slab slot
+// l = q (q < n) or q - (n_axis - 2 n) (upper layer), l < 2 n, and the arrays
+// are laid out x-type (k (ny+1) + j) 2n + l, y-type (k 2n + l)(nx+1) + i,
+// z-type (l (ny+1) + j)(nx+1) + i.
+enum PsiArray { PS_HXY = 0, PS_HXZ, PS_HYZ, PS_HYX, PS_HZX, PS_HZY, PS_EXY, PS_EXZ, PS_EYZ, PS_EYX, PS_EZX, PS_EZY };
+struct Cpml {
+    int n;                // cells per layer (0: no layers)
+    const float *cp;
+    float *psi;
+    long long off[12];    // start of each psi array
+};
+
 struct PlainArgs {
     Layout L;
     float *f;             // in-place FP32 fields
@@ -91,7 +107,9 @@ struct PlainArgs {
     const float4 *coef;
     int n_mat;
     float chx, chy, chz;
-    const float2 *gc;     // graded spacing, as in FusedArgs (null: uniform)
+    const float2 *gc;     // graded spacing, as in FusedArgs (null: uniform); with
+                          // CPML, c dt / (kappa size) so the layers' stretch is folded in
+    Cpml pml;
 };
 
 struct DiagArgs {

@@ -70,10 +70,13 @@ def lib():
         L.fdtd_coefficients.argtypes = [C.POINTER(_Material), i, d, d, d, d, vp, vp]
         L.fdtd_set_spacing.argtypes = [vp, vp, vp, vp]
         L.fdtd_graded_coefficients.argtypes = [C.POINTER(_Material), i, i, i, i, vp, vp, vp, d, vp, vp]
+        L.fdtd_set_cpml.argtypes = [vp, i, i, d, d, d]
+        L.fdtd_cpml_coefficients.argtypes = [C.POINTER(_Material), i, i, i, i, vp, vp, vp, d, i, i, d, d, d,
+                                             vp, vp, vp]
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
-                     "fdtd_graded_coefficients"):
+                     "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -117,6 +120,22 @@ def graded_coefficients(eps_r, sigma, dx, dy, dz, dt, mu_r=None):
     _check(lib().fdtd_graded_coefficients(arr, n, len(dx), len(dy), len(dz), dx.ctypes.data, dy.ctypes.data,
                                           dz.ctypes.data, dt, cag.ctypes.data, gc.ctypes.data))
     return cag, gc
+
+
+def cpml_coefficients(eps_r, sigma, dx, dy, dz, dt, thickness, order=3, sigma_factor=1.0, kappa_max=1.0,
+                      alpha_max=0.0, mu_r=None):
+    """The library's FP32 CPML tables: cag (n_mat, 2), gc (n_idx, 2) with kappa
+    folded in, cp (n_idx, 6) = b_h, a_h, c dt / d, b_e, a_e, c dt / d'."""
+    arr, n = _materials(eps_r, sigma, mu_r)
+    dx, dy, dz = _sizes(dx, dy, dz)
+    nidx = len(dx) + len(dy) + len(dz) + 3
+    cag = np.zeros((n, 2), np.float32)
+    gc = np.zeros((nidx, 2), np.float32)
+    cp = np.zeros((nidx, 6), np.float32)
+    _check(lib().fdtd_cpml_coefficients(arr, n, len(dx), len(dy), len(dz), dx.ctypes.data, dy.ctypes.data,
+                                        dz.ctypes.data, dt, thickness, order, sigma_factor, kappa_max, alpha_max,
+                                        cag.ctypes.data, gc.ctypes.data, cp.ctypes.data))
+    return cag, gc, cp
 
 
 def step_batch(solvers, n_steps):
@@ -172,6 +191,8 @@ class Solver:
             s.add_probe(c, i, j, k)
         if getattr(wl, "spacing", None) is not None:
             s.set_spacing(*wl.spacing)
+        if getattr(wl, "cpml", None):
+            s.set_cpml(**wl.cpml)
         if wl.init_fields is not None:
             s.set_fields(wl.init_fields.astype(np.float32))
         return s
@@ -184,6 +205,11 @@ class Solver:
         dx, dy, dz = _sizes(dx, dy, dz)
         assert (len(dx), len(dy), len(dz)) == (self.nx, self.ny, self.nz)
         _check(lib().fdtd_set_spacing(self._h, dx.ctypes.data, dy.ctypes.data, dz.ctypes.data))
+
+    def set_cpml(self, thickness, order=3, sigma_factor=1.0, kappa_max=1.0, alpha_max=0.0):
+        """CPML absorbing layers of `thickness` cells on every face (0 removes them)."""
+        _check(lib().fdtd_set_cpml(self._h, int(thickness), int(order), float(sigma_factor), float(kappa_max),
+                                   float(alpha_max)))
 
     def set_tiling(self, variant=0, z_chunk=0):
         _check(lib().fdtd_set_tiling(self._h, variant, z_chunk))

@@ -18,6 +18,8 @@ structure of the configurations this library is benchmarked on:
 * ``serving``   -- 256 requests with random anisotropic grids.
 * ``graded256`` -- 256^3 with graded cell sizes (fine core, geometric growth
   to coarse cells near the walls), otherwise as ``spheres256``.
+* ``open256``   -- ``spheres256`` in open space: 10-cell CPML layers on
+  every face instead of reflecting walls.
 
 All randomness comes from splitmix64 (Steele, Lea, Flood 2014), drawn in a
 fixed order: material table, spheres (cx, cy, cz, radius, index), sources,
@@ -121,6 +123,9 @@ class Workload:
     # graded spacing: per-index cell sizes (dx (nx,), dy (ny,), dz (nz,)) in
     # metres; None = uniform dx, dy, dz
     spacing: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
+    # CPML absorbing layers: dict(thickness, order, sigma_factor, kappa_max,
+    # alpha_max); None = PEC walls only
+    cpml: Optional[dict] = None
 
     @property
     def cells(self) -> int:
@@ -329,6 +334,16 @@ def graded(n: int, n_spheres: int, n_steps: int, seed: int, d_fine: float = 0.5e
 
 def graded256(n_steps: int = 1000) -> Workload:
     return graded(256, 40, n_steps, seed=1006, name="graded256")
+
+
+CPML_LAYER = dict(thickness=10, order=3, sigma_factor=1.0, kappa_max=5.0, alpha_max=0.05)
+
+
+def open256(n_steps: int = 1000) -> Workload:
+    """spheres256 radiating into open space: CPML layers on every face."""
+    wl = spheres(256, 256, 256, 40, n_steps, seed=1001, n_sources=1, name="open256")
+    wl.cpml = dict(CPML_LAYER)
+    return wl
 
 
 @dataclasses.dataclass

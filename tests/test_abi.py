@@ -94,3 +94,28 @@ def test_graded_coefficients_reject_bad_sizes():
     with pytest.raises(fdtd.FdtdError) as e:
         fdtd.graded_coefficients([1.0], [0.0], bad, sx, sx, 1e-12)
     assert e.value.code == fdtd.EINVAL
+
+
+def test_cpml_coefficients_match_oracle_rounded_once():
+    rng = np.random.default_rng(2)
+    eps = np.concatenate([[1.0], rng.uniform(1, 12, 7)])
+    sig = np.concatenate([[0.0], rng.uniform(0, 0.05, 7)])
+    sx, sy, sz = (rng.uniform(0.5e-3, 1.5e-3, n) for n in (21, 17, 25))
+    dt = W.courant_dt_graded(sx, sy, sz)
+    for layer in [dict(thickness=5, order=3, sigma_factor=1.0, kappa_max=5.0, alpha_max=0.05),
+                  dict(thickness=8, order=4, sigma_factor=0.7, kappa_max=1.0, alpha_max=0.0)]:
+        cag, gc, cp = fdtd.cpml_coefficients(eps, sig, sx, sy, sz, dt, **layer)
+        r_cag, r_hc, r_ec, r_cp = oracle.cpml_coefficients(eps, sig, dt, sx, sy, sz, **layer)
+        assert np.array_equal(cag, r_cag.astype(np.float32))
+        assert np.array_equal(gc[:, 0], r_hc.astype(np.float32))
+        assert np.array_equal(gc[:, 1], r_ec.astype(np.float32))
+        assert np.array_equal(cp, r_cp.astype(np.float32))
+
+
+def test_cpml_coefficients_reject_bad_layers():
+    s = np.full(10, 1e-3)
+    for bad in [dict(thickness=5), dict(thickness=2, order=0), dict(thickness=2, kappa_max=0.5),
+                dict(thickness=2, alpha_max=-1.0), dict(thickness=0)]:
+        with pytest.raises(fdtd.FdtdError) as e:
+            fdtd.cpml_coefficients([1.0], [0.0], s, s, s, 1e-12, **bad)
+        assert e.value.code == fdtd.EINVAL
