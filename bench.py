@@ -233,6 +233,22 @@ def main():
         extras["graded_spacing"] = {"workload": wg.name, "value": vg, "unit": "G cell-updates/s",
                                     "ratio_vs_uniform": vg / value}
         print(f"[bench] graded spacing ({wg.name}): {vg:.2f} G cell-updates/s", file=sys.stderr, flush=True)
+        # open space: CPML layers on every face (plain kernel family), and the
+        # plain kernels without layers on the same grid for reference
+        def plain_rate(w):
+            sp = fdtd.Solver.from_workload(w, kernel=fdtd.KERNEL_PLAIN)
+            try:
+                n = max(1, args.steps // 5)
+                sp.step(10)
+                return w.cells * n / time_steps(sp, n, torch, stream) / 1e9
+            finally:
+                sp.close()
+        vo = plain_rate(W.open256())
+        vp = plain_rate(wl)
+        extras["cpml"] = {"workload": "open256", "value": vo, "unit": "G cell-updates/s", "kernel": "plain",
+                          "plain_without_layers": vp, "layer": W.CPML_LAYER}
+        print(f"[bench] CPML (open256, plain kernels): {vo:.2f} G cell-updates/s; plain without layers "
+              f"{vp:.2f}", file=sys.stderr, flush=True)
         # a full solve from host buffers: create (material upload), upload of a
         # host initial state, the solve, read-back of fields and probes
         torch.cuda.synchronize()
