@@ -34,23 +34,24 @@ SERVING_RATE = 12.4
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("yee_fused.hpp", "yee_fused.hip", "yee_device.hpp", "yee_internal.hpp"):
+    for name in ("yee_fused.hpp", "yee_fused.hip", "yee_device.hpp", "yee_internal.hpp", "yee_plain.hip"):
         with open(os.path.join(ROOT, "paper_1301_4539_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, storage: str, T: int):
+def measured_traffic(workload: str, storage: str, T):
     """Physical HBM bytes per launch (FETCH_SIZE + WRITE_SIZE from rocprofv3,
     scaled by the copy-kernel calibration) from the committed summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source; else None.  T: steps per pass of
+    the fused kernel, or "plain" (bytes per step of the two plain kernels)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             d = json.load(f)
-        e = d[f"{workload}/{storage}/T{T}"]
+        e = d[f"{workload}/{storage}/" + (T if isinstance(T, str) else f"T{T}")]
         if e.get("kernel_hash") != kernel_source_hash():
             return None
         return float(e["bytes_per_launch"])
@@ -126,7 +127,10 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--T", type=int, default=4, help="steps per HBM pass of the fused kernel (1..4)")
-    ap.add_argument("--workload", default="spheres256", choices=["spheres256", "spheres512", "cavity402"])
+    ap.add_argument("--workload", default="spheres256",
+                    choices=["spheres256", "spheres512", "cavity402", "graded256", "open256"])
+    ap.add_argument("--kernel", default="fused", choices=["fused", "plain"],
+                    help="kernel family of the timed run (open256's CPML layers need plain)")
     ap.add_argument("--tiling", type=int, default=0, help="fused-kernel tile variant (0 = auto, 1..3)")
     ap.add_argument("--zchunk", type=int, default=0, help="planes per z chunk (0 = automatic)")
     ap.add_argument("--solves", type=int, default=5, help="full solves for the latency percentiles")
@@ -163,24 +167,31 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    wl = {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402}[args.workload]()
+    wl = {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402,
+          "graded256": W.graded256, "open256": W.open256}[args.workload]()
     cells = wl.cells
     T = args.T
+    plain = args.kernel == "plain"
+    if wl.cpml and not plain:
+        print("bench.py: CPML layers run on the plain kernels; pass --kernel plain", file=sys.stderr)
+        sys.exit(2)
 
     print(f"[bench] workload {wl.name} {wl.nx}x{wl.ny}x{wl.nz}, T={T}, warmup {args.warmup}, "
           f"steps {args.steps}", file=sys.stderr, flush=True)
     storage = {"fp32": W.FP32, "fp16": W.FP16, "bf16": W.BF16}[args.storage]
-    s = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_FUSED, time_block=T)
+    s = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_PLAIN if plain else fdtd.KERNEL_FUSED,
+                                  time_block=T)
     s.set_tiling(args.tiling, args.zchunk)
     if args.warmup:
         s.step(args.warmup)
     start = s.steps_done()
     t = time_steps(s, args.steps, torch, stream)
-    launches = launches_for(start, args.steps, T)
+    # a plain "launch" is one step's H and E kernel pair
+    launches = args.steps if plain else launches_for(start, args.steps, T)
     value = cells * args.steps / t / 1e9
     b_alg = roofline.algorithmic_bytes(4)
     achieved = b_alg * cells * args.steps / t / 1e9          # GB/s, algorithmic
-    traffic = measured_traffic(wl.name, "fp32", T)
+    traffic = measured_traffic(wl.name, "fp32", "plain" if plain else T)
     print(f"[bench] {args.storage}: {value:.2f} G cell-updates/s, {t * 1e3 / launches:.3f} ms per launch",
           file=sys.stderr, flush=True)
 
@@ -231,7 +242,8 @@ def main():
         finally:
             sg.close()
         extras["graded_spacing"] = {"workload": wg.name, "value": vg, "unit": "G cell-updates/s",
-                                    "ratio_vs_uniform": vg / value}
+                                    "ratio_vs_uniform": vg / value, "T": 3,
+                                    "traffic": measured_traffic(wg.name, "fp32", 3)}
         print(f"[bench] graded spacing ({wg.name}): {vg:.2f} G cell-updates/s", file=sys.stderr, flush=True)
         # open space: CPML layers on every face (plain kernel family), and the
         # plain kernels without layers on the same grid for reference
@@ -246,7 +258,8 @@ def main():
         vo = plain_rate(W.open256())
         vp = plain_rate(wl)
         extras["cpml"] = {"workload": "open256", "value": vo, "unit": "G cell-updates/s", "kernel": "plain",
-                          "plain_without_layers": vp, "layer": W.CPML_LAYER}
+                          "plain_without_layers": vp, "layer": W.CPML_LAYER,
+                          "traffic_per_step": measured_traffic("open256", "fp32", "plain")}
         print(f"[bench] CPML (open256, plain kernels): {vo:.2f} G cell-updates/s; plain without layers "
               f"{vp:.2f}", file=sys.stderr, flush=True)
         # a full solve from host buffers: create (material upload), upload of a
@@ -296,14 +309,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "storage": "fp32",
-                   "kernel": "fused", "T": T, "materials": len(wl.eps_r),
-                   "spheres": {"spheres256": 40, "spheres512": 200}.get(wl.name, 0), "sources": len(wl.sources),
+                   "kernel": args.kernel, "T": None if plain else T, "materials": len(wl.eps_r),
+                   "spheres": {"spheres256": 40, "spheres512": 200, "graded256": 40, "open256": 40}.get(wl.name, 0),
+                   "sources": len(wl.sources),
                    "probes": len(wl.probes), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": roofline.HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / roofline.HBM_PEAK_GBPS,
                      "traffic": traffic,
                      "alg_bytes_per_launch": b_alg * cells * args.steps / launches,
-                     "kernel": f"yee_fused<T={T},fp32>", "bytes_per_cell_update": b_alg,
+                     "kernel": "h_plain+e_plain<fp32>" if plain else f"yee_fused<T={T},fp32>",
+                     "bytes_per_cell_update": b_alg,
                      "avg_launch_ms": t * 1e3 / launches, "launches": launches},
     }
     line.update(extras)

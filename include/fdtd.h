@@ -88,9 +88,13 @@ typedef struct {
 /* Diagnostics of the current state (E^n, H^{n-1/2}), reduced in FP64 in a
  * fixed order (results do not depend on scheduling).
  *   energy  = 1/2 sum eps_r E^n.E^n + 1/2 sum H^{n-1/2}.H^{n+1/2}, in units of
- *             eps0*dx*dy*dz; conserved exactly by a lossless PEC box
+ *             eps0*dx*dy*dz; conserved exactly by a lossless PEC box.  With
+ *             graded spacing each term is weighted by its volume (edge
+ *             length x dual face area for E, face area x dual edge length for
+ *             H, dual sizes halved on the walls), in units of eps0 (m^3)
  *   div_e_* = div(eps_r E) at interior nodes; div_h_* = div(H) at cell
- *             centres (both in V/m^2): largest magnitude and sum of squares
+ *             centres (both in V/m^2; differences over the dual and the cell
+ *             sizes): largest magnitude and sum of squares
  *   max_abs = largest |value| of each component */
 typedef struct {
     double energy;
@@ -136,7 +140,8 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz,
  *   storage only (else FDTD_EINVAL); only before the first step
  *   (FDTD_ESTATE); may be called again to replace the sizes.  Arrays are
  *   copied.  Graded solvers run with fdtd_step (PLAIN or FUSED, any T);
- *   fdtd_step_batch and fdtd_diagnostics reject them (FDTD_EINVAL). */
+ *   fdtd_step_batch rejects them (FDTD_EINVAL).  fdtd_diagnostics weights
+ *   each term by its volume (see fdtd_diag). */
 int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const double *dz);
 
 /* CPML absorbing layers of `thickness` cells inside every face of the box
@@ -162,7 +167,8 @@ int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const d
  *   on the PLAIN kernel family (AUTO selects it; FUSED is rejected,
  *   FDTD_EINVAL); combines with fdtd_set_spacing in either order.  The psi
  *   state starts at zero and is cleared by fdtd_set_fields.
- *   fdtd_step_batch and fdtd_diagnostics reject solvers with layers. */
+ *   fdtd_step_batch and fdtd_diagnostics reject solvers with layers
+ *   (FDTD_EINVAL). */
 int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor, double kappa_max,
                   double alpha_max);
 

@@ -68,6 +68,8 @@ def lib():
         L.orc_energy_graded_f64.argtypes = [_i, _i, _i, _dp, _dp, _dp, _dp, _dp, _u8, _dp]
         L.orc_energy_graded_f64.restype = C.c_double
         L.orc_divergence_graded_f64.argtypes = [_i, _i, _i, _dp, _dp, _dp, _dp, _u8, _dp, _dp, _dp]
+        L.orc_energy_graded_f32.argtypes = [_i, _i, _i, _dp, _dp, _dp, _fp, _dp, _u8, _fp]
+        L.orc_energy_graded_f32.restype = C.c_double
         L.orc_cpml_coefficients.argtypes = [_i, _dp, _dp, C.c_double, _i, _i, _i, _dp, _dp, _dp, _i, _i,
                                             C.c_double, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
         L.orc_cpml_coefficients.restype = _i
@@ -291,6 +293,10 @@ class Problem:
         """Discrete energy (FP64): in units of eps0*dx*dy*dz on uniform grids,
         of eps0 (volumes in m^3) on graded ones."""
         if self.graded:
+            if f.dtype == np.float32:
+                f = np.ascontiguousarray(f)
+                return lib().orc_energy_graded_f32(self.nx, self.ny, self.nz, self.sx, self.sy, self.sz,
+                                                   self.hc32, self.eps_r, self.mat, f)
             f = np.ascontiguousarray(f, dtype=np.float64)
             return lib().orc_energy_graded_f64(self.nx, self.ny, self.nz, self.sx, self.sy, self.sz, self.hc64,
                                                self.eps_r, self.mat, f)

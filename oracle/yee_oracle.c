@@ -820,13 +820,11 @@ static void dual_sizes(int n, const double *d, double *dd)
         dd[q] = q == 0 ? d[0] / 2.0 : (q == n ? d[n - 1] / 2.0 : (d[q - 1] + d[q]) / 2.0);
 }
 
-double orc_energy_graded_f64(int nx, int ny, int nz, const double *dx, const double *dy, const double *dz,
-                             const double *hc, const double *eps_r, const uint8_t *mat, const double *f)
+/* weighted sum of the energy terms; h1 holds H^{n+1/2} (3 components) */
+static double graded_energy_sum(int nx, int ny, int nz, const double *dx, const double *dy, const double *dz,
+                                const double *eps_r, const uint8_t *mat, const double *f, const double *h1)
 {
     grid_t g = mkgrid(nx, ny, nz);
-    double *tmp = (double *)malloc(6 * g.n * sizeof(double));
-    memcpy(tmp, f, 6 * g.n * sizeof(double));
-    orc_h_half_graded_f64(nx, ny, nz, hc, tmp);
     double *dxd = (double *)malloc(((size_t)nx + ny + nz + 3) * sizeof(double));
     double *dyd = dxd + nx + 1, *dzd = dyd + ny + 1;
     dual_sizes(nx, dx, dxd);
@@ -853,7 +851,7 @@ double orc_energy_graded_f64(int nx, int ny, int nz, const double *dx, const dou
                 }
                 for (int c = 0; c < 3; c++)
                     if (in_range(&g, HX + c, i, j, k))
-                        acc += 0.5 * f[(size_t)(3 + c) * g.n + p] * tmp[(size_t)(3 + c) * g.n + p] * vh[c];
+                        acc += 0.5 * f[(size_t)(3 + c) * g.n + p] * h1[(size_t)c * g.n + p] * vh[c];
             }
         plane[k] = acc;
     }
@@ -861,6 +859,35 @@ double orc_energy_graded_f64(int nx, int ny, int nz, const double *dx, const dou
     for (int k = 0; k <= nz; k++) w += plane[k];
     free(plane);
     free(dxd);
+    return w;
+}
+
+double orc_energy_graded_f64(int nx, int ny, int nz, const double *dx, const double *dy, const double *dz,
+                             const double *hc, const double *eps_r, const uint8_t *mat, const double *f)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    double *tmp = (double *)malloc(6 * g.n * sizeof(double));
+    memcpy(tmp, f, 6 * g.n * sizeof(double));
+    orc_h_half_graded_f64(nx, ny, nz, hc, tmp);
+    double w = graded_energy_sum(nx, ny, nz, dx, dy, dz, eps_r, mat, f, tmp + 3 * g.n);
+    free(tmp);
+    return w;
+}
+
+/* The same energy of FP32 fields, with H^{n+1/2} from the FP32 graded
+ * half-step (the operation order of the kernels), summed in FP64. */
+double orc_energy_graded_f32(int nx, int ny, int nz, const double *dx, const double *dy, const double *dz,
+                             const float *hc, const double *eps_r, const uint8_t *mat, const float *f)
+{
+    grid_t g = mkgrid(nx, ny, nz);
+    float *tmp = (float *)malloc(6 * g.n * sizeof(float));
+    memcpy(tmp, f, 6 * g.n * sizeof(float));
+    orc_h_half_graded_f32(nx, ny, nz, hc, tmp);
+    double *e = (double *)malloc(9 * g.n * sizeof(double));
+    for (size_t p = 0; p < 6 * g.n; p++) e[p] = (double)f[p];
+    for (size_t p = 0; p < 3 * g.n; p++) e[6 * g.n + p] = (double)tmp[3 * g.n + p];
+    double w = graded_energy_sum(nx, ny, nz, dx, dy, dz, eps_r, mat, e, e + 6 * g.n);
+    free(e);
     free(tmp);
     return w;
 }

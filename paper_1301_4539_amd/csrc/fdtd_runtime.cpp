@@ -214,6 +214,7 @@ struct fdtd_solver {
     std::vector<double> sizes[3];       // per-index cell sizes (empty: uniform dx, dy, dz)
     CpmlParams pml;                     // layers (pml.n == 0: none)
     float *cp_d = nullptr;              // per axis and index {b_h, a_h, c dt/d, b_e, a_e, c dt/d'}
+    double2 *gsz_d = nullptr;           // per axis and node (cell size or 0, dual size; half on walls)
     float *psi_d = nullptr;             // CPML auxiliary state in the layers
     size_t psi_bytes = 0;
     long long psi_off[12] = {};
@@ -515,6 +516,13 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
     const size_t nidx = (size_t)n[0] + n[1] + n[2] + 3;
     float cag[2 * 256];
     std::vector<float> gc(2 * nidx), cp(6 * nidx);
+    std::vector<double2> gsz(nidx);     // sizes for the diagnostics' volume weights
+    for (int ax = 0, off = 0; ax < 3; off += n[ax] + 1, ++ax)
+        for (int q = 0; q <= n[ax]; ++q) {
+            const double *dd = d[ax];
+            const double dual = q == 0 ? dd[0] / 2.0 : (q == n[ax] ? dd[n[ax] - 1] / 2.0 : (dd[q - 1] + dd[q]) / 2.0);
+            gsz[off + q] = make_double2(q < n[ax] ? dd[q] : 0.0, dual);
+        }
     int rc = graded_tables(table, s->n_mat, n, d, s->dt, p, cag, gc.data(), cp.data());
     if (rc) return rc;
     const double limit = graded_courant_limit(n, d);
@@ -545,6 +553,10 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
         s->gc_d = nullptr;
         return hip_fail(e, "hipMalloc(graded coefficients)");
     }
+    if (!s->gsz_d && (e = hipMalloc(&s->gsz_d, gsz.size() * sizeof(double2)))) {
+        s->gsz_d = nullptr;
+        return hip_fail(e, "hipMalloc(cell sizes)");
+    }
     if (p.n > 0 && !s->cp_d && (e = hipMalloc(&s->cp_d, cp.size() * sizeof(float)))) {
         s->cp_d = nullptr;
         return hip_fail(e, "hipMalloc(CPML coefficients)");
@@ -560,6 +572,7 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
         s->psi_bytes = psi_bytes;
     }
     if ((e = hipMemcpyAsync(s->gc_d, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipMemcpyAsync(s->gsz_d, gsz.data(), gsz.size() * sizeof(double2), hipMemcpyHostToDevice, s->st)) ||
         (e = hipMemcpyAsync(s->coef_d, coef, s->n_mat * sizeof(float4), hipMemcpyHostToDevice, s->st)) ||
         (p.n > 0 && (e = hipMemcpyAsync(s->cp_d, cp.data(), cp.size() * sizeof(float), hipMemcpyHostToDevice, s->st))) ||
         (psi_bytes && (e = hipMemsetAsync(s->psi_d, 0, psi_bytes, s->st))) ||
@@ -1106,7 +1119,7 @@ int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int
 int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
 {
     if (!s || !out) return fail(FDTD_EINVAL, "NULL argument");
-    if (s->gc_d) return fail(FDTD_EINVAL, "diagnostics are for uniform spacing only");
+    if (s->pml.n > 0) return fail(FDTD_EINVAL, "diagnostics are not defined with CPML layers");
     hipError_t e;
     if (!s->diag_part_d) {
         const size_t nb = (size_t)yee::diag_blocks(s->L);
@@ -1123,6 +1136,8 @@ int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
     a.n_mat = s->n_mat;
     a.chx = s->ch[0]; a.chy = s->ch[1]; a.chz = s->ch[2];
     a.idx = 1.0 / s->dx; a.idy = 1.0 / s->dy; a.idz = 1.0 / s->dz;
+    a.gc = s->gc_d;
+    a.gsz = s->gsz_d;
     a.partial = s->diag_part_d;
     a.sb = storage_block(s);
     if ((e = yee::launch_diag(s->storage, a, s->diag_out_d, s->st))) return hip_fail(e, "diagnostics");
@@ -1187,6 +1202,7 @@ void fdtd_destroy(fdtd_solver *s)
     free_dev(s->eps_d);
     free_dev(s->gc_d);
     free_dev(s->cp_d);
+    free_dev(s->gsz_d);
     free_dev(s->psi_d);
     free_dev(s->src_pos_d);
     free_dev(s->src_wave_d);

@@ -121,6 +121,11 @@ struct DiagArgs {
     int n_mat;
     float chx, chy, chz;
     double idx, idy, idz; // 1/dx, 1/dy, 1/dz
+    // graded spacing (null: uniform): the update factors as in FusedArgs, and
+    // per axis and node q the cell size d[q] (0 at q = n) and the dual size
+    // (half cells on the walls), x then y then z
+    const float2 *gc;
+    const double2 *gsz;
     double *partial;      // per block: 11 doubles
     StorageBlock sb;      // scale[par] decodes the stored fields
 };

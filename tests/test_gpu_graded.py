@@ -128,9 +128,6 @@ def test_set_spacing_rules():
         assert e.value.code == fdtd.EINVAL
         s.set_spacing(*sizes)
         with pytest.raises(fdtd.FdtdError) as e:
-            s.diagnostics()
-        assert e.value.code == fdtd.EINVAL
-        with pytest.raises(fdtd.FdtdError) as e:
             fdtd.step_batch([s], [2])
         assert e.value.code == fdtd.EINVAL
         s.step(2)
@@ -146,3 +143,48 @@ def test_set_spacing_rules():
         assert e.value.code == fdtd.EINVAL
     finally:
         s16.close()
+
+
+def test_graded_diagnostics_match_oracle():
+    import oracle
+    wl = graded_ragged(n_steps=25, seed=4250)
+    wl.init_fields = None
+    init = np.random.default_rng(5).standard_normal((6, wl.nz + 1, wl.ny + 1, wl.nx + 1)).astype(np.float32)
+    print("graded diagnostics, 25 steps", flush=True)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=3)
+    try:
+        s.set_fields(init)
+        s.step(25)
+        d = s.diagnostics()
+        f = s.read_fields()
+    finally:
+        s.close()
+    prob = oracle.Problem.from_workload(wl)
+    w = prob.energy(f)
+    de, dh = prob.divergence(f.astype(np.float64))
+    assert abs(d["energy"] - w) <= 1e-12 * abs(w)
+    assert abs(d["div_e_max"] - np.max(np.abs(de))) <= 1e-12 * np.max(np.abs(de))
+    assert abs(d["div_h_max"] - np.max(np.abs(dh))) <= 1e-12 * np.max(np.abs(dh))
+    assert abs(d["div_e_sumsq"] - np.sum(de * de)) <= 1e-10 * np.sum(de * de)
+    assert abs(d["div_h_sumsq"] - np.sum(dh * dh)) <= 1e-10 * np.sum(dh * dh)
+    for c in range(6):
+        assert d["max_abs"][c] == float(np.max(np.abs(f[c])))
+
+
+def test_graded_lossless_energy_conserved_on_gpu():
+    """The volume-weighted energy of a lossless graded PEC box stays constant
+    over 200 GPU steps (FP32 round-off)."""
+    wl = graded_ragged(n_steps=200, seed=4251)
+    wl.sigma[:] = 0.0
+    wl.sources, wl.waveforms = [], np.zeros((0, 200))
+    init = wl.init_fields.astype(np.float32)
+    wl.init_fields = None
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=3)
+    try:
+        s.set_fields(init)
+        w0 = s.diagnostics()["energy"]
+        s.step(200)
+        w1 = s.diagnostics()["energy"]
+    finally:
+        s.close()
+    assert abs(w1 - w0) < 1e-5 * w0

@@ -211,3 +211,20 @@ def test_graded_fp32_is_the_stated_operation_order():
                 dhy = np.float32(g[4, k, j, i] - g[4, k - 1, j, i])
                 t = np.float32(ca * g[0, k, j, i])
                 assert h[0, k, j, i] == fma(-cbz, dhy, fma(cby, dhz, t))
+
+
+def test_graded_fp32_energy_close_to_fp64_energy():
+    """The FP32-half-step form of the graded energy (what the GPU reports)
+    agrees with the FP64 form on the same fields to FP32 rounding."""
+    n = (9, 7, 8)
+    rng = np.random.default_rng(14)
+    sx, sy, sz = (_sizes(rng, m, spread=2.0) for m in n)
+    dt = _graded_dt(sx, sy, sz)
+    eps = np.array([1.0, 3.0])
+    mat = rng.integers(0, 2, size=n[::-1]).astype(np.uint8)
+    prob = _problem(n, (sx, sy, sz), eps, np.zeros(2), mat, dt)
+    f = rng.standard_normal((6, n[2] + 1, n[1] + 1, n[0] + 1)).astype(np.float32)
+    f[0:3][~W.interior_e_mask(*n)] = 0.0
+    w64 = prob.energy(f.astype(np.float64))
+    w32 = prob.energy(f)
+    assert abs(w32 - w64) < 1e-6 * w64
