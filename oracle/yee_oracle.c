@@ -37,7 +37,11 @@
  *   4. Probes: record the component at (i,j,k) (pin-point outputs, Sec. 4.2).
  *
  * Materials: each interior E edge takes eps_r and sigma of its owner cell,
- * the cell whose lowest corner is the edge's lower end; mu_r = 1.
+ * the cell whose lowest corner is the edge's lower end; mu_r = 1.  A
+ * material with sigma = +infinity is a perfect electric conductor: its
+ * coefficients are Ca = Cb = 0 (G = 0 on graded grids), so the edges its
+ * cells own are zero after every update (the limit of the loss term, where
+ * E is driven to zero, taken exactly).
  */
 #include <math.h>
 #include <stddef.h>
@@ -112,6 +116,10 @@ void orc_coefficients(int n_mat, const double *eps_r, const double *sigma,
                       double *ch /* {chx, chy, chz} */)
 {
     for (int m = 0; m < n_mat; m++) {
+        if (isinf(sigma[m])) {              /* perfect conductor */
+            for (int v = 0; v < 4; v++) coef[4 * m + v] = 0.0;
+            continue;
+        }
         double a = (sigma[m] * dt) / (2.0 * EPS0 * eps_r[m]);
         double cb = ((C0 * dt) / eps_r[m]) / (1.0 + a);
         coef[4 * m + 0] = (1.0 - a) / (1.0 + a);
@@ -626,6 +634,10 @@ void orc_graded_coefficients(int n_mat, const double *eps_r, const double *sigma
                              double *cag /* n_mat x {Ca, G} */, double *hc, double *ec)
 {
     for (int m = 0; m < n_mat; m++) {
+        if (isinf(sigma[m])) {              /* perfect conductor */
+            cag[2 * m + 0] = cag[2 * m + 1] = 0.0;
+            continue;
+        }
         double a = (sigma[m] * dt) / (2.0 * EPS0 * eps_r[m]);
         cag[2 * m + 0] = (1.0 - a) / (1.0 + a);
         cag[2 * m + 1] = (1.0 / eps_r[m]) / (1.0 + a);
