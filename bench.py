@@ -128,7 +128,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--T", type=int, default=4, help="steps per HBM pass of the fused kernel (1..4)")
     ap.add_argument("--workload", default="spheres256",
-                    choices=["spheres256", "spheres512", "cavity402", "graded256", "open256"])
+                    choices=["spheres256", "spheres512", "cavity402", "sphere402", "graded256", "open256"])
     ap.add_argument("--kernel", default="fused", choices=["fused", "plain"],
                     help="kernel family of the timed run (open256's CPML layers need plain)")
     ap.add_argument("--tiling", type=int, default=0, help="fused-kernel tile variant (0 = auto, 1..3)")
@@ -168,7 +168,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     wl = {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402,
-          "graded256": W.graded256, "open256": W.open256}[args.workload]()
+          "sphere402": W.sphere402, "graded256": W.graded256, "open256": W.open256}[args.workload]()
     cells = wl.cells
     T = args.T
     plain = args.kernel == "plain"

@@ -79,10 +79,20 @@ enum fdtd_component { FDTD_EX = 0, FDTD_EY = 1, FDTD_EZ = 2, FDTD_HX = 3, FDTD_H
  * storage only -- fdtd_create rejects 16-bit storage for such grids). */
 enum fdtd_kernel { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_PLAIN = 1, FDTD_KERNEL_FUSED = 2 };
 
+/* A material.  sigma = +INFINITY makes a perfect electric conductor: the
+ * coefficients of the three E edges each of its cells owns are Ca = Cb = 0,
+ * so those edges are zero after every update (the loss term's limit taken
+ * exactly), and fdtd_set_fields zeroes them.  Since a cell owns the edges at
+ * its lowest corner, a conductor region's high-side faces are exact
+ * staircase PEC walls: PEC cells filling i >= m (or j, k) leave exactly the
+ * cavity of the cells below live.  On its low side the wall lies on the
+ * region's lowest nodes, and the edges leaving those nodes towards the
+ * region are held at zero too.  A source on a PEC-owned edge is added after
+ * that edge's update and cleared by the next one. */
 typedef struct {
-    double eps_r;   /* relative permittivity, > 0 */
+    double eps_r;   /* relative permittivity, > 0, finite */
     double mu_r;    /* relative permeability; must be 1 */
-    double sigma;   /* conductivity in S/m, >= 0 */
+    double sigma;   /* conductivity in S/m, >= 0; +INFINITY = perfect conductor */
 } fdtd_material;
 
 /* Diagnostics of the current state (E^n, H^{n-1/2}), reduced in FP64 in a
@@ -189,8 +199,9 @@ int fdtd_set_tiling(fdtd_solver *s, int variant, int z_chunk);
 
 /* Replace the whole state.  host: 6*(nx+1)*(ny+1)*(nz+1) floats, components
  * Ex, Ey, Ez, Hx, Hy, Hz one after another (E^n, then H^{n-1/2}); NULL sets
- * every field to zero.  Positions outside a component's range and
- * tangential E on the walls are forced to zero.  With reduced storage the
+ * every field to zero.  Positions outside a component's range, tangential E
+ * on the walls and E on edges owned by perfect-conductor cells are forced to
+ * zero.  With reduced storage the
  * values are encoded here, with scales from their own maxima and from the
  * sources registered so far.  Synchronises the stream. */
 int fdtd_set_fields(fdtd_solver *s, const float *host);

@@ -205,6 +205,11 @@ struct fdtd_solver {
     float ch[3];
     double eps_h[256];
     double sig_h[256];
+    // perfect-conductor entries (sigma = +inf) and, when there are any, the
+    // host copy of the cell material index (fdtd_set_fields zeroes the edges
+    // those cells own)
+    bool pec[256] = {};
+    std::vector<uint8_t> mat_h;
     float4 *coef_d = nullptr;
     double *eps_d = nullptr;
     // graded spacing (fdtd_set_spacing) and CPML layers (fdtd_set_cpml):
@@ -421,8 +426,12 @@ int graded_tables(const fdtd_material *table, int n_mat, const int n[3], const d
     if (n[0] < 2 || n[1] < 2 || n[2] < 2 || !(dt > 0)) return fail(FDTD_EINVAL, "bad dimensions or dt");
     for (int m = 0; m < n_mat; ++m) {
         const double eps = table[m].eps_r, sig = table[m].sigma;
-        if (!(eps > 0) || !(sig >= 0) || table[m].mu_r != 1.0)
+        if (!(eps > 0) || !(sig >= 0) || table[m].mu_r != 1.0 || !std::isfinite(eps))
             return fail(FDTD_EINVAL, "material " + std::to_string(m) + ": need eps_r > 0, sigma >= 0, mu_r = 1");
+        if (std::isinf(sig)) {              // perfect conductor
+            cag[2 * m + 0] = cag[2 * m + 1] = 0.0f;
+            continue;
+        }
         const double a = (sig * dt) / (2.0 * EPS0 * eps);
         cag[2 * m + 0] = (float)((1.0 - a) / (1.0 + a));
         cag[2 * m + 1] = (float)((1.0 / eps) / (1.0 + a));
@@ -616,8 +625,12 @@ int fdtd_coefficients(const fdtd_material *table, int n_materials, double dx, do
     if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !(dt > 0)) return fail(FDTD_EINVAL, "bad spacing or dt");
     for (int m = 0; m < n_materials; ++m) {
         const double eps = table[m].eps_r, sig = table[m].sigma;
-        if (!(eps > 0) || !(sig >= 0) || table[m].mu_r != 1.0)
+        if (!(eps > 0) || !(sig >= 0) || table[m].mu_r != 1.0 || !std::isfinite(eps))
             return fail(FDTD_EINVAL, "material " + std::to_string(m) + ": need eps_r > 0, sigma >= 0, mu_r = 1");
+        if (std::isinf(sig)) {              // perfect conductor: the owned edges stay zero
+            for (int v = 0; v < 4; ++v) out[4 * m + v] = 0.0f;
+            continue;
+        }
         // semi-implicit loss: a = sigma dt / (2 eps0 eps_r)
         const double a = (sig * dt) / (2.0 * EPS0 * eps);
         const double cb = ((C0 * dt) / eps) / (1.0 + a);
@@ -683,10 +696,15 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz, double dx, double dy,
                 return fail(FDTD_EINVAL, "material index " + std::to_string(mat_index[q]) + " >= n_materials");
             }
     s->n_mat = n_materials;
+    bool any_pec = false;
     for (int m = 0; m < n_materials; ++m) {
         s->eps_h[m] = table[m].eps_r;
         s->sig_h[m] = table[m].sigma;
+        s->pec[m] = std::isinf(table[m].sigma);
+        any_pec = any_pec || s->pec[m];
     }
+    if (any_pec && mat_index) s->mat_h.assign(mat_index, mat_index + ncell);
+    else if (any_pec && s->pec[0]) s->mat_h.assign(ncell, 0);
     s->dx = dx; s->dy = dy; s->dz = dz; s->dt = dt;
     s->storage = storage;
     s->st = (hipStream_t)hip_stream;
@@ -828,9 +846,14 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
         return FDTD_OK;
     }
     // Stored values per component and row: positions outside the component's
-    // range and tangential E on the walls are zero.  Pass 1: maxima (for the
-    // reduced-storage scales); pass 2: clean, encode and upload plane by plane.
+    // range, tangential E on the walls and E on edges owned by perfect-conductor
+    // cells are zero.  Pass 1: maxima (for the reduced-storage scales); pass 2:
+    // clean, encode and upload plane by plane.
     const size_t nplane = (size_t)(nx + 1) * (ny + 1);
+    const bool has_pec = !s->mat_h.empty();
+    auto pec_owned = [&](int c, int i, int j, int k) {
+        return c < 3 && i < nx && j < ny && k < nz && s->pec[s->mat_h[((size_t)k * ny + j) * nx + i]];
+    };
     float m[6] = {0, 0, 0, 0, 0, 0};
     int sc[6] = {0, 0, 0, 0, 0, 0};
     if (s->storage != FDTD_FP32) {
@@ -840,7 +863,8 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
                     int i0, i1;
                     if (!row_span(nx, ny, nz, c, j, k, &i0, &i1)) continue;
                     const float *row = host + (size_t)c * nbox + (size_t)k * nplane + (size_t)j * (nx + 1);
-                    for (int i = i0; i < i1; ++i) m[c] = std::max(m[c], std::fabs(row[i]));
+                    for (int i = i0; i < i1; ++i)
+                        if (!(has_pec && pec_owned(c, i, j, k))) m[c] = std::max(m[c], std::fabs(row[i]));
                 }
         choose_scales(m, s->a_max, sc);
     }
@@ -872,10 +896,14 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
                 const size_t at = (size_t)c * s->L.cstride + (size_t)j * pitch;
                 if (s->storage == FDTD_FP32) {
                     std::memcpy((float *)buf + at + i0, row + i0, (size_t)(i1 - i0) * sizeof(float));
+                    if (has_pec && c < 3)
+                        for (int i = i0; i < i1; ++i)
+                            if (pec_owned(c, i, j, k)) ((float *)buf)[at + i] = 0.0f;
                 } else {
                     uint16_t *q = (uint16_t *)buf + at;
                     for (int i = i0; i < i1; ++i) {
-                        const uint16_t h = encode(s->storage, row[i] * upf[c], &sat);
+                        const float v = has_pec && pec_owned(c, i, j, k) ? 0.0f : row[i];
+                        const uint16_t h = encode(s->storage, v * upf[c], &sat);
                         q[i] = h;
                         const float d = std::fabs(decode(s->storage, h) * dnf[c]);
                         if (d > mx[c]) mx[c] = d;        // NaN never compares greater

@@ -20,6 +20,8 @@ structure of the configurations this library is benchmarked on:
   to coarse cells near the walls), otherwise as ``spheres256``.
 * ``open256``   -- ``spheres256`` in open space: 10-cell CPML layers on
   every face instead of reflecting walls.
+* ``sphere402`` -- the paper's case S: a spherical PEC cavity of 400 cells
+  diameter in a 402^3 box, a pin-point current inside.
 
 All randomness comes from splitmix64 (Steele, Lea, Flood 2014), drawn in a
 fixed order: material table, spheres (cx, cy, cz, radius, index), sources,
@@ -334,6 +336,42 @@ def graded(n: int, n_spheres: int, n_steps: int, seed: int, d_fine: float = 0.5e
 
 def graded256(n_steps: int = 1000) -> Workload:
     return graded(256, 40, n_steps, seed=1006, name="graded256")
+
+
+def sphere402(n_steps: int = 1300, seed: int = 1007, storage: int = FP32) -> Workload:
+    """The paper's production case S (Sec. 4.2): a sphere of 400 cells
+    diameter inside a 402^3 box, the field inside it, driven by a current at
+    a pin point, 1300 steps, 6 outputs.
+
+    Readings: the sphere is a perfect conductor enclosing the field (a cell is
+    conductor when its centre lies farther than 200 cells from the box centre);
+    the pin point is a seeded interior Ez edge at least 50 cells inside the
+    sphere, with the Gaussian-modulated sine of the other workloads; the 6
+    outputs are seeded probes inside the sphere, recorded at every step.
+    """
+    n, d = 402, 1e-3
+    dt = courant_dt(d, d, d)
+    rng = SplitMix64(seed)
+    c, r = n / 2.0, 200.0
+    mat = np.zeros((n, n, n), np.uint8)
+    ax = np.arange(n) + 0.5 - c
+    yx = ax[:, None] ** 2 + ax[None, :] ** 2
+    for k in range(n):
+        mat[k][yx + ax[k] ** 2 > r * r] = 1
+    def inside(lo):
+        while True:
+            p = tuple(rng.randint(lo, n - lo) for _ in range(3))
+            if sum((q + 0.5 - c) ** 2 for q in p) < (r - 50.0) ** 2:
+                return p
+    i, j, k = inside(60)
+    srcs = [(EZ, i, j, k)]
+    waves = gaussian_sine(n_steps, dt, d)[None, :]
+    probes = []
+    for q in range(6):
+        pi, pj, pk = inside(20)
+        probes.append((_PROBE_CYCLE[q % 6], pi, pj, pk))
+    return Workload("sphere402", n, n, n, d, d, d, dt, np.ones(2), np.ones(2), np.array([0.0, np.inf]), mat,
+                    srcs, waves, probes, n_steps, storage=storage)
 
 
 CPML_LAYER = dict(thickness=10, order=3, sigma_factor=1.0, kappa_max=5.0, alpha_max=0.05)

@@ -119,3 +119,17 @@ def test_cpml_coefficients_reject_bad_layers():
         with pytest.raises(fdtd.FdtdError) as e:
             fdtd.cpml_coefficients([1.0], [0.0], s, s, s, 1e-12, **bad)
         assert e.value.code == fdtd.EINVAL
+
+
+def test_perfect_conductor_entries_are_zero_and_match_oracle():
+    inf = float("inf")
+    eps, sig = np.array([1.0, 4.0, 2.0]), np.array([0.0, inf, 0.01])
+    ours, ch = fdtd.coefficients(eps, sig, 1e-3, 1.1e-3, 0.9e-3, 1.5e-12)
+    ref, _ = oracle.coefficients(eps, sig, 1.5e-12, 1e-3, 1.1e-3, 0.9e-3)
+    assert np.array_equal(ours, ref.astype(np.float32)) and np.all(ours[1] == 0.0)
+    s = np.full(6, 1e-3)
+    cag, _ = fdtd.graded_coefficients(eps, sig, s, s, s, 1.5e-12)
+    r_cag, _, _ = oracle.graded_coefficients(eps, sig, 1.5e-12, s, s, s)
+    assert np.array_equal(cag, r_cag.astype(np.float32)) and np.all(cag[1] == 0.0)
+    with pytest.raises(fdtd.FdtdError):
+        fdtd.coefficients([inf], [0.0], 1e-3, 1e-3, 1e-3, 1.5e-12)      # eps_r must be finite
