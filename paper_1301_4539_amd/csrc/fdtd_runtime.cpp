@@ -557,36 +557,43 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
         }
         psi_bytes = (size_t)at * sizeof(float);
     }
-    hipError_t e;
-    if (!s->gc_d && (e = hipMalloc(&s->gc_d, gc.size() * sizeof(float)))) {
-        s->gc_d = nullptr;
-        return hip_fail(e, "hipMalloc(graded coefficients)");
+    // Fill fresh device buffers and adopt them only once every copy has
+    // completed, so that a failure leaves the solver exactly as it was.
+    hipError_t e = hipSuccess;
+    float2 *gc_d = nullptr;
+    double2 *gsz_d = nullptr;
+    float *cp_d = nullptr, *psi_d = nullptr;
+    float4 *coef_d = nullptr;
+    auto drop = [&]() {
+        free_dev(gc_d);
+        free_dev(gsz_d);
+        free_dev(cp_d);
+        free_dev(psi_d);
+        free_dev(coef_d);
+    };
+    if ((e = hipMalloc(&gc_d, gc.size() * sizeof(float))) || (e = hipMalloc(&gsz_d, gsz.size() * sizeof(double2))) ||
+        (e = hipMalloc(&coef_d, 256 * sizeof(float4))) ||
+        (p.n > 0 && (e = hipMalloc(&cp_d, cp.size() * sizeof(float)))) ||
+        (psi_bytes && (e = hipMalloc(&psi_d, psi_bytes)))) {
+        drop();
+        return hip_fail(e, "hipMalloc(graded tables)");
     }
-    if (!s->gsz_d && (e = hipMalloc(&s->gsz_d, gsz.size() * sizeof(double2)))) {
-        s->gsz_d = nullptr;
-        return hip_fail(e, "hipMalloc(cell sizes)");
+    if ((e = hipMemcpyAsync(gc_d, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipMemcpyAsync(gsz_d, gsz.data(), gsz.size() * sizeof(double2), hipMemcpyHostToDevice, s->st)) ||
+        (e = hipMemcpyAsync(coef_d, coef, s->n_mat * sizeof(float4), hipMemcpyHostToDevice, s->st)) ||
+        (p.n > 0 && (e = hipMemcpyAsync(cp_d, cp.data(), cp.size() * sizeof(float), hipMemcpyHostToDevice, s->st))) ||
+        (psi_bytes && (e = hipMemsetAsync(psi_d, 0, psi_bytes, s->st))) ||
+        (e = hipStreamSynchronize(s->st))) {
+        drop();
+        return hip_fail(e, "upload graded tables");
     }
-    if (p.n > 0 && !s->cp_d && (e = hipMalloc(&s->cp_d, cp.size() * sizeof(float)))) {
-        s->cp_d = nullptr;
-        return hip_fail(e, "hipMalloc(CPML coefficients)");
-    }
-    if (psi_bytes != s->psi_bytes) {
-        free_dev(s->psi_d);
-        s->psi_d = nullptr;
-        s->psi_bytes = 0;
-        if (psi_bytes && (e = hipMalloc(&s->psi_d, psi_bytes))) {
-            s->psi_d = nullptr;
-            return hip_fail(e, "hipMalloc(CPML state)");
-        }
-        s->psi_bytes = psi_bytes;
-    }
-    if ((e = hipMemcpyAsync(s->gc_d, gc.data(), gc.size() * sizeof(float), hipMemcpyHostToDevice, s->st)) ||
-        (e = hipMemcpyAsync(s->gsz_d, gsz.data(), gsz.size() * sizeof(double2), hipMemcpyHostToDevice, s->st)) ||
-        (e = hipMemcpyAsync(s->coef_d, coef, s->n_mat * sizeof(float4), hipMemcpyHostToDevice, s->st)) ||
-        (p.n > 0 && (e = hipMemcpyAsync(s->cp_d, cp.data(), cp.size() * sizeof(float), hipMemcpyHostToDevice, s->st))) ||
-        (psi_bytes && (e = hipMemsetAsync(s->psi_d, 0, psi_bytes, s->st))) ||
-        (e = hipStreamSynchronize(s->st)))
-        return hip_fail(e, "upload graded coefficients");
+    std::swap(s->gc_d, gc_d);
+    std::swap(s->gsz_d, gsz_d);
+    std::swap(s->coef_d, coef_d);
+    std::swap(s->cp_d, cp_d);
+    std::swap(s->psi_d, psi_d);
+    drop();                             // the solver's previous buffers
+    s->psi_bytes = psi_bytes;
     std::memcpy(s->coef_h, coef, s->n_mat * 4 * sizeof(float));
     for (int ax = 0; ax < 3; ++ax) s->sizes[ax] = sz[ax];
     s->pml = p;
