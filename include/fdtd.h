@@ -191,6 +191,16 @@ int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor,
  * FP16/BF16 storage, T sets where values are re-quantised (every T steps). */
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
 
+/* Zero-tile skipping of the FUSED kernel (enable != 0, the default after
+ * fdtd_create).  The library tracks a node box holding every value that may
+ * differ from +0: the values fdtd_set_fields stored (or none), widened by one
+ * node per step on each axis -- the reach of the stencil -- plus the points
+ * of sources that still have samples.  A tile whose loaded region misses the
+ * box computes +0 exactly, so it is skipped (its probes record 0).  Results
+ * are bit-identical either way; this only saves time while a field is still
+ * spreading from its sources. */
+int fdtd_set_zero_skip(fdtd_solver *s, int enable);
+
 /* Tile shape of the FUSED kernel -- variant 0 = chosen per storage format and
  * T (default), 1..3 = the three rows-per-lane / waves-per-workgroup splits of
  * that T -- and planes per z chunk (0 = chosen from the grid).  Results do

@@ -192,6 +192,10 @@ struct fdtd_solver {
     int T = 1;                          // set by fdtd_create (automatic) or fdtd_set_kernel
     bool T_auto = true;                 // T chosen automatically (re-chosen by fdtd_set_spacing)
     int tiling = 0;                     // fused-kernel tile shape: 0 = auto, 1..3 = explicit
+    // Zero-tile skipping: every value that may differ from +0, in both field
+    // buffers, lies in the node box [box_lo, box_hi] (empty when lo > hi)
+    bool zero_skip = true;
+    int box_lo[3] = {1, 1, 1}, box_hi[3] = {0, 0, 0};
     int zchunk = 0;                     // planes per z chunk (0 = automatic)
     hipStream_t st = nullptr;
     Dims d{};
@@ -291,13 +295,15 @@ int ensure_probe_rows(fdtd_solver *s, long long rows)
     hipError_t e;
     const size_t np = s->probe_pos.size();
     if ((e = hipMalloc(&p, (size_t)cap * np * sizeof(double)))) return hip_fail(e, "hipMalloc(probes)");
-    if (s->probe_out_d) {
-        if ((e = hipMemcpyAsync(p, s->probe_out_d, (size_t)s->probe_cap * np * sizeof(double),
-                                hipMemcpyDeviceToDevice, s->st)))
-            return hip_fail(e, "hipMemcpy(probes)");
-        if ((e = hipStreamSynchronize(s->st))) return hip_fail(e, "hipStreamSynchronize");
-        free_dev(s->probe_out_d);
+    // rows start as 0: a tile skipped as all-zero leaves its probes' rows alone
+    const size_t keep = (size_t)s->probe_cap * np * sizeof(double);
+    if ((e = hipMemsetAsync((char *)p + keep, 0, (size_t)cap * np * sizeof(double) - keep, s->st)) ||
+        (s->probe_out_d && (e = hipMemcpyAsync(p, s->probe_out_d, keep, hipMemcpyDeviceToDevice, s->st))) ||
+        (e = hipStreamSynchronize(s->st))) {
+        free_dev(p);
+        return hip_fail(e, "initialise probe rows");
     }
+    free_dev(s->probe_out_d);
     s->probe_out_d = p;
     s->probe_cap = cap;
     return FDTD_OK;
@@ -398,6 +404,8 @@ void fill_fused(const fdtd_solver *s, yee::FusedArgs *a)
     a->fout = s->fbuf[s->cur ^ 1];
     a->step0 = s->steps;
     a->sb = storage_block(s);
+    a->box_lo = make_int4(-(1 << 28), -(1 << 28), -(1 << 28), 0);   // no tile skipped unless set
+    a->box_hi = make_int4(1 << 28, 1 << 28, 1 << 28, 0);
 }
 
 void advance(fdtd_solver *s, int len)
@@ -405,6 +413,67 @@ void advance(fdtd_solver *s, int len)
     s->cur ^= 1;
     s->steps += len;
     s->block += 1;
+}
+
+// The box after `len` more steps from step s->steps: the current box and the
+// points of the sources that still have samples, widened by len nodes on
+// every axis (the stencil reaches one node per step), clipped to the grid.
+void box_add_point(fdtd_solver *s, const int p[3])
+{
+    const bool empty = s->box_lo[0] > s->box_hi[0];
+    for (int ax = 0; ax < 3; ++ax) {
+        s->box_lo[ax] = empty ? p[ax] : std::min(s->box_lo[ax], p[ax]);
+        s->box_hi[ax] = empty ? p[ax] : std::max(s->box_hi[ax], p[ax]);
+    }
+}
+
+// Take in the stored values q[i0..i1) of row (j, k) that are not +0 (any bit set).
+template <class Q>
+void box_add_row(fdtd_solver *s, const Q *q, int i0, int i1, int j, int k)
+{
+    int first = i0;
+    while (first < i1 && q[first] == 0 && !std::signbit((double)q[first])) ++first;
+    if (first == i1) return;
+    int last = i1 - 1;
+    while (q[last] == 0 && !std::signbit((double)q[last])) --last;
+    const int a[3] = {first, j, k}, b[3] = {last, j, k};
+    box_add_point(s, a);
+    box_add_point(s, b);
+}
+
+void box_take_sources(fdtd_solver *s)
+{
+    for (size_t q = 0; q < s->src_pos.size(); ++q) {
+        if (s->src_wave[q].y <= s->steps) continue;     // no samples left
+        const int p[3] = {s->src_pos[q].y, s->src_pos[q].z, s->src_pos[q].w};
+        box_add_point(s, p);
+    }
+}
+
+void box_grow(fdtd_solver *s, int len)
+{
+    if (s->box_lo[0] > s->box_hi[0]) return;
+    const int n[3] = {s->L.nx, s->L.ny, s->L.nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        s->box_lo[ax] = std::max(0, s->box_lo[ax] - len);
+        s->box_hi[ax] = std::min(n[ax], s->box_hi[ax] + len);
+    }
+}
+
+// Kernel form of the box: outside the grid when empty, covering everything
+// when skipping is off.
+void box_args(const fdtd_solver *s, yee::FusedArgs *a)
+{
+    constexpr int FAR = 1 << 28;
+    if (!s->zero_skip) {
+        a->box_lo = make_int4(-FAR, -FAR, -FAR, 0);
+        a->box_hi = make_int4(FAR, FAR, FAR, 0);
+    } else if (s->box_lo[0] > s->box_hi[0]) {
+        a->box_lo = a->box_hi = make_int4(-FAR, -FAR, -FAR, 0);
+    } else {
+        a->box_lo = make_int4(s->box_lo[0], s->box_lo[1], s->box_lo[2], 0);
+        a->box_hi = make_int4(s->box_hi[0], s->box_hi[1], s->box_hi[2], 0);
+    }
 }
 
 // Per-index tables of graded spacing (sizes d[axis][q], q < n[axis]) with
@@ -821,6 +890,13 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
     return FDTD_OK;
 }
 
+int fdtd_set_zero_skip(fdtd_solver *s, int enable)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    s->zero_skip = enable != 0;
+    return FDTD_OK;
+}
+
 int fdtd_set_tiling(fdtd_solver *s, int variant, int z_chunk)
 {
     if (!s) return fail(FDTD_EINVAL, "solver is NULL");
@@ -843,6 +919,11 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
     std::memset(&ctrl, 0, sizeof(ctrl));
     s->cur = 0;
     s->block = 0;
+    s->box_lo[0] = 1;                   // empty box: filled below from the uploaded values
+    s->box_hi[0] = 0;
+    // both buffers start as +0 outside the uploaded values (the zero-tile skip
+    // relies on the older buffer too)
+    if ((e = hipMemsetAsync(s->fbuf[1], 0, s->d.fbytes, s->st))) return hip_fail(e, "hipMemset");
     if (s->psi_d && (e = hipMemsetAsync(s->psi_d, 0, s->psi_bytes, s->st)))
         return hip_fail(e, "clear CPML state");
     if (!host) {
@@ -902,10 +983,12 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
                 const float *row = src + (size_t)j * (nx + 1);
                 const size_t at = (size_t)c * s->L.cstride + (size_t)j * pitch;
                 if (s->storage == FDTD_FP32) {
-                    std::memcpy((float *)buf + at + i0, row + i0, (size_t)(i1 - i0) * sizeof(float));
+                    float *q = (float *)buf + at;
+                    std::memcpy(q + i0, row + i0, (size_t)(i1 - i0) * sizeof(float));
                     if (has_pec && c < 3)
                         for (int i = i0; i < i1; ++i)
-                            if (pec_owned(c, i, j, k)) ((float *)buf)[at + i] = 0.0f;
+                            if (pec_owned(c, i, j, k)) q[i] = 0.0f;
+                    box_add_row(s, q, i0, i1, j, k);
                 } else {
                     uint16_t *q = (uint16_t *)buf + at;
                     for (int i = i0; i < i1; ++i) {
@@ -915,6 +998,7 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
                         const float d = std::fabs(decode(s->storage, h) * dnf[c]);
                         if (d > mx[c]) mx[c] = d;        // NaN never compares greater
                     }
+                    box_add_row(s, q, i0, i1, j, k);
                 }
             }
         }
@@ -1009,9 +1093,11 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         a.chx = s->ch[0]; a.chy = s->ch[1]; a.chz = s->ch[2];
         a.gc = s->gc_d;
         a.pml = cpml_args(s);
+        box_take_sources(s);
         for (int q = 0; q < n_steps; ++q) {
             if ((e = yee::launch_plain_step(a, src, probe, s->steps + q, s->st))) return hip_fail(e, "plain step");
         }
+        box_grow(s, n_steps);
         s->steps += n_steps;
         return FDTD_OK;
     }
@@ -1023,7 +1109,10 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         const int shape = s->tiling > 0 ? s->tiling - 1 : yee::auto_shape(s->storage, len, s->gc_d != nullptr);
         if (!yee::fused_fits(s->L, s->storage, len))      // never launch a chunk beyond its addressing
             return fail(FDTD_EINVAL, "grid planes too large for the fused kernel at this T");
+        box_take_sources(s);
+        box_args(s, &a);
         if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
+        box_grow(s, len);
         advance(s, len);
         left -= len;
     }
@@ -1076,6 +1165,7 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
             for (int j = i; j < count && n < yee::MAX_BATCH; ++j)
                 if (!done[j] && key[j] == key[i]) {
                     fill_fused(solvers[j], &group[n]);
+                    box_take_sources(solvers[j]);
                     members[n++] = j;
                     done[j] = 1;
                 }
@@ -1084,6 +1174,7 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
             hipError_t e = yee::launch_fused_batch(s0->storage, len[i], group, n, shape, s0->zchunk, st);
             if (e) return hip_fail(e, "batched step");
             for (int q = 0; q < n; ++q) {
+                box_grow(solvers[members[q]], len[i]);
                 advance(solvers[members[q]], len[i]);
                 left[members[q]] -= len[i];
             }

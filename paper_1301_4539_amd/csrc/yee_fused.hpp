@@ -28,6 +28,17 @@
 // levels like the material indices.  An E coefficient is the material's G
 // times the dual-size factor, formed in FP32 before its fma.
 //
+// Zero tiles: the host tracks a box holding every value that may differ from
+// +0 in the input state (it grows by one node per step on each axis, the
+// reach of the stencil) and every source point active in the launch.  A tile
+// whose loaded region misses that box computes +0 everywhere -- every
+// difference is +0, and fma(c, +0, +0) and Ca * (+0) round to zeros that the
+// next fma turns into +0 -- and its owned region of the output buffer already
+// holds +0 (an older state, inside a smaller box), so it exits at once; its
+// probe rows keep the 0 they were allocated with.  The host passes a box
+// outside the grid for an all-zero state, and one covering every tile to
+// turn skipping off.
+//
 // Addressing: every array is read through a buffer resource based at the
 // chunk's first plane; the per-lane x offset lives in one VGPR and the plane
 // and row offsets are scalar, so a load costs one instruction.  Halo lanes
@@ -556,6 +567,21 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     __syncthreads();   // LDS is reused by the next tile of a batched launch
 }
 
+// True (uniformly) when tile `logical` computes only +0 in this launch: its
+// loaded region misses the box (see the zero-tile note above; the box holds
+// every source point active in the launch, and probe rows start as 0).
+template <int T, int RY, int NW>
+__device__ __forceinline__ bool zero_tile(const FusedArgs &a, const int logical)
+{
+    constexpr int OX = 64 - 2 * T, NR = NW * RY, OY = NR - 2 * T;
+    const int tx = logical % a.ntx, rem = logical / a.ntx;
+    const int ty = rem % a.nty, tz = rem / a.nty;
+    const int xl = tx * OX - T, yt = ty * OY - T;
+    const int kb = tz * a.zc - T, ke = tz * a.zc + a.zc - 1 + T;   // unclamped: only compared
+    return xl + 63 < a.box_lo.x || xl > a.box_hi.x || yt + NR - 1 < a.box_lo.y || yt > a.box_hi.y ||
+           ke < a.box_lo.z || kb > a.box_hi.z;
+}
+
 template <int T, int RY, int NW, class Codec, bool GR>
 __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
 {
@@ -565,6 +591,8 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     const int nb = gridDim.x, b = blockIdx.x;
     const int logical = (b & 7) * (nb >> 3) + (b >> 3);
     if (logical >= a.nwg) return;   // uniform per workgroup
+    // (with scaled storage tile 0 always runs: it publishes the next block's scales)
+    if (!(Codec::scaled && logical == 0) && zero_tile<T, RY, NW>(a, logical)) return;
     fused_tile<T, RY, NW, Codec, GR>(a, logical, sm);
 }
 

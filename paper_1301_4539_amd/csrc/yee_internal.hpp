@@ -66,6 +66,10 @@ struct FusedArgs {
     // index, x (nx+1 entries) then y (ny+1) then z (nz+1): (c dt / primal
     // cell size, c dt / dual cell size); an E coefficient is G * the second.
     const float2 *gc;
+    // Zero-tile skipping: every value of the input state outside the box
+    // [box_lo, box_hi] (node indices x, y, z; w unused) is +0, and so is the
+    // output buffer there.  box_hi.x < box_lo.x: no box, skipping off.
+    int4 box_lo, box_hi;
     int ntx, nty, ntz, nwg;
     int zc;               // planes per z chunk
     long long step0;      // absolute step index advanced by time level 1
