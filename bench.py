@@ -204,6 +204,14 @@ def main():
             lat.append(time_steps(s, wl.n_steps, torch, stream) * 1e3)
         extras["latency_ms"] = {"solve": f"{wl.n_steps} steps", "p50": float(np.percentile(lat, 50)),
                                 "p99": float(np.percentile(lat, 99)), "n": len(lat)}
+        # the same solves with zero-tile skipping off (bit-identical results)
+        s.set_zero_skip(False)
+        lat0 = []
+        for _ in range(max(1, args.solves // 2)):
+            s.set_fields(None)
+            lat0.append(time_steps(s, wl.n_steps, torch, stream) * 1e3)
+        s.set_zero_skip(True)
+        extras["latency_ms"]["p50_without_zero_skip"] = float(np.percentile(lat0, 50))
         s.close()
 
         def rate(st, tb):

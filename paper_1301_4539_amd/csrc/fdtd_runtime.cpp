@@ -1166,6 +1166,7 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
                 if (!done[j] && key[j] == key[i]) {
                     fill_fused(solvers[j], &group[n]);
                     box_take_sources(solvers[j]);
+                    box_args(solvers[j], &group[n]);
                     members[n++] = j;
                     done[j] = 1;
                 }

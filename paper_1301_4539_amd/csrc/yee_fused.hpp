@@ -607,7 +607,9 @@ __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         int i = 0;
         while (i + 1 < a.n && item >= a.start[i + 1]) ++i;
-        fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], sm);
+        const int logical = item - a.start[i];
+        if (!(Codec::scaled && logical == 0) && zero_tile<T, RY, NW>(a.s[i], logical)) continue;   // uniform
+        fused_tile<T, RY, NW, Codec>(a.s[i], logical, sm);
     }
 }
 
