@@ -5,6 +5,9 @@ Flags that the bit-exactness contract depends on:
                                      fused multiply-add is written explicitly)
   -fno-gpu-flush-denormals-to-zero   keep FP32 subnormals
   -target-feature -packed-fp32-ops   no packed FP32 instructions
+and one for speed:
+  -falign-loops=64                   loop heads on 64-byte boundaries (the fused
+                                     kernel's z-march loops run ~1% faster)
 """
 import os
 import subprocess
@@ -22,7 +25,7 @@ def hipcc_flags():
     return ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-result", "-Wno-unknown-pragmas",
+            "-falign-loops=64", "-Wall", "-Wno-unused-result", "-Wno-unknown-pragmas",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

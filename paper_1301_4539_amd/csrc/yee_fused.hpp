@@ -31,13 +31,13 @@
 // Zero tiles: the host tracks a box holding every value that may differ from
 // +0 in the input state (it grows by one node per step on each axis, the
 // reach of the stencil) and every source point active in the launch.  A tile
-// whose loaded region misses that box computes +0 everywhere -- every
+// whose loaded region misses that box would compute +0 everywhere -- every
 // difference is +0, and fma(c, +0, +0) and Ca * (+0) round to zeros that the
 // next fma turns into +0 -- and its owned region of the output buffer already
-// holds +0 (an older state, inside a smaller box), so it exits at once; its
-// probe rows keep the 0 they were allocated with.  The host passes a box
-// outside the grid for an all-zero state, and one covering every tile to
-// turn skipping off.
+// holds +0 (an older state, inside a smaller box).  Such tiles are not
+// launched: the grid covers only the box of tiles meeting the value box
+// (offsets tx0, ty0, tz0), and the probe rows of the others keep the 0 they
+// were allocated with.
 //
 // Addressing: every array is read through a buffer resource based at the
 // chunk's first plane; the per-lane x offset lives in one VGPR and the plane
@@ -174,9 +174,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
 
     const Layout L = a.L;
     const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const int tx = logical % a.ntx;
+    const int tx = a.tx0 + logical % a.ntx;   // within the launched range of tiles
     const int rem = logical / a.ntx;
-    const int ty = rem % a.nty, tz = rem / a.nty;
+    const int ty = a.ty0 + rem % a.nty, tz = a.tz0 + rem / a.nty;
     const int x0 = tx * OX, y0 = ty * OY, z0 = tz * a.zc;
     const int z1 = min(z0 + a.zc, nz + 1);
     const int xl = x0 - T;              // x of lane 0
@@ -567,21 +567,6 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     __syncthreads();   // LDS is reused by the next tile of a batched launch
 }
 
-// True (uniformly) when tile `logical` computes only +0 in this launch: its
-// loaded region misses the box (see the zero-tile note above; the box holds
-// every source point active in the launch, and probe rows start as 0).
-template <int T, int RY, int NW>
-__device__ __forceinline__ bool zero_tile(const FusedArgs &a, const int logical)
-{
-    constexpr int OX = 64 - 2 * T, NR = NW * RY, OY = NR - 2 * T;
-    const int tx = logical % a.ntx, rem = logical / a.ntx;
-    const int ty = rem % a.nty, tz = rem / a.nty;
-    const int xl = tx * OX - T, yt = ty * OY - T;
-    const int kb = tz * a.zc - T, ke = tz * a.zc + a.zc - 1 + T;   // unclamped: only compared
-    return xl + 63 < a.box_lo.x || xl > a.box_hi.x || yt + NR - 1 < a.box_lo.y || yt > a.box_hi.y ||
-           ke < a.box_lo.z || kb > a.box_hi.z;
-}
-
 template <int T, int RY, int NW, class Codec, bool GR>
 __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
 {
@@ -591,8 +576,6 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     const int nb = gridDim.x, b = blockIdx.x;
     const int logical = (b & 7) * (nb >> 3) + (b >> 3);
     if (logical >= a.nwg) return;   // uniform per workgroup
-    // (with scaled storage tile 0 always runs: it publishes the next block's scales)
-    if (!(Codec::scaled && logical == 0) && zero_tile<T, RY, NW>(a, logical)) return;
     fused_tile<T, RY, NW, Codec, GR>(a, logical, sm);
 }
 
@@ -607,9 +590,7 @@ __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         int i = 0;
         while (i + 1 < a.n && item >= a.start[i + 1]) ++i;
-        const int logical = item - a.start[i];
-        if (!(Codec::scaled && logical == 0) && zero_tile<T, RY, NW>(a.s[i], logical)) continue;   // uniform
-        fused_tile<T, RY, NW, Codec>(a.s[i], logical, sm);
+        fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], sm);
     }
 }
 
@@ -680,6 +661,35 @@ int resident_slots(K kernel, int threads)
     return cus * per_cu;
 }
 
+// Restrict a's tiling (ntx x nty x ntz tiles of OX x OY points and zc planes)
+// to the tiles whose loaded region meets the value box; false when none does.
+template <int T, int NR>
+bool restrict_to_box(FusedArgs &a)
+{
+    constexpr int OX = 64 - 2 * T, OY = NR - 2 * T;
+    auto range = [](int lo, int hi, int own, int load_lo, int load_len, int n, int *t0, int *t1) {
+        // tile t loads [t own + load_lo, t own + load_lo + load_len - 1]
+        const long long a0 = (long long)lo - load_lo - load_len + 1, b0 = (long long)hi - load_lo;
+        long long first = a0 <= 0 ? 0 : (a0 + own - 1) / own;
+        long long last = b0 < 0 ? -1 : b0 / own;
+        *t0 = (int)std::max(0LL, first);
+        *t1 = (int)std::min((long long)n - 1, last);
+        return *t0 <= *t1;
+    };
+    int x0, x1, y0, y1, z0, z1;
+    const bool any = range(a.box_lo.x, a.box_hi.x, OX, -T, 64, a.ntx, &x0, &x1) &&
+                     range(a.box_lo.y, a.box_hi.y, OY, -T, NR, a.nty, &y0, &y1) &&
+                     range(a.box_lo.z, a.box_hi.z, a.zc, -T, a.zc + 2 * T, a.ntz, &z0, &z1);
+    if (!any) return false;
+    a.tx0 = x0;
+    a.ty0 = y0;
+    a.tz0 = z0;
+    a.ntx = x1 - x0 + 1;
+    a.nty = y1 - y0 + 1;
+    a.ntz = z1 - z0 + 1;
+    return true;
+}
+
 template <int T, int V, class Codec, bool GR>
 hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
 {
@@ -688,6 +698,11 @@ hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
     FusedArgs a = a0;
     int threads;
     geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+    if (!restrict_to_box<T, tl.ry * tl.nw>(a)) {
+        if (!Codec::scaled) return hipSuccess;      // all +0 and stays so
+        a.ntx = a.nty = a.ntz = 1;                  // one tile publishes the next block's scales
+        a.tx0 = a.ty0 = a.tz0 = 0;
+    }
     a.nwg = a.ntx * a.nty * a.ntz;
     const int grid = (a.nwg + 7) / 8 * 8;
     hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR>), dim3(grid), dim3(threads), 0, st, a);
@@ -707,10 +722,15 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
         FusedArgs &a = b.s[i];
         a = args[i];
         geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, 0, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+        if (!restrict_to_box<T, tl.ry * tl.nw>(a)) {
+            a.ntx = a.nty = a.ntz = Codec::scaled ? 1 : 0;
+            a.tx0 = a.ty0 = a.tz0 = 0;
+        }
         a.nwg = a.ntx * a.nty * a.ntz;
         b.start[i + 1] = b.start[i] + a.nwg;
     }
     // persistent: at most ~4 resident workgroups per CU, each striding over the work list
+    if (b.start[n] == 0) return hipSuccess;        // every solve all +0 (unscaled storage)
     const int grid = std::min(b.start[n], 1024);
     hipLaunchKernelGGL((yee_fused_batch<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, b);
     return hipGetLastError();

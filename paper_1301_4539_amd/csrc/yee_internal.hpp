@@ -68,9 +68,10 @@ struct FusedArgs {
     const float2 *gc;
     // Zero-tile skipping: every value of the input state outside the box
     // [box_lo, box_hi] (node indices x, y, z; w unused) is +0, and so is the
-    // output buffer there.  box_hi.x < box_lo.x: no box, skipping off.
+    // output buffer there; the launcher runs only the tiles meeting it.
     int4 box_lo, box_hi;
-    int ntx, nty, ntz, nwg;
+    int ntx, nty, ntz, nwg;   // launched tiles per axis (filled by the launcher)
+    int tx0, ty0, tz0;        // index of the first launched tile per axis
     int zc;               // planes per z chunk
     long long step0;      // absolute step index advanced by time level 1
     SourceTable src;
