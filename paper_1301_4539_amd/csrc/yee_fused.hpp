@@ -28,7 +28,8 @@
 // levels like the material indices.  An E coefficient is the material's G
 // times the dual-size factor, formed in FP32 before its fma.
 //
-// Zero tiles: the host tracks a box holding every value that may differ from
+// Zero tiles (Sec. 4.2 leaves out sub-domains whose fields are all zero):
+// the host tracks a box holding every value that may differ from
 // +0 in the input state (it grows by one node per step on each axis, the
 // reach of the stencil) and every source point active in the launch.  A tile
 // whose loaded region misses that box would compute +0 everywhere -- every
