@@ -118,3 +118,22 @@ def test_skip_after_batched_and_plain_steps():
     f0, p0 = _run(wl, 48, False, 4)
     _assert_same(f1, f0, "fields")
     _assert_same(p1, p0, "probes")
+
+
+def test_skip_with_conductor_from_zero():
+    """Perfect-conductor cells (a slab and a sphere) with the field spreading
+    from zero: skipping on equals off equals the oracle."""
+    wl = spreading(n_steps=48, seed=4275)
+    wl.eps_r = np.append(wl.eps_r, 1.0)
+    wl.mu_r = np.append(wl.mu_r, 1.0)
+    wl.sigma = np.append(wl.sigma, np.inf)
+    k, j, i = np.meshgrid(*(np.arange(v) for v in (wl.nz, wl.ny, wl.nx)), indexing="ij")
+    wl.mat[(i >= 150) | ((i + 0.5 - 60) ** 2 + (j + 0.5 - 40) ** 2 + (k + 0.5 - 50) ** 2 <= 100)] = 16
+    print("zero skip with conductor cells, 48 steps", flush=True)
+    f1, p1 = _run(wl, 48, True, 4)
+    f0, p0 = _run(wl, 48, False, 4)
+    _assert_same(f1, f0, "fields skip on/off")
+    _assert_same(p1, p0, "probes skip on/off")
+    fo, po = G.oracle_f32(wl, 48)
+    _assert_same(f1, fo, "fields vs oracle")
+    _assert_same(p1, po, "probes vs oracle")
