@@ -261,6 +261,20 @@ int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out);
 /* Number of steps enqueued so far. */
 int fdtd_steps_done(const fdtd_solver *s, long long *n);
 
+/* Checkpoint and resume.  fdtd_save_state copies the whole evolving state
+ * to host memory: the fields exactly as stored (reduced storage included),
+ * the storage scales and saturation flag, the CPML psi state, the step count
+ * and the zero-tile box.  fdtd_load_state restores it into a solver created
+ * with the same grid, storage, CPML layers, spacing, materials, sources and
+ * probes (grid, storage and layers are checked; FDTD_EINVAL otherwise), which
+ * then continues bit-identically to the saved solver.  Probe records before
+ * the restored step are not part of the state (a fresh restoring solver
+ * reads them as 0).  host_dst / host_src hold at least fdtd_state_bytes(s)
+ * bytes (0 for a NULL solver); both calls synchronise the stream. */
+size_t fdtd_state_bytes(const fdtd_solver *s);
+int fdtd_save_state(fdtd_solver *s, void *host_dst, size_t bytes);
+int fdtd_load_state(fdtd_solver *s, const void *host_src, size_t bytes);
+
 /* Current per-component storage scales (2^scale multiplies a value before
  * encoding; all 0 for FP32 storage) and the saturation flag.  Synchronises. */
 int fdtd_storage_state(fdtd_solver *s, int scales[6], int *saturated);

@@ -1281,6 +1281,80 @@ int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
     return FDTD_OK;
 }
 
+// Saved state: a header, the current field buffer as stored on the device,
+// the reduced-storage control block and the CPML psi arrays.
+namespace {
+struct StateHeader {
+    char magic[8];                      // "FDTDSTA1"
+    int32_t nx, ny, nz, storage;
+    int32_t pml_n, pad;
+    int64_t steps, block;
+    int32_t box_lo[3], box_hi[3];
+    uint64_t field_bytes, ctrl_bytes, psi_bytes;
+};
+constexpr char STATE_MAGIC[8] = {'F', 'D', 'T', 'D', 'S', 'T', 'A', '1'};
+}  // namespace
+
+size_t fdtd_state_bytes(const fdtd_solver *s)
+{
+    if (!s) return 0;
+    return sizeof(StateHeader) + s->d.fbytes + sizeof(yee::Ctrl) + s->psi_bytes;
+}
+
+int fdtd_save_state(fdtd_solver *s, void *host_dst, size_t bytes)
+{
+    if (!s || !host_dst) return fail(FDTD_EINVAL, "NULL argument");
+    if (bytes < fdtd_state_bytes(s)) return fail(FDTD_EINVAL, "buffer smaller than fdtd_state_bytes");
+    StateHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, STATE_MAGIC, 8);
+    h.nx = s->L.nx; h.ny = s->L.ny; h.nz = s->L.nz; h.storage = s->storage;
+    h.pml_n = s->pml.n;
+    h.steps = s->steps; h.block = s->block;
+    for (int a = 0; a < 3; ++a) { h.box_lo[a] = s->box_lo[a]; h.box_hi[a] = s->box_hi[a]; }
+    h.field_bytes = s->d.fbytes; h.ctrl_bytes = sizeof(yee::Ctrl); h.psi_bytes = s->psi_bytes;
+    char *dst = (char *)host_dst;
+    std::memcpy(dst, &h, sizeof(h));
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dst + sizeof(h), s->fbuf[s->cur], s->d.fbytes, hipMemcpyDeviceToHost, s->st)) ||
+        (e = hipMemcpyAsync(dst + sizeof(h) + s->d.fbytes, s->ctrl, sizeof(yee::Ctrl), hipMemcpyDeviceToHost, s->st)) ||
+        (s->psi_bytes && (e = hipMemcpyAsync(dst + sizeof(h) + s->d.fbytes + sizeof(yee::Ctrl), s->psi_d, s->psi_bytes,
+                                             hipMemcpyDeviceToHost, s->st))) ||
+        (e = hipStreamSynchronize(s->st)))
+        return hip_fail(e, "save state");
+    return FDTD_OK;
+}
+
+int fdtd_load_state(fdtd_solver *s, const void *host_src, size_t bytes)
+{
+    if (!s || !host_src) return fail(FDTD_EINVAL, "NULL argument");
+    StateHeader h;
+    if (bytes < sizeof(h)) return fail(FDTD_EINVAL, "state too short");
+    std::memcpy(&h, host_src, sizeof(h));
+    if (std::memcmp(h.magic, STATE_MAGIC, 8) != 0) return fail(FDTD_EINVAL, "not a saved solver state");
+    if (h.nx != s->L.nx || h.ny != s->L.ny || h.nz != s->L.nz || h.storage != s->storage || h.pml_n != s->pml.n ||
+        h.field_bytes != s->d.fbytes || h.ctrl_bytes != sizeof(yee::Ctrl) || h.psi_bytes != s->psi_bytes)
+        return fail(FDTD_EINVAL, "saved state does not match this solver (grid, storage or CPML layers)");
+    if (bytes < fdtd_state_bytes(s)) return fail(FDTD_EINVAL, "state truncated");
+    if (h.steps < 0 || h.block < 0) return fail(FDTD_EINVAL, "corrupt state");
+    if (int rc = ensure_probe_rows(s, h.steps)) return rc;
+    const char *src = (const char *)host_src;
+    hipError_t e;
+    if ((e = hipStreamSynchronize(s->st)) ||
+        (e = hipMemcpyAsync(s->fbuf[0], src + sizeof(h), s->d.fbytes, hipMemcpyHostToDevice, s->st)) ||
+        (e = hipMemsetAsync(s->fbuf[1], 0, s->d.fbytes, s->st)) ||
+        (e = hipMemcpyAsync(s->ctrl, src + sizeof(h) + s->d.fbytes, sizeof(yee::Ctrl), hipMemcpyHostToDevice, s->st)) ||
+        (s->psi_bytes && (e = hipMemcpyAsync(s->psi_d, src + sizeof(h) + s->d.fbytes + sizeof(yee::Ctrl), s->psi_bytes,
+                                             hipMemcpyHostToDevice, s->st))) ||
+        (e = hipStreamSynchronize(s->st)))
+        return hip_fail(e, "load state");
+    s->cur = 0;
+    s->steps = h.steps;
+    s->block = h.block;
+    for (int a = 0; a < 3; ++a) { s->box_lo[a] = h.box_lo[a]; s->box_hi[a] = h.box_hi[a]; }
+    return FDTD_OK;
+}
+
 int fdtd_steps_done(const fdtd_solver *s, long long *n)
 {
     if (!s || !n) return fail(FDTD_EINVAL, "NULL argument");

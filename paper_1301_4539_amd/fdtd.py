@@ -63,6 +63,10 @@ def lib():
         L.fdtd_read_probes.argtypes = [vp, vp, ll, i]
         L.fdtd_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
         L.fdtd_steps_done.argtypes = [vp, C.POINTER(ll)]
+        L.fdtd_state_bytes.argtypes = [vp]
+        L.fdtd_state_bytes.restype = sz
+        L.fdtd_save_state.argtypes = [vp, vp, sz]
+        L.fdtd_load_state.argtypes = [vp, vp, sz]
         L.fdtd_storage_state.argtypes = [vp, C.POINTER(i), C.POINTER(i)]
         L.fdtd_synchronize.argtypes = [vp]
         L.fdtd_destroy.argtypes = [vp]
@@ -77,7 +81,8 @@ def lib():
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_zero_skip", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
-                     "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients"):
+                     "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
+                     "fdtd_load_state"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -260,6 +265,17 @@ class Solver:
         _check(lib().fdtd_diagnostics(self._h, C.byref(d)))
         return {"energy": d.energy, "div_e_max": d.div_e_max, "div_e_sumsq": d.div_e_sumsq,
                 "div_h_max": d.div_h_max, "div_h_sumsq": d.div_h_sumsq, "max_abs": list(d.max_abs)}
+
+    def save_state(self) -> np.ndarray:
+        """The whole evolving state as an opaque byte array (checkpoint)."""
+        buf = np.empty(int(lib().fdtd_state_bytes(self._h)), np.uint8)
+        _check(lib().fdtd_save_state(self._h, buf.ctypes.data, buf.size))
+        return buf
+
+    def load_state(self, buf: np.ndarray):
+        """Restore a state saved from a solver of the same configuration."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().fdtd_load_state(self._h, buf.ctypes.data, buf.size))
 
     def steps_done(self) -> int:
         n = C.c_longlong()
