@@ -201,6 +201,13 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
  * spreading from its sources. */
 int fdtd_set_zero_skip(fdtd_solver *s, int enable);
 
+/* Debugging aid (enable != 0): before every FUSED launch, fill its output
+ * buffer with NaN bit patterns, and launch every tile.  A launch that leaves
+ * an owned value unwritten, or reads a neighbour from the buffer it writes,
+ * then shows NaN in the results; correct code gives bit-identical results
+ * either way.  Costs one buffer fill per launch.  Off by default. */
+int fdtd_set_poison(fdtd_solver *s, int enable);
+
 /* Tile shape of the FUSED kernel -- variant 0 = chosen per storage format and
  * T (default), 1..3 = the three rows-per-lane / waves-per-workgroup splits of
  * that T -- and planes per z chunk (0 = chosen from the grid).  Results do

@@ -195,6 +195,7 @@ struct fdtd_solver {
     // Zero-tile skipping: every value that may differ from +0, in both field
     // buffers, lies in the node box [box_lo, box_hi] (empty when lo > hi)
     bool zero_skip = true;
+    bool poison = false;                // debug: fill each fused launch's output buffer with NaN first
     int box_lo[3] = {1, 1, 1}, box_hi[3] = {0, 0, 0};
     int zchunk = 0;                     // planes per z chunk (0 = automatic)
     hipStream_t st = nullptr;
@@ -897,6 +898,19 @@ int fdtd_set_zero_skip(fdtd_solver *s, int enable)
     return FDTD_OK;
 }
 
+int fdtd_set_poison(fdtd_solver *s, int enable)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (!enable && s->poison) {
+        // the second buffer now holds NaN outside what the last launch wrote
+        // (its padding): restore +0 there for the zero-tile invariant
+        hipError_t e = hipMemsetAsync(s->fbuf[s->cur ^ 1], 0, s->d.fbytes, s->st);
+        if (e) return hip_fail(e, "clear poison");
+    }
+    s->poison = enable != 0;
+    return FDTD_OK;
+}
+
 int fdtd_set_tiling(fdtd_solver *s, int variant, int z_chunk)
 {
     if (!s) return fail(FDTD_EINVAL, "solver is NULL");
@@ -1111,6 +1125,11 @@ int fdtd_step(fdtd_solver *s, int n_steps)
             return fail(FDTD_EINVAL, "grid planes too large for the fused kernel at this T");
         box_take_sources(s);
         box_args(s, &a);
+        if (s->poison) {     // every value the launch owns must be rewritten: nothing may rely on the old buffer
+            a.box_lo = make_int4(-(1 << 28), -(1 << 28), -(1 << 28), 0);
+            a.box_hi = make_int4(1 << 28, 1 << 28, 1 << 28, 0);
+            if ((e = hipMemsetAsync(s->fbuf[s->cur ^ 1], 0xff, s->d.fbytes, s->st))) return hip_fail(e, "poison");
+        }
         if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
         box_grow(s, len);
         advance(s, len);

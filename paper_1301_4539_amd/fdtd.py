@@ -54,6 +54,7 @@ def lib():
         L.fdtd_set_kernel.argtypes = [vp, i, i]
         L.fdtd_set_tiling.argtypes = [vp, i, i]
         L.fdtd_set_zero_skip.argtypes = [vp, i]
+        L.fdtd_set_poison.argtypes = [vp, i]
         L.fdtd_set_fields.argtypes = [vp, vp]
         L.fdtd_set_source.argtypes = [vp, i, i, i, i, vp, i, C.POINTER(i)]
         L.fdtd_set_probe.argtypes = [vp, i, i, i, i, C.POINTER(i)]
@@ -78,7 +79,7 @@ def lib():
         L.fdtd_set_cpml.argtypes = [vp, i, i, d, d, d]
         L.fdtd_cpml_coefficients.argtypes = [C.POINTER(_Material), i, i, i, i, vp, vp, vp, d, i, i, d, d, d,
                                              vp, vp, vp]
-        for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_zero_skip", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
+        for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_zero_skip", "fdtd_set_poison", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
                      "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
@@ -220,6 +221,10 @@ class Solver:
     def set_zero_skip(self, enable: bool):
         """Skip fused-kernel tiles that can only compute +0 (default on)."""
         _check(lib().fdtd_set_zero_skip(self._h, 1 if enable else 0))
+
+    def set_poison(self, enable: bool):
+        """Debugging aid: NaN-fill each fused launch's output buffer first."""
+        _check(lib().fdtd_set_poison(self._h, 1 if enable else 0))
 
     def set_tiling(self, variant=0, z_chunk=0):
         _check(lib().fdtd_set_tiling(self._h, variant, z_chunk))
