@@ -146,10 +146,11 @@ int fdtd_create(fdtd_solver **out, int nx, int ny, int nz,
  * coefficient is formed in FP32 as G * (c dt / dual size) with
  * G = (1/eps_r) / (1 + sigma dt / (2 eps0 eps_r)).
  *   Sizes > 0 and finite; dt must satisfy the Courant bound of the smallest
- *   size on each axis (else FDTD_ECFL; sufficient for such grids).  FP32
- *   storage only (else FDTD_EINVAL); only before the first step
- *   (FDTD_ESTATE); may be called again to replace the sizes.  Arrays are
- *   copied.  Graded solvers run with fdtd_step (PLAIN or FUSED, any T);
+ *   size on each axis (else FDTD_ECFL; sufficient for such grids).  Any
+ *   storage format (the PLAIN family needs FP32 storage as always); only
+ *   before the first step (FDTD_ESTATE); may be called again to replace the
+ *   sizes.  Arrays are copied.  Graded solvers run with fdtd_step (PLAIN or
+ *   FUSED, any T);
  *   fdtd_step_batch rejects them (FDTD_EINVAL).  fdtd_diagnostics weights
  *   each term by its volume (see fdtd_diag). */
 int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const double *dz);

@@ -79,6 +79,9 @@ def lib():
         L.orc_run_cpml_f32.argtypes = [_i, _i, _i, _i, _fp, _fp, _fp, _fp, _u8, _fp, _fp, _l, _i, _i, _ip, _fp,
                                        _i, _i, _ip, _dp]
         L.orc_run_cpml_f32.restype = _i
+        L.orc_run_q_graded.argtypes = [_i, _i, _i, _i, _i, _fp, _fp, _fp, _u8, _fp, _l, _i, _i, _ip, _fp, _i, _i,
+                                       _ip, _dp, C.c_float, _ip, _fp, _ip]
+        L.orc_run_q_graded.restype = _i
         _lib = L
     return _lib
 
@@ -247,12 +250,18 @@ class Problem:
         """Reduced-storage emulation.  state: dict with 'scales' (6 int32),
         'm_stored' (6 float32), 'flag' (1 int32), updated in place."""
         assert f.dtype == np.float32 and f.flags.c_contiguous
-        assert not self.graded, "reduced storage is emulated on uniform grids only"
+        assert not self.cpml, "reduced storage is emulated without CPML layers"
         out = np.zeros((n_steps, max(len(self.probe), 1)))
-        rc = lib().orc_run_q(self.nx, self.ny, self.nz, fmt, T, self.ch32, self.coef32, self.mat, f, step0,
-                             n_steps, len(self.src), self.src, self.wave32, self.wave32.shape[1],
-                             len(self.probe), self.probe, out, self.a_max,
-                             state["scales"], state["m_stored"], state["flag"])
+        if self.graded:
+            rc = lib().orc_run_q_graded(self.nx, self.ny, self.nz, fmt, T, self.hc32, self.cag32, self.ec32, self.mat,
+                                        f, step0, n_steps, len(self.src), self.src, self.wave32, self.wave32.shape[1],
+                                        len(self.probe), self.probe, out, self.a_max,
+                                        state["scales"], state["m_stored"], state["flag"])
+        else:
+            rc = lib().orc_run_q(self.nx, self.ny, self.nz, fmt, T, self.ch32, self.coef32, self.mat, f, step0,
+                                 n_steps, len(self.src), self.src, self.wave32, self.wave32.shape[1],
+                                 len(self.probe), self.probe, out, self.a_max,
+                                 state["scales"], state["m_stored"], state["flag"])
         if rc:
             raise ValueError("bad source or probe descriptor")
         return out[:, :len(self.probe)]

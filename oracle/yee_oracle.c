@@ -1316,6 +1316,25 @@ int orc_run_cpml_f32(int nx, int ny, int nz, int N, const float *hc, const float
     return 0;
 }
 
+/* Reduced-storage emulation on graded grids: the graded FP32 step, with the
+ * state quantised at the same block ends as orc_run_q. */
+int orc_run_q_graded(int nx, int ny, int nz, int fmt, int T, const float *hc, const float *cag, const float *ec,
+                     const uint8_t *mat, float *f, long step0, int n_steps,
+                     int n_src, const int *src, const float *wave, int n_wave,
+                     int n_probe, const int *probe, double *probe_out,
+                     float a_max, int *scales, float *m_stored, int *flag)
+{
+    for (int s = 0; s < n_steps; s++) {
+        int rc = orc_run_graded_f32(nx, ny, nz, hc, cag, ec, mat, f, step0 + s, 1, n_src, src, wave, n_wave,
+                                    n_probe, probe, probe_out + (size_t)s * n_probe);
+        if (rc) return rc;
+        long done = step0 + s + 1;
+        if (done % T == 0 || s == n_steps - 1)
+            orc_quantize_state(nx, ny, nz, fmt, 0, a_max, f, scales, m_stored, flag);
+    }
+    return 0;
+}
+
 /* Number of threads the parallel loops use (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>

@@ -846,7 +846,6 @@ int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const d
 {
     if (!s || !dx || !dy || !dz) return fail(FDTD_EINVAL, "NULL argument");
     if (s->steps > 0) return fail(FDTD_ESTATE, "spacing must be set before the first step");
-    if (s->storage != FDTD_FP32) return fail(FDTD_EINVAL, "graded spacing needs FP32 storage");
     std::vector<double> sz[3] = {std::vector<double>(dx, dx + s->L.nx), std::vector<double>(dy, dy + s->L.ny),
                                  std::vector<double>(dz, dz + s->L.nz)};
     return apply_graded(s, sz, s->pml);

@@ -159,7 +159,7 @@ hipError_t launch_diag_t(const DiagArgs &a, double *out, hipStream_t st)
     dim3 block(DBX, DBY, 1);
     dim3 grid((a.L.nx + 1 + DBX - 1) / DBX, (a.L.ny + 1 + DBY - 1) / DBY, a.L.nz + 1);
     if (a.gc) {
-        if (!a.gsz || Codec::scaled) return hipErrorInvalidValue;   // graded grids store FP32
+        if (!a.gsz) return hipErrorInvalidValue;
         hipLaunchKernelGGL((diag_points<Codec, true>), grid, block, 0, st, a);
     } else {
         hipLaunchKernelGGL((diag_points<Codec, false>), grid, block, 0, st, a);

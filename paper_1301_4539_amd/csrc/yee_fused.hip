@@ -11,15 +11,24 @@ hipError_t launch_fused_f16(int T, const FusedArgs *a, int n, bool batch, int va
 hipError_t launch_fused_bf16(int T, const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st);
 hipError_t launch_fused_f32_graded(int T, const FusedArgs *a, int n, bool batch, int variant, int zc,
                                    hipStream_t st);
+hipError_t launch_fused_f16_graded(int T, const FusedArgs *a, int n, bool batch, int variant, int zc,
+                                   hipStream_t st);
+hipError_t launch_fused_bf16_graded(int T, const FusedArgs *a, int n, bool batch, int variant, int zc,
+                                    hipStream_t st);
 
 namespace {
 
 hipError_t launch_any(int storage, int T, const FusedArgs *a, int n, bool batch, int variant, int zc,
                       hipStream_t st)
 {
-    if (a->gc) {   // graded spacing: FP32 storage, one solve per launch
-        if (storage != 0 || batch) return hipErrorInvalidValue;
-        return launch_fused_f32_graded(T, a, n, batch, variant, zc, st);
+    if (a->gc) {   // graded spacing: one solve per launch
+        if (batch) return hipErrorInvalidValue;
+        switch (storage) {
+        case 0: return launch_fused_f32_graded(T, a, n, batch, variant, zc, st);
+        case 1: return launch_fused_f16_graded(T, a, n, batch, variant, zc, st);
+        case 2: return launch_fused_bf16_graded(T, a, n, batch, variant, zc, st);
+        }
+        return hipErrorInvalidValue;
     }
     switch (storage) {
     case 0: return launch_fused_f32(T, a, n, batch, variant, zc, st);

@@ -137,10 +137,13 @@ def test_set_spacing_rules():
     finally:
         s.close()
     wl, s16 = _solver(storage=W.FP16)
-    try:
+    try:   # 16-bit storage takes graded sizes too (on the fused kernels)
+        s16.set_spacing(*[np.full(n, 1e-3) for n in (wl.nx, wl.ny, wl.nz)])
         with pytest.raises(fdtd.FdtdError) as e:
-            s16.set_spacing(*[np.full(n, 1e-3) for n in (wl.nx, wl.ny, wl.nz)])
+            s16.set_kernel(fdtd.KERNEL_PLAIN, 1)
         assert e.value.code == fdtd.EINVAL
+        s16.step(3)
+        s16.synchronize()
     finally:
         s16.close()
 
@@ -188,3 +191,38 @@ def test_graded_lossless_energy_conserved_on_gpu():
     finally:
         s.close()
     assert abs(w1 - w0) < 1e-5 * w0
+
+
+@pytest.mark.parametrize("fmt,T", [(W.FP16, 3), (W.FP16, 1), (W.BF16, 3), (W.BF16, 4)])
+def test_graded_reduced_storage_bitexact_with_emulation(fmt, T):
+    wl = graded_ragged(n_steps=30, seed=4252)
+    wl.storage = fmt
+    wl.init_fields = None
+    print(f"graded reduced storage fmt={fmt} T={T}, 30 steps in 11+19", flush=True)
+    f, p = G.gpu_run(wl, 30, kernel=fdtd.KERNEL_FUSED, T=T, storage=fmt, chunks=[11, 19])
+    prob = oracle.Problem.from_workload(wl)
+    fo = oracle.zero_fields(wl.nx, wl.ny, wl.nz, np.float32)
+    st = prob.quantize_upload(fo, fmt)
+    po = np.concatenate([prob.run_q(fo, 0, 11, fmt, T, st), prob.run_q(fo, 11, 19, fmt, T, st)])
+    _assert_same(f, fo, "fields")
+    _assert_same(p, po, "probes")
+
+
+def test_graded_fp16_diagnostics_match_oracle():
+    wl = graded_ragged(n_steps=20, seed=4253)
+    wl.storage = W.FP16
+    init = wl.init_fields.astype(np.float32)
+    wl.init_fields = None
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=3)
+    try:
+        s.set_fields(init)
+        s.step(20)
+        d = s.diagnostics()
+        f = s.read_fields()
+    finally:
+        s.close()
+    prob = oracle.Problem.from_workload(wl)
+    w = prob.energy(f)
+    assert abs(d["energy"] - w) <= 1e-12 * abs(w)
+    for c in range(6):
+        assert d["max_abs"][c] == float(np.max(np.abs(f[c])))

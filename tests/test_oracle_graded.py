@@ -228,3 +228,35 @@ def test_graded_fp32_energy_close_to_fp64_energy():
     w64 = prob.energy(f.astype(np.float64))
     w32 = prob.energy(f)
     assert abs(w32 - w64) < 1e-6 * w64
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_graded_reduced_storage_composes_step_and_quantisation(fmt):
+    """The graded emulation mode is the graded FP32 step with the state
+    re-encoded at block ends: one block of all the steps equals the FP32
+    run followed by one re-encoding, and blocks of T equal T-step FP32 runs
+    each followed by one."""
+    n = (10, 9, 11)
+    rng = np.random.default_rng(31)
+    sx, sy, sz = (_sizes(rng, m) for m in n)
+    dt = _graded_dt(sx, sy, sz)
+    eps, sig = np.array([1.0, 3.0]), np.array([0.0, 0.02])
+    mat = rng.integers(0, 2, size=n[::-1]).astype(np.uint8)
+    prob = _problem(n, (sx, sy, sz), eps, sig, mat, dt)
+    f0 = rng.standard_normal((6, n[2] + 1, n[1] + 1, n[0] + 1)).astype(np.float32)
+    f0[0:3][~W.interior_e_mask(*n)] = 0.0
+    fq = f0.copy()
+    st = prob.quantize_upload(fq, fmt)
+    for T, steps in ((12, 12), (4, 12)):
+        a = fq.copy()
+        sa = {k: v.copy() for k, v in st.items()}
+        prob.run_q(a, 0, steps, fmt, T, sa)
+        b = fq.copy()
+        sb = {k: v.copy() for k, v in st.items()}
+        for s0 in range(0, steps, T):
+            prob.run_f32(b, s0, T)
+            lib = oracle.lib()
+            lib.orc_quantize_state(prob.nx, prob.ny, prob.nz, fmt, 0, prob.a_max, b, sb["scales"], sb["m_stored"],
+                                   sb["flag"])
+        assert np.array_equal(a, b) and np.array_equal(sa["scales"], sb["scales"])
+        assert not np.array_equal(a, fq)
