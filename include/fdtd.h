@@ -83,12 +83,13 @@ enum fdtd_kernel { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_PLAIN = 1, FDTD_KERNEL_FUSE
  * coefficients of the three E edges each of its cells owns are Ca = Cb = 0,
  * so those edges are zero after every update (the loss term's limit taken
  * exactly), and fdtd_set_fields zeroes them.  Since a cell owns the edges at
- * its lowest corner, a conductor region's high-side faces are exact
- * staircase PEC walls: PEC cells filling i >= m (or j, k) leave exactly the
- * cavity of the cells below live.  On its low side the wall lies on the
- * region's lowest nodes, and the edges leaving those nodes towards the
- * region are held at zero too.  A source on a PEC-owned edge is added after
- * that edge's update and cleared by the next one. */
+ * its lowest corner, the faces of a conductor region that look towards lower
+ * indices are exact staircase PEC walls (its lowest nodes hold tangential
+ * E = 0): PEC cells filling i >= m (or j, k) leave exactly the cavity of the
+ * cells below live.  On the faces that look towards higher indices the wall
+ * lies one node inside the region, and the edges joining it to the region's
+ * outer nodes are held at zero too.  A source on a PEC-owned edge is added
+ * after that edge's update and cleared by the next one. */
 typedef struct {
     double eps_r;   /* relative permittivity, > 0, finite */
     double mu_r;    /* relative permeability; must be 1 */
