@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--T", type=int, default=4, help="steps per HBM pass of the fused kernel (1..4)")
+    ap.add_argument("--T", type=int, default=4, help="steps per HBM pass of the fused kernel (1..6)")
     ap.add_argument("--workload", default="spheres256",
                     choices=["spheres256", "spheres512", "cavity402", "sphere402", "graded256", "open256"])
     ap.add_argument("--kernel", default="fused", choices=["fused", "plain"],
@@ -246,6 +246,11 @@ def main():
         extras["bf16_store"] = {"value": vbf, "T": serve.DEFAULT_T[W.BF16], "ratio_vs_fp32": vbf / value}
         print(f"[bench] fp16 (T={t16}): {v16:.2f} G cell-updates/s, x{v16 / value:.2f}; matched T=4 "
               f"x{v16_4 / value:.2f}, T=1 x{v16_1 / v32_1:.2f}; bf16 {vbf:.2f}", file=sys.stderr, flush=True)
+        # deeper step gathering, T = 5 and 6: past the register file (slower),
+        # but 16-bit storage is re-encoded less often
+        extras["deep_blocks"] = {f: {f"T{tb}": rate(st, tb) for tb in (5, 6)}
+                                 for f, st in (("fp32", W.FP32), ("fp16", W.FP16))}
+        print(f"[bench] deep blocks: {extras['deep_blocks']}", file=sys.stderr, flush=True)
         # graded cell sizes (per-index coefficient arrays), FP32, automatic T and tile shape
         wg = W.graded256()
         sg = fdtd.Solver.from_workload(wg)

@@ -185,10 +185,14 @@ int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor,
                   double alpha_max);
 
 /* Kernel family (fdtd_kernel) and steps per HBM pass T for the FUSED family:
- * 1..4, or 0 = automatic (the default after fdtd_create): 4 for FP32
+ * 1..6, or 0 = automatic (the default after fdtd_create): 4 for FP32
  * storage, 3 for FP16/BF16 storage and for graded spacing, the fastest on
  * MI355X, lowered for grids whose planes are too large for that T (an
- * automatic T is chosen again by fdtd_set_spacing).  Allowed before the first
+ * automatic T is chosen again by fdtd_set_spacing).  T = 5 and 6 (deeper step
+ * gathering, Sec. 3.4 and the conclusion) exceed the register file and run
+ * slower, but re-quantise 16-bit storage less often; solvers with graded
+ * spacing and fdtd_step_batch take T <= 4 (FDTD_EINVAL otherwise, also from
+ * fdtd_set_spacing on a solver with a fixed T > 4).  Allowed before the first
  * step and between steps.  Results do not depend on T for FP32 storage; for
  * FP16/BF16 storage, T sets where values are re-quantised (every T steps). */
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);

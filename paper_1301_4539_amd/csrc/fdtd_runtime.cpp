@@ -607,6 +607,9 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
     const double limit = graded_courant_limit(n, d);
     if (s->dt > limit)
         return fail(FDTD_ECFL, "dt exceeds the Courant limit " + std::to_string(limit) + " of the smallest cells");
+    if (!s->T_auto && s->T > yee::MAX_T_GRADED)
+        return fail(FDTD_EINVAL, "graded spacing runs blocks of at most " + std::to_string(yee::MAX_T_GRADED) +
+                                     " steps; lower time_block first");
     float coef[256 * 4];
     for (int m = 0; m < s->n_mat; ++m) {
         coef[4 * m + 0] = cag[2 * m + 0];
@@ -873,7 +876,10 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
 {
     if (!s) return fail(FDTD_EINVAL, "solver is NULL");
     if (kernel < 0 || kernel > 2) return fail(FDTD_EINVAL, "bad kernel family");
-    if (time_block < 0 || time_block > 4) return fail(FDTD_EINVAL, "time_block must be 0 (automatic) or 1..4");
+    if (time_block < 0 || time_block > yee::MAX_T)
+        return fail(FDTD_EINVAL, "time_block must be 0 (automatic) or 1.." + std::to_string(yee::MAX_T));
+    if (s->gc_d && time_block > yee::MAX_T_GRADED)
+        return fail(FDTD_EINVAL, "graded spacing runs blocks of at most " + std::to_string(yee::MAX_T_GRADED) + " steps");
     const bool automatic = time_block == 0;
     if (automatic) time_block = auto_T(s);
     if (kernel == FDTD_KERNEL_AUTO)   // AUTO lowers T to what the grid allows (plain if nothing fits)
@@ -1150,6 +1156,8 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
         if (s->kernel == FDTD_KERNEL_PLAIN || !yee::fused_fits(s->L, s->storage, s->T))
             return fail(FDTD_EINVAL, "batched steps use the fused kernel");
         if (s->gc_d) return fail(FDTD_EINVAL, "graded-spacing solvers are stepped alone (fdtd_step)");
+        if (s->T > yee::MAX_T_BATCH)
+            return fail(FDTD_EINVAL, "batched steps run blocks of at most " + std::to_string(yee::MAX_T_BATCH) + " steps");
         if (n_steps[i] < 0) return fail(FDTD_EINVAL, "negative step count");
         for (int j = 0; j < i; ++j)
             if (solvers[j] == s) return fail(FDTD_EINVAL, "a solver appears twice in the batch");

@@ -597,13 +597,19 @@ __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
 
 // ---- tilings ---------------------------------------------------------------
 // (RY rows per lane, NW waves) per time-block length; variant 0 is the default.
+// T = 5 and 6 exceed the register file at every shape: 2 x 16 waves is capped
+// at 128 VGPRs per lane and spills a few values in the steady loop, the
+// 8-wave shapes (256 VGPRs) spill less.  They serve uniform-spacing solves
+// alone (no batches, no graded sizes).
 struct Tiling { int ry, nw; };
-constexpr Tiling kTilings[5][3] = {
+constexpr Tiling kTilings[MAX_T + 1][3] = {
     {},
     {{4, 4}, {2, 8}, {2, 16}},    // T = 1
     {{2, 16}, {4, 8}, {3, 12}},   // T = 2
     {{2, 16}, {4, 8}, {3, 12}},   // T = 3
     {{2, 16}, {4, 8}, {3, 12}},   // T = 4
+    {{2, 16}, {4, 8}, {3, 12}},   // T = 5
+    {{4, 8}, {2, 16}, {3, 12}},   // T = 6
 };
 
 int planes_fit(const Layout &L, int es)
@@ -740,8 +746,8 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
 template <int T, class Codec, bool GR>
 hipError_t launch_t(const FusedArgs *a, int n, bool batch, int variant, int zc, hipStream_t st)
 {
-    if constexpr (GR) {
-        if (batch) return hipErrorInvalidValue;   // batches are uniform-spacing solves
+    if constexpr (GR || T > MAX_T_BATCH) {
+        if (batch) return hipErrorInvalidValue;   // batches are uniform-spacing solves of short blocks
     } else if (batch) {
         switch (variant) {
         case 1: return launch_batch_tv<T, 1, Codec>(a, n, zc, st);
@@ -764,6 +770,12 @@ hipError_t launch_codec(int T, const FusedArgs *a, int n, bool batch, int varian
     case 2: return launch_t<2, Codec, GR>(a, n, batch, variant, zc, st);
     case 3: return launch_t<3, Codec, GR>(a, n, batch, variant, zc, st);
     case 4: return launch_t<4, Codec, GR>(a, n, batch, variant, zc, st);
+    }
+    if constexpr (!GR) {                          // deeper blocks: uniform spacing only
+        switch (T) {
+        case 5: return launch_t<5, Codec, false>(a, n, batch, variant, zc, st);
+        case 6: return launch_t<6, Codec, false>(a, n, batch, variant, zc, st);
+        }
     }
     return hipErrorInvalidValue;
 }

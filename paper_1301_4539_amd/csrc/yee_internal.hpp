@@ -83,6 +83,9 @@ struct FusedArgs {
 // (tile) of solve i, start[n] the total.  Passed by value as kernel
 // arguments (no device copy of the descriptors).
 constexpr int MAX_BATCH = 12;
+// Longest time block of the fused kernel, and of its batched and
+// graded-spacing forms.
+constexpr int MAX_T = 6, MAX_T_BATCH = 4, MAX_T_GRADED = 4;
 struct BatchArgs {
     int n;
     int start[MAX_BATCH + 1];
