@@ -198,13 +198,23 @@ int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor,
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
 
 /* Zero-tile skipping of the FUSED kernel (enable != 0, the default after
- * fdtd_create).  The library tracks a node box holding every value that may
- * differ from +0: the values fdtd_set_fields stored (or none), widened by one
- * node per step on each axis -- the reach of the stencil -- plus the points
- * of sources that still have samples.  A tile whose loaded region misses the
- * box computes +0 exactly, so it is skipped (its probes record 0).  Results
- * are bit-identical either way; this only saves time while a field is still
- * spreading from its sources. */
+ * fdtd_create); Sec. 4.2 leaves sub-domains whose fields are zero out of the
+ * computation.  Two kinds of tiles are skipped:
+ *  - The library tracks a node box holding every value that may differ from
+ *    +0: the values fdtd_set_fields stored (or none), widened by one node per
+ *    step on each axis -- the reach of the stencil -- plus the points of
+ *    sources that still have samples.  A tile whose loaded region misses the
+ *    box computes +0 exactly.  This saves time while a field is still
+ *    spreading from its sources.
+ *  - With perfect-conductor materials, a node is dead when its E edges are
+ *    walls or owned by conductor cells (no source on them), its H values see
+ *    only such edges, and its six stored values are +0 (as fdtd_set_fields or
+ *    fdtd_load_state found them): it then stays +0 for good.  Tiles owning
+ *    only dead nodes (conductor interiors) are not launched, for the whole
+ *    run.  The map is made by fdtd_set_fields (and fdtd_create, with zero
+ *    fields) and fdtd_load_state; fdtd_set_source wakes the nodes around its
+ *    edge.  Batched steps run every tile.
+ * Skipped tiles' probes record 0.  Results are bit-identical either way. */
 int fdtd_set_zero_skip(fdtd_solver *s, int enable);
 
 /* Debugging aid (enable != 0): before every FUSED launch, fill its output

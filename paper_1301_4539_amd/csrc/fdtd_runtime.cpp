@@ -252,13 +252,168 @@ struct fdtd_solver {
     // that host work on one plane overlaps the copy of the other
     char *stage[2] = {nullptr, nullptr};
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    // live nodes (only when a material is a perfect conductor): conductor
+    // interiors whose values are +0 for good are not launched
+    yee::LiveNodes *live = nullptr;
 };
+
+namespace yee {
+
+// One bit per node, 1 = live; row (j, k) is `words` 64-bit words from
+// ((k (ny+1) + j) words).  Tile lists are made on first use per geometry.
+struct LiveNodes {
+    int nx = 0, ny = 0, nz = 0, words = 0;
+    std::vector<uint64_t> bits;
+    struct List {
+        int ox, oy, zc, ntx, nty, ntz;
+        int count;
+        int *dev;                       // null: every tile is live
+        std::vector<int> host;          // source of the (asynchronous) upload
+    };
+    std::vector<List> lists;
+
+    void drop_lists()
+    {
+        for (List &l : lists)
+            if (l.dev) (void)hipFree(l.dev);
+        lists.clear();
+    }
+    void mark(int i, int j, int k)
+    {
+        if (i < 0 || j < 0 || k < 0 || i > nx || j > ny || k > nz) return;
+        bits[((size_t)k * (ny + 1) + j) * words + (i >> 6)] |= 1ULL << (i & 63);
+    }
+};
+
+const int *live_tile_list(LiveNodes *d, int ox, int oy, int zc, int ntx, int nty, int ntz, int *count,
+                          hipStream_t st)
+{
+    *count = 0;
+    for (const LiveNodes::List &l : d->lists)
+        if (l.ox == ox && l.oy == oy && l.zc == zc && l.ntx == ntx && l.nty == nty && l.ntz == ntz) {
+            *count = l.count;
+            return l.dev;
+        }
+    // a tile (tx, ty, tz) owns x in [tx ox, tx ox + ox), y in [ty oy, ..),
+    // z in [tz zc, ..): mark the owner of every live node, skipping the rest
+    // of a tile's bits once it is marked
+    std::vector<uint8_t> flag((size_t)ntx * nty * ntz, 0);
+    for (int k = 0; k <= d->nz; ++k)
+        for (int j = 0; j <= d->ny; ++j) {
+            const uint64_t *row = &d->bits[((size_t)k * (d->ny + 1) + j) * d->words];
+            uint8_t *f = &flag[((size_t)(k / zc) * nty + j / oy) * ntx];
+            for (int w = 0; w < d->words; ++w) {
+                uint64_t b = row[w];
+                while (b) {
+                    const int tx = (w * 64 + __builtin_ctzll(b)) / ox;
+                    f[tx] = 1;
+                    const int next = (tx + 1) * ox - w * 64;    // next tile's first bit in this word
+                    if (next >= 64) break;
+                    b &= ~0ULL << next;
+                }
+            }
+        }
+    LiveNodes::List l{ox, oy, zc, ntx, nty, ntz, 0, nullptr, {}};
+    for (size_t t = 0; t < flag.size(); ++t)
+        if (flag[t]) l.host.push_back((int)t);
+    l.count = (int)l.host.size();
+    if (l.host.size() < flag.size()) {
+        if (hipMalloc(&l.dev, std::max<size_t>(1, l.host.size()) * sizeof(int)) != hipSuccess) {
+            l.dev = nullptr;            // no list: every tile runs
+            return nullptr;
+        }
+        if (!l.host.empty() &&
+            hipMemcpyAsync(l.dev, l.host.data(), l.host.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess) {
+            (void)hipFree(l.dev);
+            return nullptr;
+        }
+    }
+    d->lists.push_back(std::move(l));
+    *count = d->lists.back().count;
+    return d->lists.back().dev;
+}
+
+}  // namespace yee
 
 namespace {
 
 void free_dev(void *p)
 {
     if (p) (void)hipFree(p);
+}
+
+void live_drop(fdtd_solver *s)
+{
+    if (!s->live) return;
+    (void)hipStreamSynchronize(s->st);  // no launch in flight still reads a list
+    s->live->drop_lists();
+    delete s->live;
+    s->live = nullptr;
+}
+
+// A source at node (i, j, k) unpins its edge: every node whose E or H
+// involves that edge, within {i-1, i} x {j-1, j} x {k-1, k}, becomes live.
+void live_source(fdtd_solver *s, int i, int j, int k)
+{
+    if (!s->live) return;
+    (void)hipStreamSynchronize(s->st);
+    s->live->drop_lists();
+    for (int dk = -1; dk <= 0; ++dk)
+        for (int dj = -1; dj <= 0; ++dj)
+            for (int di = -1; di <= 0; ++di) s->live->mark(i + di, j + dj, k + dk);
+}
+
+// A node is dead when its E edges are all pinned -- walls, or owned by a
+// perfect-conductor cell, with no source -- each of its H values sees only
+// pinned edges, and its six stored values are +0: then every update rewrites
+// +0 there (Ca = Cb = 0 for pinned E, a zero curl for H).  nonzero(c, i, j,
+// k) tells whether stored component c is not +0.  Without perfect-conductor
+// cells there is no map.
+template <class NonZero>
+void live_build(fdtd_solver *s, NonZero nonzero)
+{
+    live_drop(s);
+    if (s->mat_h.empty()) return;
+    const int nx = s->L.nx, ny = s->L.ny, nz = s->L.nz;
+    auto *d = new yee::LiveNodes;
+    d->nx = nx; d->ny = ny; d->nz = nz;
+    d->words = (nx + 1 + 63) / 64;
+    d->bits.assign((size_t)(nz + 1) * (ny + 1) * d->words, 0);
+    // bit c of P[k & 1][j (nx+1) + i]: E component c at node (i, j, k) is pinned
+    const size_t np = (size_t)(nx + 1) * (ny + 1);
+    std::vector<uint8_t> P[2] = {std::vector<uint8_t>(np), std::vector<uint8_t>(np)};
+    auto pinned_plane = [&](int k, uint8_t *p) {
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                const bool pc = i < nx && j < ny && k < nz && s->pec[s->mat_h[((size_t)k * ny + j) * nx + i]];
+                uint8_t m = 0;
+                for (int c = 0; c < 3; ++c)
+                    if (pc || !e_interior(nx, ny, nz, c, i, j, k)) m |= (uint8_t)(1 << c);
+                p[(size_t)j * (nx + 1) + i] = m;
+            }
+    };
+    pinned_plane(0, P[0].data());
+    for (int k = 0; k <= nz; ++k) {
+        const uint8_t *p0 = P[k & 1].data();
+        if (k < nz) pinned_plane(k + 1, P[(k + 1) & 1].data());
+        const uint8_t *p1 = P[(k + 1) & 1].data();     // read only when k < nz
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                const size_t q = (size_t)j * (nx + 1) + i;
+                bool dead = p0[q] == 7;
+                if (dead && j < ny && k < nz)    // Hx: Ez at j and j+1, Ey at k and k+1
+                    dead = (p0[q + nx + 1] & 4) && (p1[q] & 2);
+                if (dead && i < nx && k < nz)    // Hy: Ex at k and k+1, Ez at i and i+1
+                    dead = (p1[q] & 1) && (p0[q + 1] & 4);
+                if (dead && i < nx && j < ny)    // Hz: Ey at i and i+1, Ex at j and j+1
+                    dead = (p0[q + 1] & 2) && (p0[q + nx + 1] & 1);
+                for (int c = 0; c < 6 && dead; ++c)
+                    dead = !(in_range(nx, ny, nz, c, i, j, k) && nonzero(c, i, j, k));
+                if (!dead) d->mark(i, j, k);
+            }
+    }
+    s->live = d;
+    for (const int4 &p : s->src_pos) live_source(s, p.y, p.z, p.w);
 }
 
 int upload_sources(fdtd_solver *s)
@@ -950,6 +1105,7 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
             (e = hipMemcpyAsync(s->ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, s->st)) ||
             (e = hipStreamSynchronize(s->st)))
             return hip_fail(e, "zero fields");
+        live_build(s, [](int, int, int, int) { return false; });
         return FDTD_OK;
     }
     // Stored values per component and row: positions outside the component's
@@ -1037,6 +1193,12 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
         (e = hipStreamSynchronize(s->st)))
         return hip_fail(e, "upload fields");
     release_large_staging(s);
+    live_build(s, [&](int c, int i, int j, int k) {
+        if (c < 3) return false;        // pinned E edges were stored as +0
+        uint32_t b;
+        std::memcpy(&b, host + (size_t)c * nbox + (size_t)k * nplane + (size_t)j * (nx + 1) + i, 4);
+        return b != 0;                  // -0 and values a 16-bit format rounds to +0 count as live
+    });
     return FDTD_OK;
 }
 
@@ -1057,6 +1219,7 @@ int fdtd_set_source(fdtd_solver *s, int comp, int i, int j, int k, const float *
     s->samples.insert(s->samples.end(), waveform, waveform + n_samples);
     s->src_pos.push_back(make_int4(comp, i, j, k));
     s->src_wave.push_back(make_int2(off, n_samples));
+    live_source(s, i, j, k);
     s->a_max = amax;
     int rc = upload_sources(s);
     if (rc) return rc;
@@ -1130,9 +1293,11 @@ int fdtd_step(fdtd_solver *s, int n_steps)
             return fail(FDTD_EINVAL, "grid planes too large for the fused kernel at this T");
         box_take_sources(s);
         box_args(s, &a);
+        a.live = s->zero_skip ? s->live : nullptr;
         if (s->poison) {     // every value the launch owns must be rewritten: nothing may rely on the old buffer
             a.box_lo = make_int4(-(1 << 28), -(1 << 28), -(1 << 28), 0);
             a.box_hi = make_int4(1 << 28, 1 << 28, 1 << 28, 0);
+            a.live = nullptr;
             if ((e = hipMemsetAsync(s->fbuf[s->cur ^ 1], 0xff, s->d.fbytes, s->st))) return hip_fail(e, "poison");
         }
         if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
@@ -1378,6 +1543,14 @@ int fdtd_load_state(fdtd_solver *s, const void *host_src, size_t bytes)
     s->steps = h.steps;
     s->block = h.block;
     for (int a = 0; a < 3; ++a) { s->box_lo[a] = h.box_lo[a]; s->box_hi[a] = h.box_hi[a]; }
+    const char *fb = src + sizeof(h);
+    const int es = elem_size(s->storage);
+    live_build(s, [&](int c, int i, int j, int k) {
+        const size_t at = ((size_t)c * s->L.cstride + (size_t)k * s->L.kstride + (size_t)j * s->L.pitch + i) * es;
+        uint32_t b = 0;
+        std::memcpy(&b, fb + at, es);
+        return b != 0;
+    });
     return FDTD_OK;
 }
 
@@ -1424,6 +1597,7 @@ void fdtd_destroy(fdtd_solver *s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->st);
+    live_drop(s);
     if (s->own_ws) free_dev(s->ws);
     free_dev(s->coef_d);
     free_dev(s->eps_d);

@@ -39,6 +39,11 @@
 // launched: the grid covers only the box of tiles meeting the value box
 // (offsets tx0, ty0, tz0), and the probe rows of the others keep the 0 they
 // were allocated with.
+// Dead tiles: inside a perfect conductor, a node whose E edges are all
+// conductor-owned (Ca = Cb = 0, so every update writes +0) and whose H values
+// see only such edges (a zero curl) keeps +0 for good once it holds +0.  The
+// host lists the tiles owning a node that is not dead; the launch walks that
+// list, and a listed tile missing the value box exits at once.
 //
 // Addressing: every array is read through a buffer resource based at the
 // chunk's first plane; the per-lane x offset lives in one VGPR and the plane
@@ -127,8 +132,32 @@ struct TileShared {
 // `logical` is the tile index within the solve.  Starts and ends with every
 // thread of the workgroup in step, so a workgroup may run several tiles in a
 // row (the batched kernel does).
+// Tile coordinates of work item `logical`: from the launched range of tiles,
+// or from a list of the tiles owning a live node (indices into the full
+// tiling).  False for a listed tile outside the range -- it misses the value
+// box, so it would only rewrite +0 -- except item 0, which runs anyway: it
+// publishes the next block's scales.
+__device__ __forceinline__ bool tile_coords(const FusedArgs &a, const int logical, int &tx, int &ty, int &tz)
+{
+    if (!a.tiles) {
+        const int rem = logical / a.ntx;
+        tx = a.tx0 + logical % a.ntx;
+        ty = a.ty0 + rem % a.nty;
+        tz = a.tz0 + rem / a.nty;
+        return true;
+    }
+    const int t = a.tiles[logical];
+    const int rem = t / a.ltx;
+    tx = t % a.ltx;
+    ty = rem % a.lty;
+    tz = rem / a.lty;
+    return logical == 0 || (tx >= a.tx0 && tx < a.tx0 + a.ntx && ty >= a.ty0 && ty < a.ty0 + a.nty &&
+                            tz >= a.tz0 && tz < a.tz0 + a.ntz);
+}
+
 template <int T, int RY, int NW, class Codec, bool GR = false>
-__device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical, TileShared<T, NW> &sm)
+__device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical, const int tx, const int ty,
+                                           const int tz, TileShared<T, NW> &sm)
 {
     constexpr int OX = 64 - 2 * T;      // owned points per tile in x
     constexpr int NR = NW * RY;         // rows per tile
@@ -175,9 +204,6 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
 
     const Layout L = a.L;
     const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const int tx = a.tx0 + logical % a.ntx;   // within the launched range of tiles
-    const int rem = logical / a.ntx;
-    const int ty = a.ty0 + rem % a.nty, tz = a.tz0 + rem / a.nty;
     const int x0 = tx * OX, y0 = ty * OY, z0 = tz * a.zc;
     const int z1 = min(z0 + a.zc, nz + 1);
     const int xl = x0 - T;              // x of lane 0
@@ -576,8 +602,9 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     // contiguous run of tiles so that halo re-reads hit its own L2.
     const int nb = gridDim.x, b = blockIdx.x;
     const int logical = (b & 7) * (nb >> 3) + (b >> 3);
-    if (logical >= a.nwg) return;   // uniform per workgroup
-    fused_tile<T, RY, NW, Codec, GR>(a, logical, sm);
+    int tx, ty, tz;
+    if (logical >= a.nwg || !tile_coords(a, logical, tx, ty, tz)) return;   // uniform per workgroup
+    fused_tile<T, RY, NW, Codec, GR>(a, logical, tx, ty, tz, sm);
 }
 
 // Several solves in one persistent launch: the workgroups stride over the
@@ -591,7 +618,9 @@ __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         int i = 0;
         while (i + 1 < a.n && item >= a.start[i + 1]) ++i;
-        fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], sm);
+        int tx, ty, tz;
+        tile_coords(a.s[i], item - a.start[i], tx, ty, tz);   // a range: always true
+        fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], tx, ty, tz, sm);
     }
 }
 
@@ -705,12 +734,20 @@ hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
     FusedArgs a = a0;
     int threads;
     geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
-    if (!restrict_to_box<T, tl.ry * tl.nw>(a)) {
+    int listed = 0;
+    a.tiles = nullptr;
+    if (a.live) {
+        a.tiles = live_tile_list(a.live, 64 - 2 * T, tl.ry * tl.nw - 2 * T, a.zc, a.ntx, a.nty, a.ntz, &listed, st);
+        a.ltx = a.ntx;
+        a.lty = a.nty;
+    }
+    if (!restrict_to_box<T, tl.ry * tl.nw>(a) || (a.tiles && listed == 0)) {
         if (!Codec::scaled) return hipSuccess;      // all +0 and stays so
         a.ntx = a.nty = a.ntz = 1;                  // one tile publishes the next block's scales
         a.tx0 = a.ty0 = a.tz0 = 0;
+        a.tiles = nullptr;
     }
-    a.nwg = a.ntx * a.nty * a.ntz;
+    a.nwg = a.tiles ? listed : a.ntx * a.nty * a.ntz;
     const int grid = (a.nwg + 7) / 8 * 8;
     hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR>), dim3(grid), dim3(threads), 0, st, a);
     return hipGetLastError();
@@ -728,6 +765,8 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
     for (int i = 0; i < n; ++i) {
         FusedArgs &a = b.s[i];
         a = args[i];
+        a.live = nullptr;                           // batched solves run every tile of their range
+        a.tiles = nullptr;
         geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, 0, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
         if (!restrict_to_box<T, tl.ry * tl.nw>(a)) {
             a.ntx = a.nty = a.ntz = Codec::scaled ? 1 : 0;

@@ -54,6 +54,20 @@ struct StorageBlock {
     float a_max;          // largest |source sample|
 };
 
+// Live nodes of a solve: a node is dead when its six values are +0 and stay
+// so for good -- its E edges are walls or belong to perfect-conductor cells
+// (no source on them), and each of its H values sees only such edges.  The
+// runtime keeps the map; the launcher asks it, per tile geometry, for the
+// tiles whose owned region holds a live node (conductor interiors drop out).
+struct LiveNodes;
+// Device list, ascending, of tile indices (tz nty + ty) ntx + tx of the full
+// ntx x nty x ntz tiling (owned regions of ox x oy points and zc planes) that
+// own a live node; *count is its length.  nullptr when every tile does (or
+// the list could not be made): then every tile runs.  The list stays valid
+// until the map changes.
+const int *live_tile_list(LiveNodes *d, int ox, int oy, int zc, int ntx, int nty, int ntz, int *count,
+                          hipStream_t st);
+
 struct FusedArgs {
     Layout L;
     const void *fin;
@@ -72,6 +86,13 @@ struct FusedArgs {
     int4 box_lo, box_hi;
     int ntx, nty, ntz, nwg;   // launched tiles per axis (filled by the launcher)
     int tx0, ty0, tz0;        // index of the first launched tile per axis
+    // Dead tiles: `live` (host, null: all live) is consulted by the launcher,
+    // which then runs the listed `tiles` (device, full-tiling indices with ltx
+    // x lty tiles per plane) instead of the range; listed tiles outside the
+    // range exit at once.
+    LiveNodes *live;
+    const int *tiles;
+    int ltx, lty;
     int zc;               // planes per z chunk
     long long step0;      // absolute step index advanced by time level 1
     SourceTable src;
