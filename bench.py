@@ -281,6 +281,23 @@ def main():
                           "traffic_per_step": measured_traffic("open256", "fp32", "plain")}
         print(f"[bench] CPML (open256, plain kernels): {vo:.2f} G cell-updates/s; plain without layers "
               f"{vp:.2f}", file=sys.stderr, flush=True)
+        # the paper's case S: a 400-cell perfect-conductor sphere in 402^3, a
+        # 1300-step solve from zero fields, with the conductor interior's
+        # tiles skipped and without (rates count every cell, as the paper does)
+        ws = W.sphere402()
+        case_s = {"workload": ws.name, "steps": ws.n_steps}
+        for key, st, tb, skip in (("fp32", W.FP32, 4, True), ("fp16", W.FP16, 3, True),
+                                  ("fp32_no_skip", W.FP32, 4, False)):
+            sx = fdtd.Solver.from_workload(ws, storage=st, kernel=fdtd.KERNEL_FUSED, time_block=tb)
+            try:
+                sx.set_zero_skip(skip)
+                ms = time_steps(sx, ws.n_steps, torch, stream) * 1e3
+            finally:
+                sx.close()
+            case_s[key] = {"ms": ms, "value": ws.cells * ws.n_steps / ms / 1e6, "T": tb}
+        extras["case_s"] = case_s
+        print(f"[bench] case S: FP32 {case_s['fp32']['ms']:.1f} ms, FP16 {case_s['fp16']['ms']:.1f} ms, "
+              f"FP32 without skipping {case_s['fp32_no_skip']['ms']:.1f} ms", file=sys.stderr, flush=True)
         # a full solve from host buffers: create (material upload), upload of a
         # host initial state, the solve, read-back of fields and probes
         torch.cuda.synchronize()

@@ -37,7 +37,7 @@ def test_source_and_probe_validation():
         assert _code(s.read_probes, 0, 4) == fdtd.EINVAL              # step 3 not run yet
         assert s.read_probes(0, 3).shape == (3, 1)
         assert _code(s.set_tiling, 4, 0) == fdtd.EINVAL
-        assert _code(s.set_kernel, fdtd.KERNEL_FUSED, 5) == fdtd.EINVAL
+        assert _code(s.set_kernel, fdtd.KERNEL_FUSED, 7) == fdtd.EINVAL      # T = 1..6
     finally:
         s.close()
 
