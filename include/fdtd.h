@@ -328,6 +328,22 @@ int fdtd_graded_coefficients(const fdtd_material *table, int n_materials, int nx
                              const double *dx, const double *dy, const double *dz, double dt,
                              float *cag, float *gc);
 
+/* Host only (no device, no solver): the live-node map the zero-tile skip
+ * uses for perfect conductors, for a state whose stored values are all +0.
+ * A node (i, j, k) of the (nx+1)(ny+1)(nz+1) box is dead (live[...] = 0)
+ * when its three E edges are walls or owned by cells whose material has
+ * sigma = +INFINITY, with no source on them, and each of its in-range H
+ * values (Hx from Ez at j, j+1 and Ey at k, k+1; Hy from Ex at k, k+1 and Ez
+ * at i, i+1; Hz from Ey at i, i+1 and Ex at j, j+1) sees only such edges:
+ * every update then leaves its six values at +0.  mat_index: nx*ny*nz cell
+ * indices, x fastest; sources: n_sources x (comp, i, j, k), interior E edges
+ * (a source wakes the nodes {i-1, i} x {j-1, j} x {k-1, k}); live: output,
+ * (nx+1)(ny+1)(nz+1) bytes, x fastest, 1 = live.  FDTD_EINVAL on NULL
+ * arguments, bad sizes, indices >= n_materials or a source off the interior
+ * E edges. */
+int fdtd_live_nodes(const fdtd_material *table, int n_materials, const uint8_t *mat_index, int nx, int ny, int nz,
+                    const int *sources, int n_sources, uint8_t *live);
+
 /* FP32 tables of CPML layers over graded spacing (see fdtd_set_cpml): cag
  * and gc as fdtd_graded_coefficients but with kappa folded into gc
  * (c dt / (kappa d)); cp gets, per node index of x, then y, then z, the six

@@ -353,29 +353,30 @@ void live_drop(fdtd_solver *s)
 
 // A source at node (i, j, k) unpins its edge: every node whose E or H
 // involves that edge, within {i-1, i} x {j-1, j} x {k-1, k}, becomes live.
+void live_mark_source(yee::LiveNodes *d, int i, int j, int k)
+{
+    for (int dk = -1; dk <= 0; ++dk)
+        for (int dj = -1; dj <= 0; ++dj)
+            for (int di = -1; di <= 0; ++di) d->mark(i + di, j + dj, k + dk);
+}
+
 void live_source(fdtd_solver *s, int i, int j, int k)
 {
     if (!s->live) return;
     (void)hipStreamSynchronize(s->st);
     s->live->drop_lists();
-    for (int dk = -1; dk <= 0; ++dk)
-        for (int dj = -1; dj <= 0; ++dj)
-            for (int di = -1; di <= 0; ++di) s->live->mark(i + di, j + dj, k + dk);
+    live_mark_source(s->live, i, j, k);
 }
 
 // A node is dead when its E edges are all pinned -- walls, or owned by a
 // perfect-conductor cell, with no source -- each of its H values sees only
 // pinned edges, and its six stored values are +0: then every update rewrites
-// +0 there (Ca = Cb = 0 for pinned E, a zero curl for H).  nonzero(c, i, j,
-// k) tells whether stored component c is not +0.  Without perfect-conductor
-// cells there is no map.
-template <class NonZero>
-void live_build(fdtd_solver *s, NonZero nonzero)
+// +0 there (Ca = Cb = 0 for pinned E, a zero curl for H).  pec(i, j, k) tells
+// whether cell (i, j, k) is a perfect conductor; nonzero(c, i, j, k) whether
+// stored component c is not +0; src holds the sources as (comp, i, j, k).
+template <class Pec, class NonZero>
+void live_fill(yee::LiveNodes *d, int nx, int ny, int nz, Pec pec, NonZero nonzero, const int4 *src, size_t n_src)
 {
-    live_drop(s);
-    if (s->mat_h.empty()) return;
-    const int nx = s->L.nx, ny = s->L.ny, nz = s->L.nz;
-    auto *d = new yee::LiveNodes;
     d->nx = nx; d->ny = ny; d->nz = nz;
     d->words = (nx + 1 + 63) / 64;
     d->bits.assign((size_t)(nz + 1) * (ny + 1) * d->words, 0);
@@ -385,7 +386,7 @@ void live_build(fdtd_solver *s, NonZero nonzero)
     auto pinned_plane = [&](int k, uint8_t *p) {
         for (int j = 0; j <= ny; ++j)
             for (int i = 0; i <= nx; ++i) {
-                const bool pc = i < nx && j < ny && k < nz && s->pec[s->mat_h[((size_t)k * ny + j) * nx + i]];
+                const bool pc = i < nx && j < ny && k < nz && pec(i, j, k);
                 uint8_t m = 0;
                 for (int c = 0; c < 3; ++c)
                     if (pc || !e_interior(nx, ny, nz, c, i, j, k)) m |= (uint8_t)(1 << c);
@@ -412,8 +413,21 @@ void live_build(fdtd_solver *s, NonZero nonzero)
                 if (!dead) d->mark(i, j, k);
             }
     }
+    for (size_t q = 0; q < n_src; ++q) live_mark_source(d, src[q].y, src[q].z, src[q].w);
+}
+
+// The solver's map (none without perfect-conductor cells).
+template <class NonZero>
+void live_build(fdtd_solver *s, NonZero nonzero)
+{
+    live_drop(s);
+    if (s->mat_h.empty()) return;
+    const int nx = s->L.nx, ny = s->L.ny;
+    auto *d = new yee::LiveNodes;
+    live_fill(
+        d, nx, ny, s->L.nz, [&](int i, int j, int k) { return s->pec[s->mat_h[((size_t)k * ny + j) * nx + i]]; },
+        nonzero, s->src_pos.data(), s->src_pos.size());
     s->live = d;
-    for (const int4 &p : s->src_pos) live_source(s, p.y, p.z, p.w);
 }
 
 int upload_sources(fdtd_solver *s)
@@ -887,6 +901,35 @@ int fdtd_graded_coefficients(const fdtd_material *table, int n_materials, int nx
     const int n[3] = {nx, ny, nz};
     const double *d[3] = {dx, dy, dz};
     return graded_tables(table, n_materials, n, d, dt, CpmlParams(), cag, gc, nullptr);
+}
+
+int fdtd_live_nodes(const fdtd_material *table, int n_materials, const uint8_t *mat_index, int nx, int ny, int nz,
+                    const int *sources, int n_sources, uint8_t *live)
+{
+    if (!table || !mat_index || !live || (n_sources > 0 && !sources)) return fail(FDTD_EINVAL, "NULL argument");
+    if (nx < 1 || ny < 1 || nz < 1 || n_materials < 1 || n_materials > 256 || n_sources < 0)
+        return fail(FDTD_EINVAL, "bad sizes");
+    const size_t ncell = (size_t)nx * ny * nz;
+    for (size_t q = 0; q < ncell; ++q)
+        if (mat_index[q] >= n_materials) return fail(FDTD_EINVAL, "material index out of range");
+    std::vector<int4> src(n_sources);
+    for (int q = 0; q < n_sources; ++q) {
+        src[q] = make_int4(sources[4 * q], sources[4 * q + 1], sources[4 * q + 2], sources[4 * q + 3]);
+        if (!e_interior(nx, ny, nz, src[q].x, src[q].y, src[q].z, src[q].w))
+            return fail(FDTD_EINVAL, "source must sit on an interior E edge");
+    }
+    yee::LiveNodes d;
+    live_fill(
+        &d, nx, ny, nz,
+        [&](int i, int j, int k) { return std::isinf(table[mat_index[((size_t)k * ny + j) * nx + i]].sigma); },
+        [](int, int, int, int) { return false; }, src.data(), src.size());
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j <= ny; ++j) {
+            const uint64_t *row = &d.bits[((size_t)k * (ny + 1) + j) * d.words];
+            for (int i = 0; i <= nx; ++i)
+                live[((size_t)k * (ny + 1) + j) * (nx + 1) + i] = (uint8_t)((row[i >> 6] >> (i & 63)) & 1u);
+        }
+    return FDTD_OK;
 }
 
 int fdtd_cpml_coefficients(const fdtd_material *table, int n_materials, int nx, int ny, int nz,

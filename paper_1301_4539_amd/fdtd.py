@@ -79,11 +79,12 @@ def lib():
         L.fdtd_set_cpml.argtypes = [vp, i, i, d, d, d]
         L.fdtd_cpml_coefficients.argtypes = [C.POINTER(_Material), i, i, i, i, vp, vp, vp, d, i, i, d, d, d,
                                              vp, vp, vp]
+        L.fdtd_live_nodes.argtypes = [C.POINTER(_Material), i, vp, i, i, i, vp, i, vp]
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_zero_skip", "fdtd_set_poison", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
                      "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
-                     "fdtd_load_state"):
+                     "fdtd_load_state", "fdtd_live_nodes"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -143,6 +144,19 @@ def cpml_coefficients(eps_r, sigma, dx, dy, dz, dt, thickness, order=3, sigma_fa
                                         dz.ctypes.data, dt, thickness, order, sigma_factor, kappa_max, alpha_max,
                                         cag.ctypes.data, gc.ctypes.data, cp.ctypes.data))
     return cag, gc, cp
+
+
+def live_nodes(eps_r, sigma, mat, sources=(), mu_r=None):
+    """The library's live-node map for all-zero stored values: (nz+1, ny+1,
+    nx+1) uint8, 1 = live, for cell materials mat (nz, ny, nx) and sources
+    given as (comp, i, j, k)."""
+    arr, n = _materials(eps_r, sigma, mu_r)
+    mat = np.ascontiguousarray(mat, dtype=np.uint8)
+    nz, ny, nx = mat.shape
+    src = np.ascontiguousarray(np.asarray(list(sources), dtype=np.int32).reshape(-1, 4))
+    out = np.zeros((nz + 1, ny + 1, nx + 1), np.uint8)
+    _check(lib().fdtd_live_nodes(arr, n, mat.ctypes.data, nx, ny, nz, src.ctypes.data, len(src), out.ctypes.data))
+    return out
 
 
 def step_batch(solvers, n_steps):
