@@ -14,7 +14,10 @@ structure of the configurations this library is benchmarked on:
 * ``spheres256`` -- 256^3, 16-entry dielectric table, 40 random spheres,
   Ez soft source at the centre, 16 probes, 1000 steps.
 * ``spheres512`` -- 512^3, 200 spheres, three sources (Ex, Ey, Ez).
-* ``aniso1024`` -- 1024x512x256, same recipe as ``spheres512``.
+* ``precision512``, ``precision1024`` -- 512^3 and 1024x512x256, the
+  ``spheres512`` recipe with 16-bit storage, 2000 steps.
+* ``cavity402`` -- the paper's case C: an empty 402^3 PEC cavity with a
+  pin-point current.
 * ``serving``   -- 256 requests with random anisotropic grids.
 * ``graded256`` -- 256^3 with graded cell sizes (fine core, geometric growth
   to coarse cells near the walls), otherwise as ``spheres256``.
