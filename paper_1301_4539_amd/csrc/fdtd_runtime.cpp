@@ -271,12 +271,17 @@ struct LiveNodes {
         std::vector<int> host;          // source of the (asynchronous) upload
     };
     std::vector<List> lists;
+    struct Chunk {
+        int ox, oy, T, slots, zmax, zc;
+    };
+    std::vector<Chunk> chunks;          // chosen z chunk per geometry
 
     void drop_lists()
     {
         for (List &l : lists)
             if (l.dev) (void)hipFree(l.dev);
         lists.clear();
+        chunks.clear();
     }
     void mark(int i, int j, int k)
     {
@@ -331,6 +336,49 @@ const int *live_tile_list(LiveNodes *d, int ox, int oy, int zc, int ntx, int nty
     d->lists.push_back(std::move(l));
     *count = d->lists.back().count;
     return d->lists.back().dev;
+}
+
+int live_best_zc(LiveNodes *d, int ox, int oy, int ntx, int nty, int T, int slots, int zmax)
+{
+    for (const LiveNodes::Chunk &c : d->chunks)
+        if (c.ox == ox && c.oy == oy && c.T == T && c.slots == slots && c.zmax == zmax) return c.zc;
+    // col[k][ty][tx]: plane k holds a live node in the owned columns of tile (tx, ty)
+    const int np = d->nz + 1;
+    std::vector<uint8_t> col((size_t)np * nty * ntx, 0);
+    for (int k = 0; k < np; ++k)
+        for (int j = 0; j <= d->ny; ++j) {
+            const uint64_t *row = &d->bits[((size_t)k * (d->ny + 1) + j) * d->words];
+            uint8_t *f = &col[((size_t)k * nty + j / oy) * ntx];
+            for (int w = 0; w < d->words; ++w) {
+                uint64_t b = row[w];
+                while (b) {
+                    const int tx = (w * 64 + __builtin_ctzll(b)) / ox;
+                    f[tx] = 1;
+                    const int next = (tx + 1) * ox - w * 64;
+                    if (next >= 64) break;
+                    b &= ~0ULL << next;
+                }
+            }
+        }
+    const int per_plane = ntx * nty;
+    std::vector<uint8_t> any(per_plane);
+    int best_z = 0;
+    double best = 0.0;
+    for (int n = 1; n <= np; ++n) {
+        const int zz = (np + n - 1) / n;
+        if (zz > zmax || (n > 1 && zz == (np + n - 2) / (n - 1))) continue;
+        long long listed = 0;
+        for (int k0 = 0; k0 < np; k0 += zz) {
+            std::fill(any.begin(), any.end(), 0);
+            for (int k = k0; k < std::min(np, k0 + zz); ++k)
+                for (int t = 0; t < per_plane; ++t) any[t] |= col[(size_t)k * per_plane + t];
+            for (int t = 0; t < per_plane; ++t) listed += any[t];
+        }
+        const double cost = (double)((listed + slots - 1) / slots) * (zz + 1.5 * T);
+        if (best_z == 0 || cost < best) { best = cost; best_z = zz; }
+    }
+    d->chunks.push_back({ox, oy, T, slots, zmax, best_z});
+    return best_z;
 }
 
 }  // namespace yee

@@ -655,7 +655,7 @@ int planes_fit(const Layout &L, int es)
 // launch takes ceil(workgroups / slots) rounds -- a few workgroups spilling
 // into another round cost a whole round.
 void geometry_for(int T, int variant, int zc_req, int es, const Layout &L, int slots, int *ntx, int *nty, int *ntz,
-                  int *zc, int *threads)
+                  int *zc, int *threads, LiveNodes *live = nullptr)
 {
     const Tiling tl = kTilings[T][variant];
     const int OX = 64 - 2 * T, OY = tl.nw * tl.ry - 2 * T;
@@ -664,6 +664,8 @@ void geometry_for(int T, int variant, int zc_req, int es, const Layout &L, int s
     const int zmax = std::max(1, planes_fit(L, es) - 2 * T - 1);
     const int per_plane = *ntx * *nty;
     int z = zc_req;
+    if (z <= 0 && slots > 0 && live)            // the same model over the listed tiles only
+        z = live_best_zc(live, OX, OY, *ntx, *nty, T, slots, zmax);
     if (z <= 0 && slots > 0) {
         double best = 0.0;
         for (int n = 1; n <= L.nz + 1; ++n) {
@@ -733,7 +735,7 @@ hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
     static const int slots = resident_slots(yee_fused<T, tl.ry, tl.nw, Codec, GR>, 64 * tl.nw);
     FusedArgs a = a0;
     int threads;
-    geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+    geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads, a.live);
     int listed = 0;
     a.tiles = nullptr;
     if (a.live) {

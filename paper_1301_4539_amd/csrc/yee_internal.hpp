@@ -67,6 +67,10 @@ struct LiveNodes;
 // until the map changes.
 const int *live_tile_list(LiveNodes *d, int ox, int oy, int zc, int ntx, int nty, int ntz, int *count,
                           hipStream_t st);
+// The z chunk (<= zmax planes) minimising rounds * (zc + 1.5 T) when only the
+// tiles owning a live node are launched, `slots` workgroups at a time; 0 when
+// none qualifies.  Cached per geometry until the map changes.
+int live_best_zc(LiveNodes *d, int ox, int oy, int ntx, int nty, int T, int slots, int zmax);
 
 struct FusedArgs {
     Layout L;
