@@ -188,6 +188,10 @@ def main():
     s = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_PLAIN if plain else fdtd.KERNEL_FUSED,
                                   time_block=T)
     s.set_tiling(args.tiling, args.zchunk)
+    # Every timed launch does its full work (the zero-tile skip off), so the
+    # algorithmic bytes per launch hold for each of them; the skip's effect
+    # is measured on its own in latency_ms.
+    s.set_zero_skip(False)
     if args.warmup:
         s.step(args.warmup)
     start = s.steps_done()
@@ -195,9 +199,9 @@ def main():
     # a plain "launch" is one step's H and E kernel pair
     launches = args.steps if plain else launches_for(start, args.steps, T)
     value = cells * args.steps / t / 1e9
-    b_alg = roofline.algorithmic_bytes(4)
+    b_alg = roofline.algorithmic_bytes(4 if storage == W.FP32 else 2)
     achieved = b_alg * cells * args.steps / t / 1e9          # GB/s, algorithmic
-    traffic = measured_traffic(wl.name, "fp32", "plain" if plain else T)
+    traffic = measured_traffic(wl.name, args.storage, "plain" if plain else T)
     print(f"[bench] {args.storage}: {value:.2f} G cell-updates/s, {t * 1e3 / launches:.3f} ms per launch",
           file=sys.stderr, flush=True)
 
@@ -344,16 +348,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "storage": "fp32",
+        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "storage": args.storage,
                    "kernel": args.kernel, "T": None if plain else T, "materials": len(wl.eps_r),
                    "spheres": {"spheres256": 40, "spheres512": 200, "graded256": 40, "open256": 40}.get(wl.name, 0),
                    "sources": len(wl.sources),
-                   "probes": len(wl.probes), "parallelism": "single-gpu"},
+                   "probes": len(wl.probes), "zero_skip": False, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": roofline.HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / roofline.HBM_PEAK_GBPS,
                      "traffic": traffic,
                      "alg_bytes_per_launch": b_alg * cells * args.steps / launches,
-                     "kernel": "h_plain+e_plain<fp32>" if plain else f"yee_fused<T={T},fp32>",
+                     "kernel": "h_plain+e_plain<fp32>" if plain else f"yee_fused<T={T},{args.storage}>",
                      "bytes_per_cell_update": b_alg,
                      "avg_launch_ms": t * 1e3 / launches, "launches": launches},
     }
