@@ -228,6 +228,7 @@ def main():
             """G cell-updates/s of the fused kernel for storage st at time block tb."""
             sx = fdtd.Solver.from_workload(wl, storage=st, kernel=fdtd.KERNEL_FUSED, time_block=tb)
             try:
+                sx.set_zero_skip(False)             # full launches, as in the timed leg
                 if args.warmup:
                     sx.step(args.warmup)
                 return cells * args.steps / time_steps(sx, args.steps, torch, stream) / 1e9
@@ -259,6 +260,7 @@ def main():
         wg = W.graded256()
         sg = fdtd.Solver.from_workload(wg)
         try:
+            sg.set_zero_skip(False)
             if args.warmup:
                 sg.step(args.warmup)
             vg = wg.cells * args.steps / time_steps(sg, args.steps, torch, stream) / 1e9
