@@ -102,10 +102,27 @@ def cpu_baseline(wl, budget_s=15.0):
     t0 = time.perf_counter()
     prob.run_f32(f, 2, n)
     dt = time.perf_counter() - t0
-    return {"value": wl.cells * n / dt / 1e9, "unit": "G cell-updates/s", "cores": oracle.threads(),
+    # the same oracle on one thread, over a few more steps
+    nt = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        n1 = int(max(1, min(20, 4.0 / max(per * nt, 1e-6))))
+        t0 = time.perf_counter()
+        prob.run_f32(f, 2 + n, n1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(nt)
+    host = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            host = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"value": wl.cells * n / dt / 1e9, "unit": "G cell-updates/s", "cores": nt,
             "kind": "oracle",
             "sample": f"{wl.nx}x{wl.ny}x{wl.nz} {wl.name}, steps 3-{2 + n} ({n} steps) of the FP32 "
-                      f"operation-order oracle from zero fields, {oracle.threads()} OpenMP threads"}
+                      f"operation-order oracle from zero fields, {nt} OpenMP threads",
+            "one_thread": {"value": wl.cells * n1 / dt1 / 1e9, "steps": n1}, "host_cpu": host}
 
 
 def serving_leg(rate, n, torch):

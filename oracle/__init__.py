@@ -53,6 +53,8 @@ def lib():
         L.orc_energy_f32.argtypes = [_i, _i, _i, _fp, _dp, _u8, _fp]
         L.orc_energy_f32.restype = C.c_double
         L.orc_threads.restype = _i
+        L.orc_set_threads.argtypes = [_i]
+        L.orc_set_threads.restype = None
         L.orc_divergence_f64.argtypes = [_i, _i, _i, C.c_double, C.c_double, C.c_double, _dp, _u8, _dp, _dp, _dp]
         L.orc_graded_coefficients.argtypes = [_i, _dp, _dp, C.c_double, _i, _i, _i, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_h_half_graded_f64.argtypes = [_i, _i, _i, _dp, _dp]
@@ -345,3 +347,8 @@ def choose_scales(m_prev, a_max):
 def threads() -> int:
     """Threads the oracle's parallel loops use."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int):
+    """Threads for the parallel loops from now on (timing only)."""
+    lib().orc_set_threads(int(n))

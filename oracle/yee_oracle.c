@@ -1335,10 +1335,13 @@ int orc_run_q_graded(int nx, int ny, int nz, int fmt, int T, const float *hc, co
     return 0;
 }
 
-/* Number of threads the parallel loops use (1 without OpenMP). */
+/* Number of threads the parallel loops use (1 without OpenMP), and setting
+ * it (timing only; results do not depend on it). */
 #ifdef _OPENMP
 #include <omp.h>
 int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 int orc_threads(void) { return 1; }
+void orc_set_threads(int n) { (void)n; }
 #endif
