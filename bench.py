@@ -233,6 +233,18 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        # FP64 diagnostics (energy, div E, div H, max |value|) of the final
+        # state, outside the timed region: cost per call, and its share of a
+        # run that asks for them every 250 steps
+        s.synchronize()
+        d_ms = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            dg = s.diagnostics()
+            d_ms.append((time.perf_counter() - t0) * 1e3)
+        dm = float(np.median(d_ms))
+        extras["diagnostics"] = {"ms_per_call": dm, "share_every_250_steps": dm / (dm + 250 * t * 1e3 / args.steps),
+                                 "energy": dg["energy"], "div_e_max": dg["div_e_max"], "div_h_max": dg["div_h_max"]}
         s.close()
 
         # per-solve latency: full solves of the workload (a fresh solver each,
