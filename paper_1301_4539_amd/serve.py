@@ -153,6 +153,18 @@ class GpuBackend:
         self.wl = workloads
         tb = DEFAULT_T if time_block is None else time_block
         self.T = dict(tb) if isinstance(tb, dict) else {k: int(tb) for k in DEFAULT_T}
+        self.alone = set()      # solves fdtd_step_batch does not take: stepped one by one
+
+    def solver_options(self, wl):
+        """(kernel, T, batched) for a request: uniform grids run the fused
+        kernel at the storage's T in shared launches; graded sizes take their
+        automatic T and CPML layers the plain kernels, each stepped alone."""
+        f = self.fdtd
+        if wl.cpml:
+            return f.KERNEL_AUTO, 0, False
+        if wl.spacing is not None:
+            return f.KERNEL_FUSED, 0, False
+        return f.KERNEL_FUSED, self.T[wl.storage], True
 
     def now(self) -> float:
         return time.perf_counter()
@@ -166,21 +178,30 @@ class GpuBackend:
         return self.fdtd.workspace_bytes(req.nx, req.ny, req.nz, req.storage) + 8 * 8 * (req.n_steps + 256)
 
     def create(self, req):
+        kernel, tb, batched = self.solver_options(self.wl[req.rid])
         try:
-            return self.fdtd.Solver.from_workload(self.wl[req.rid], kernel=self.fdtd.KERNEL_FUSED,
-                                                  time_block=self.T[req.storage])
+            h = self.fdtd.Solver.from_workload(self.wl[req.rid], kernel=kernel, time_block=tb)
+            if not batched:
+                self.alone.add(h)
+            return h
         except (self.fdtd.FdtdError, self.torch.cuda.OutOfMemoryError) as e:
             if isinstance(e, self.fdtd.FdtdError) and e.code != self.fdtd.ENOMEM:
                 raise
             raise AdmissionError(str(e)) from e
 
     def step(self, handles, counts):
-        self.fdtd.step_batch(handles, counts)
+        batch = [(h, n) for h, n in zip(handles, counts) if h not in self.alone]
+        if batch:
+            self.fdtd.step_batch([h for h, _ in batch], [n for _, n in batch])
+        for h, n in zip(handles, counts):
+            if h in self.alone:
+                h.step(n)
 
     def sync(self):
         self.torch.cuda.synchronize()
 
     def finish(self, h, req) -> np.ndarray:
         p = h.read_probes(0, req.n_steps)
+        self.alone.discard(h)
         h.close()
         return p
