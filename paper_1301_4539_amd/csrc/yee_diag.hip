@@ -7,13 +7,18 @@
 //     magnitude and sum of squares (both constant in time without sources
 //     and losses);
 //   largest |value| per component.
-// Reduction is deterministic: each block reduces its points in a fixed
-// tree, then one block sums the block partials in index order.
+// Reduction is deterministic: each thread accumulates its (i, j) column over
+// a fixed run of planes in ascending k, each block reduces its threads in a
+// fixed tree, then one block sums the block partials in index order.  The
+// plane runs keep the partials few (a few thousand), so the final
+// single-block pass is short.
 // Graded spacing (GR): every term is weighted by its volume (edge length x
 // dual face area for E, face area x dual edge length for H; dual sizes are
 // half cells on the walls), the energy is then in units of eps0 with volumes
 // in m^3, differences are divided by the per-index sizes, and H^{n+1/2} uses
 // the per-index update factors.
+
+#include <algorithm>
 
 #include "yee_device.hpp"
 #include "yee_internal.hpp"
@@ -23,6 +28,7 @@ namespace yee {
 namespace {
 
 constexpr int DBX = 64, DBY = 4, DT = DBX * DBY;
+constexpr int DZ = 8;   // plane runs per grid (fewer for thin grids)
 
 template <class Codec, bool GR>
 __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
@@ -37,7 +43,8 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
     const Layout &L = a.L;
     const int i = blockIdx.x * DBX + threadIdx.x;
     const int j = blockIdx.y * DBY + threadIdx.y;
-    const int k = blockIdx.z;
+    const int run = (L.nz + 1 + gridDim.z - 1) / gridDim.z;
+    const int k0 = blockIdx.z * run, k1 = min(L.nz + 1, k0 + run);
     const S *f = static_cast<const S *>(a.f);
     float dn[6];
     for (int c = 0; c < 6; ++c) dn[c] = Codec::scaled ? ldexpf(1.0f, -a.sb.ctrl->scale[a.sb.par][c]) : 1.0f;
@@ -45,7 +52,7 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
 
     double v[DIAG_W];
     for (int q = 0; q < DIAG_W; ++q) v[q] = 0.0;
-    if (i <= L.nx && j <= L.ny) {
+    for (int k = k0; k < k1 && i <= L.nx && j <= L.ny; ++k) {
         const int nx = L.nx, ny = L.ny, nz = L.nz;
         const long long p = k * L.kstride + (long long)j * L.pitch + i;
         // owner-cell permittivity of an E edge, zero on wall (PEC) edges
@@ -101,8 +108,8 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
             double d;
             if constexpr (GR) d = tx / sx.y + ty / sy.y + tz / sz.y;
             else d = tx * a.idx + ty * a.idy + tz * a.idz;
-            v[1] = d * d;
-            v[3] = fabs(d);
+            v[1] += d * d;
+            v[3] = fmax(v[3], fabs(d));
         }
         // div(H) at cell centres
         if (i < nx && j < ny && k < nz) {
@@ -111,11 +118,11 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
             double d;
             if constexpr (GR) d = tx / sx.x + ty / sy.x + tz / sz.x;
             else d = tx * a.idx + ty * a.idy + tz * a.idz;
-            v[2] = d * d;
-            v[4] = fabs(d);
+            v[2] += d * d;
+            v[4] = fmax(v[4], fabs(d));
         }
-        v[5] = fabs(ex); v[6] = fabs(ey); v[7] = fabs(ez);
-        v[8] = fabs(hx); v[9] = fabs(hy); v[10] = fabs(hz);
+        v[5] = fmax(v[5], fabs(ex)); v[6] = fmax(v[6], fabs(ey)); v[7] = fmax(v[7], fabs(ez));
+        v[8] = fmax(v[8], fabs(hx)); v[9] = fmax(v[9], fabs(hy)); v[10] = fmax(v[10], fabs(hz));
     }
     // fixed-tree block reduction, one quantity at a time
     const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -157,7 +164,7 @@ template <class Codec>
 hipError_t launch_diag_t(const DiagArgs &a, double *out, hipStream_t st)
 {
     dim3 block(DBX, DBY, 1);
-    dim3 grid((a.L.nx + 1 + DBX - 1) / DBX, (a.L.ny + 1 + DBY - 1) / DBY, a.L.nz + 1);
+    dim3 grid((a.L.nx + 1 + DBX - 1) / DBX, (a.L.ny + 1 + DBY - 1) / DBY, std::min(DZ, a.L.nz + 1));
     if (a.gc) {
         if (!a.gsz) return hipErrorInvalidValue;
         hipLaunchKernelGGL((diag_points<Codec, true>), grid, block, 0, st, a);
@@ -173,7 +180,7 @@ hipError_t launch_diag_t(const DiagArgs &a, double *out, hipStream_t st)
 
 int diag_blocks(const Layout &L)
 {
-    return ((L.nx + 1 + DBX - 1) / DBX) * ((L.ny + 1 + DBY - 1) / DBY) * (L.nz + 1);
+    return ((L.nx + 1 + DBX - 1) / DBX) * ((L.ny + 1 + DBY - 1) / DBY) * std::min(DZ, L.nz + 1);
 }
 
 hipError_t launch_diag(int storage, const DiagArgs &a, double *out, hipStream_t st)
