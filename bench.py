@@ -296,18 +296,22 @@ def main():
         print(f"[bench] deep blocks: {extras['deep_blocks']}", file=sys.stderr, flush=True)
         # graded cell sizes (per-index coefficient arrays), FP32, automatic T and tile shape
         wg = W.graded256()
-        sg = fdtd.Solver.from_workload(wg)
-        try:
-            sg.set_zero_skip(False)
-            if args.warmup:
-                sg.step(args.warmup)
-            vg = wg.cells * args.steps / time_steps(sg, args.steps, torch, stream) / 1e9
-        finally:
-            sg.close()
+
+        def graded_rate(st):
+            sg = fdtd.Solver.from_workload(wg, storage=st)
+            try:
+                sg.set_zero_skip(False)
+                if args.warmup:
+                    sg.step(args.warmup)
+                return wg.cells * args.steps / time_steps(sg, args.steps, torch, stream) / 1e9
+            finally:
+                sg.close()
+        vg, vg16 = graded_rate(W.FP32), graded_rate(W.FP16)
         extras["graded_spacing"] = {"workload": wg.name, "value": vg, "unit": "G cell-updates/s",
                                     "ratio_vs_uniform": vg / value, "T": 3,
-                                    "traffic": measured_traffic(wg.name, "fp32", 3)}
-        print(f"[bench] graded spacing ({wg.name}): {vg:.2f} G cell-updates/s", file=sys.stderr, flush=True)
+                                    "traffic": measured_traffic(wg.name, "fp32", 3), "fp16": vg16}
+        print(f"[bench] graded spacing ({wg.name}): {vg:.2f} G cell-updates/s, FP16 storage {vg16:.2f}",
+              file=sys.stderr, flush=True)
         # open space: CPML layers on every face (plain kernel family), and the
         # plain kernels without layers on the same grid for reference
         def plain_rate(w):
