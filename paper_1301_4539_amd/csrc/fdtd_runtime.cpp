@@ -431,35 +431,41 @@ void live_fill(yee::LiveNodes *d, int nx, int ny, int nz, Pec pec, NonZero nonze
     // bit c of P[k & 1][j (nx+1) + i]: E component c at node (i, j, k) is pinned
     const size_t np = (size_t)(nx + 1) * (ny + 1);
     std::vector<uint8_t> P[2] = {std::vector<uint8_t>(np), std::vector<uint8_t>(np)};
+    // (the interior tests of e_interior, split into their row and x parts)
     auto pinned_plane = [&](int k, uint8_t *p) {
-        for (int j = 0; j <= ny; ++j)
+        const bool kin = k > 0 && k < nz, klt = k < nz;
+        for (int j = 0; j <= ny; ++j) {
+            const bool jin = j > 0 && j < ny, jlt = j < ny;
+            const bool rx = jin && kin, ry = jlt && kin, rz = klt && jin, rc = jlt && klt;
+            uint8_t *q = p + (size_t)j * (nx + 1);
             for (int i = 0; i <= nx; ++i) {
-                const bool pc = i < nx && j < ny && k < nz && pec(i, j, k);
-                uint8_t m = 0;
-                for (int c = 0; c < 3; ++c)
-                    if (pc || !e_interior(nx, ny, nz, c, i, j, k)) m |= (uint8_t)(1 << c);
-                p[(size_t)j * (nx + 1) + i] = m;
+                const bool iin = i > 0 && i < nx;
+                const bool pc = rc && i < nx && pec(i, j, k);
+                q[i] = (uint8_t)((pc || !(rx && i < nx)) | ((pc || !(ry && iin)) << 1) | ((pc || !(rz && iin)) << 2));
             }
+        }
     };
     pinned_plane(0, P[0].data());
     for (int k = 0; k <= nz; ++k) {
         const uint8_t *p0 = P[k & 1].data();
         if (k < nz) pinned_plane(k + 1, P[(k + 1) & 1].data());
         const uint8_t *p1 = P[(k + 1) & 1].data();     // read only when k < nz
-        for (int j = 0; j <= ny; ++j)
+        for (int j = 0; j <= ny; ++j) {
+            uint64_t *row = &d->bits[((size_t)k * (ny + 1) + j) * d->words];
+            const uint8_t *a = p0 + (size_t)j * (nx + 1);
             for (int i = 0; i <= nx; ++i) {
-                const size_t q = (size_t)j * (nx + 1) + i;
-                bool dead = p0[q] == 7;
+                bool dead = a[i] == 7;
                 if (dead && j < ny && k < nz)    // Hx: Ez at j and j+1, Ey at k and k+1
-                    dead = (p0[q + nx + 1] & 4) && (p1[q] & 2);
+                    dead = (a[i + nx + 1] & 4) && (p1[(size_t)j * (nx + 1) + i] & 2);
                 if (dead && i < nx && k < nz)    // Hy: Ex at k and k+1, Ez at i and i+1
-                    dead = (p1[q] & 1) && (p0[q + 1] & 4);
+                    dead = (p1[(size_t)j * (nx + 1) + i] & 1) && (a[i + 1] & 4);
                 if (dead && i < nx && j < ny)    // Hz: Ey at i and i+1, Ex at j and j+1
-                    dead = (p0[q + 1] & 2) && (p0[q + nx + 1] & 1);
+                    dead = (a[i + 1] & 2) && (a[i + nx + 1] & 1);
                 for (int c = 0; c < 6 && dead; ++c)
                     dead = !(in_range(nx, ny, nz, c, i, j, k) && nonzero(c, i, j, k));
-                if (!dead) d->mark(i, j, k);
+                if (!dead) row[i >> 6] |= 1ULL << (i & 63);
             }
+        }
     }
     for (size_t q = 0; q < n_src; ++q) live_mark_source(d, src[q].y, src[q].z, src[q].w);
 }
@@ -966,10 +972,11 @@ int fdtd_live_nodes(const fdtd_material *table, int n_materials, const uint8_t *
         if (!e_interior(nx, ny, nz, src[q].x, src[q].y, src[q].z, src[q].w))
             return fail(FDTD_EINVAL, "source must sit on an interior E edge");
     }
+    bool pt[256] = {};
+    for (int m = 0; m < n_materials; ++m) pt[m] = std::isinf(table[m].sigma);
     yee::LiveNodes d;
     live_fill(
-        &d, nx, ny, nz,
-        [&](int i, int j, int k) { return std::isinf(table[mat_index[((size_t)k * ny + j) * nx + i]].sigma); },
+        &d, nx, ny, nz, [&](int i, int j, int k) { return pt[mat_index[((size_t)k * ny + j) * nx + i]]; },
         [](int, int, int, int) { return false; }, src.data(), src.size());
     for (int k = 0; k <= nz; ++k)
         for (int j = 0; j <= ny; ++j) {
