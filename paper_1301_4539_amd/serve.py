@@ -4,7 +4,8 @@ Requests (grid size, material layout, step count, storage format) arrive
 over time.  The engine admits them in arrival order while a slot is free and
 their device footprint fits the HBM budget, keeps their fields resident, and
 advances every admitted solve by a chunk of steps per tick through
-fdtd_step_batch, so small grids share persistent launches.  Solves admitted
+fdtd_step_batch, so small grids share persistent launches; solves waiting
+long get up to a few chunks per tick.  Solves admitted
 between ticks join the next tick; finished solves release their slot and
 memory.  Latency runs from arrival to the probe records being on the host.
 
@@ -17,6 +18,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import math
 import time
 from typing import Dict, List, Optional
 
@@ -66,12 +68,26 @@ class AdmissionError(RuntimeError):
 
 
 class Engine:
-    def __init__(self, backend, budget_bytes: int = 24 << 30, max_slots: int = 64, chunk: int = 64):
-        assert chunk > 0
+    """Continuous batching.  Every tick advances each admitted solve by
+    `chunk` steps, or by a multiple of it for solves that have waited long:
+    k = ceil(age / age_step) chunks, at most `max_boost` (age from arrival).
+    Multiples of the chunk keep every solve's blocks where a solo run puts
+    them; the boost bounds the tail latency of long solves."""
+
+    def __init__(self, backend, budget_bytes: int = 24 << 30, max_slots: int = 64, chunk: int = 64,
+                 age_step: float = 0.5, max_boost: int = 3):
+        assert chunk > 0 and max_boost >= 1 and age_step > 0
         self.b = backend
         self.budget = budget_bytes
         self.max_slots = max_slots
         self.chunk = chunk
+        self.age_step = age_step
+        self.max_boost = max_boost
+
+    def steps_for(self, a, now) -> int:
+        age = now - a["req"].arrival
+        k = min(self.max_boost, max(1, math.ceil(age / self.age_step)))
+        return min(a["left"], k * self.chunk)
 
     def run(self, requests) -> Report:
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
@@ -112,7 +128,8 @@ class Engine:
                     # nothing fits even on an idle device: the budget forbids it
                     rejected.append(waiting.popleft().rid)
                 continue
-            counts = [min(a["left"], self.chunk) for a in active]
+            now = self.b.now() - t0
+            counts = [self.steps_for(a, now) for a in active]
             ts = self.b.now()
             self.b.step([a["h"] for a in active], counts)
             self.b.sync()

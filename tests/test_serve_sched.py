@@ -105,3 +105,22 @@ def test_budget_limits_concurrency():
     rep = serve.Engine(fake, budget_bytes=2 * fp, max_slots=64, chunk=16).run(reqs)
     assert fake.max_live == 2
     assert all(np.isfinite(r.finished) for r in rep.records)
+
+
+def test_long_waiting_solves_get_larger_steps():
+    """A solve that has waited longer than age_step is advanced by two chunks
+    per tick, and never by more than max_boost chunks; every count is a
+    multiple of the chunk until the solve's last tick."""
+    long = W.Request(0, 0.0, 40, 40, 40, 5, 3000, W.FP32)
+    fake = Fake(rate=1e8)
+    counts = []
+    step = fake.step
+
+    def record(handles, cs):
+        counts.append(list(cs))
+        step(handles, cs)
+    fake.step = record
+    serve.Engine(fake, budget_bytes=1 << 40, max_slots=4, chunk=16, age_step=0.05, max_boost=3).run([long])
+    flat = [c[0] for c in counts]
+    assert flat[0] == 16 and max(flat) == 48 and 32 in flat
+    assert all(c % 16 == 0 for c in flat[:-1]) and sum(flat) == 3000
