@@ -139,6 +139,7 @@ def serving_leg(rate, n, torch):
     rep = eng.run(reqs)
     out = rep.summary()
     out.update({"rate_req_per_s": rate, "budget_GiB": 24, "max_slots": 64, "chunk_steps": 48,
+                "age_step_s": eng.age_step, "max_boost": eng.max_boost,
                 "T_by_storage": {"fp32": serve.DEFAULT_T[0], "fp16": serve.DEFAULT_T[1]},
                 "mean_work_G": float(np.mean([r.nx * r.ny * r.nz * r.n_steps for r in reqs]) / 1e9)})
     return out
