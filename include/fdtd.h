@@ -213,7 +213,9 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
  *    only dead nodes (conductor interiors) are not launched, for the whole
  *    run.  The map is made by fdtd_set_fields (and fdtd_create, with zero
  *    fields) and fdtd_load_state; fdtd_set_source wakes the nodes around its
- *    edge.  Batched steps run every tile.
+ *    edge.  The first fused launch of each tile geometry lists the tiles and
+ *    uploads the list (a small device allocation, kept until the map
+ *    changes).  Batched steps run every tile.
  * Skipped tiles' probes record 0.  Results are bit-identical either way. */
 int fdtd_set_zero_skip(fdtd_solver *s, int enable);
 
