@@ -357,9 +357,12 @@ def main():
             try:
                 sx.set_zero_skip(skip)
                 ms = time_steps(sx, ws.n_steps, torch, stream) * 1e3
+                sx_stats = sx.tile_stats()
             finally:
                 sx.close()
-            case_s[key] = {"ms": ms, "value": ws.cells * ws.n_steps / ms / 1e6, "T": tb}
+            run, full = sx_stats
+            case_s[key] = {"ms": ms, "value": ws.cells * ws.n_steps / ms / 1e6, "T": tb,
+                           "tiles_dispatched_share": run / full if full else None}
         extras["case_s"] = case_s
         print(f"[bench] case S: FP32 {case_s['fp32']['ms']:.1f} ms, FP16 {case_s['fp16']['ms']:.1f} ms, "
               f"FP32 without skipping {case_s['fp32_no_skip']['ms']:.1f} ms", file=sys.stderr, flush=True)

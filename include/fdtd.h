@@ -219,6 +219,14 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
  * Skipped tiles' probes record 0.  Results are bit-identical either way. */
 int fdtd_set_zero_skip(fdtd_solver *s, int enable);
 
+/* Fused-kernel tile counters since fdtd_create, summed over the fused
+ * launches of fdtd_step and fdtd_step_batch: workgroups dispatched and
+ * tiles of the full tiling.  Their ratio is the share of the
+ * grid that ran once the zero-tile skip had its say (a listed tile that
+ * misses the value box is dispatched and exits at once).  Host counters,
+ * updated as steps are enqueued; no device call.  FDTD_EINVAL on NULL. */
+int fdtd_tile_stats(const fdtd_solver *s, long long *dispatched, long long *full);
+
 /* Debugging aid (enable != 0): before every FUSED launch, fill its output
  * buffer with NaN bit patterns, and launch every tile.  A launch that leaves
  * an owned value unwritten, or reads a neighbour from the buffer it writes,

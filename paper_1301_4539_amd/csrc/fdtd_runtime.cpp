@@ -255,6 +255,8 @@ struct fdtd_solver {
     // live nodes (only when a material is a perfect conductor): conductor
     // interiors whose values are +0 for good are not launched
     yee::LiveNodes *live = nullptr;
+    // fused launches since create: workgroups dispatched, tiles of the full tiling
+    long long tile_stats[2] = {0, 0};
 };
 
 namespace yee {
@@ -628,6 +630,7 @@ void fill_fused(const fdtd_solver *s, yee::FusedArgs *a)
     a->fout = s->fbuf[s->cur ^ 1];
     a->step0 = s->steps;
     a->sb = storage_block(s);
+    a->tile_stats = const_cast<long long *>(s->tile_stats);
     a->box_lo = make_int4(-(1 << 28), -(1 << 28), -(1 << 28), 0);   // no tile skipped unless set
     a->box_hi = make_int4(1 << 28, 1 << 28, 1 << 28, 0);
 }
@@ -1146,6 +1149,14 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
     s->kernel = kernel;
     s->T = time_block;
     s->T_auto = automatic;
+    return FDTD_OK;
+}
+
+int fdtd_tile_stats(const fdtd_solver *s, long long *dispatched, long long *full)
+{
+    if (!s || !dispatched || !full) return fail(FDTD_EINVAL, "NULL argument");
+    *dispatched = s->tile_stats[0];
+    *full = s->tile_stats[1];
     return FDTD_OK;
 }
 

@@ -736,6 +736,7 @@ hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
     FusedArgs a = a0;
     int threads;
     geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads, a.live);
+    const long long full = (long long)a.ntx * a.nty * a.ntz;
     int listed = 0;
     a.tiles = nullptr;
     if (a.live) {
@@ -744,12 +745,19 @@ hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
         a.lty = a.nty;
     }
     if (!restrict_to_box<T, tl.ry * tl.nw>(a) || (a.tiles && listed == 0)) {
-        if (!Codec::scaled) return hipSuccess;      // all +0 and stays so
+        if (!Codec::scaled) {                       // all +0 and stays so
+            if (a.tile_stats) a.tile_stats[1] += full;
+            return hipSuccess;
+        }
         a.ntx = a.nty = a.ntz = 1;                  // one tile publishes the next block's scales
         a.tx0 = a.ty0 = a.tz0 = 0;
         a.tiles = nullptr;
     }
     a.nwg = a.tiles ? listed : a.ntx * a.nty * a.ntz;
+    if (a.tile_stats) {
+        a.tile_stats[0] += a.nwg;
+        a.tile_stats[1] += full;
+    }
     const int grid = (a.nwg + 7) / 8 * 8;
     hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR>), dim3(grid), dim3(threads), 0, st, a);
     return hipGetLastError();
@@ -770,11 +778,16 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
         a.live = nullptr;                           // batched solves run every tile of their range
         a.tiles = nullptr;
         geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, 0, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+        const long long full = (long long)a.ntx * a.nty * a.ntz;
         if (!restrict_to_box<T, tl.ry * tl.nw>(a)) {
             a.ntx = a.nty = a.ntz = Codec::scaled ? 1 : 0;
             a.tx0 = a.ty0 = a.tz0 = 0;
         }
         a.nwg = a.ntx * a.nty * a.ntz;
+        if (a.tile_stats) {
+            a.tile_stats[0] += a.nwg;
+            a.tile_stats[1] += full;
+        }
         b.start[i + 1] = b.start[i] + a.nwg;
     }
     // persistent: at most ~4 resident workgroups per CU, each striding over the work list

@@ -102,6 +102,9 @@ struct FusedArgs {
     SourceTable src;
     ProbeTable probe;
     StorageBlock sb;
+    // host counters (null: none): += workgroups dispatched, tiles of the full
+    // tiling, per launch
+    long long *tile_stats;
 };
 
 // Up to MAX_BATCH solves in one launch; start[i] is the first work item

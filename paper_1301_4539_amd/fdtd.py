@@ -80,11 +80,12 @@ def lib():
         L.fdtd_cpml_coefficients.argtypes = [C.POINTER(_Material), i, i, i, i, vp, vp, vp, d, i, i, d, d, d,
                                              vp, vp, vp]
         L.fdtd_live_nodes.argtypes = [C.POINTER(_Material), i, vp, i, i, i, vp, i, vp]
+        L.fdtd_tile_stats.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_zero_skip", "fdtd_set_poison", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
                      "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
-                     "fdtd_load_state", "fdtd_live_nodes"):
+                     "fdtd_load_state", "fdtd_live_nodes", "fdtd_tile_stats"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -284,6 +285,13 @@ class Solver:
         _check(lib().fdtd_diagnostics(self._h, C.byref(d)))
         return {"energy": d.energy, "div_e_max": d.div_e_max, "div_e_sumsq": d.div_e_sumsq,
                 "div_h_max": d.div_h_max, "div_h_sumsq": d.div_h_sumsq, "max_abs": list(d.max_abs)}
+
+    def tile_stats(self):
+        """(workgroups dispatched, tiles of the full tiling) of the fused
+        launches since creation."""
+        a, b = C.c_longlong(), C.c_longlong()
+        _check(lib().fdtd_tile_stats(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def save_state(self) -> np.ndarray:
         """The whole evolving state as an opaque byte array (checkpoint)."""

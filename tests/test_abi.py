@@ -133,3 +133,9 @@ def test_perfect_conductor_entries_are_zero_and_match_oracle():
     assert np.array_equal(cag, r_cag.astype(np.float32)) and np.all(cag[1] == 0.0)
     with pytest.raises(fdtd.FdtdError):
         fdtd.coefficients([inf], [0.0], 1e-3, 1e-3, 1e-3, 1.5e-12)      # eps_r must be finite
+
+
+def test_tile_stats_rejects_null():
+    import ctypes as C
+    a, b = C.c_longlong(), C.c_longlong()
+    assert fdtd.lib().fdtd_tile_stats(None, C.byref(a), C.byref(b)) == fdtd.EINVAL

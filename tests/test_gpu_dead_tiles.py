@@ -150,3 +150,23 @@ def test_dead_tiles_across_checkpoint():
         s.close()
     _assert_same(f, fo, "fields")
     _assert_same(p, po[12:], "probes")
+
+
+def test_tile_stats_show_the_skip():
+    """fdtd_tile_stats: with the skip on, a conductor shell run from zero
+    fields dispatches fewer workgroups than its full tilings hold; with the
+    skip off, exactly as many."""
+    wl = shell(n_steps=40)
+    out = {}
+    for skip in (True, False):
+        s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+        try:
+            s.set_zero_skip(skip)
+            assert s.tile_stats() == (0, 0)
+            s.step(40)
+            out[skip] = s.tile_stats()
+        finally:
+            s.close()
+    run, full = out[True]
+    assert 0 < run < 0.8 * full
+    assert out[False][0] == out[False][1] > 0
