@@ -1,16 +1,20 @@
 """Benchmark of the Yee FDTD hot path on one MI355X.
 
-Workload: the 256^3 dielectric-scatterer cavity (16-entry material table,
-40 seeded spheres, Ez soft source at the centre, 16 probes), FP32 storage,
-fused kernel with T steps per HBM pass.  A "step" is one leapfrog time step
-of the whole grid (H and E half-steps with materials, PEC walls, source,
-probes); --steps K steps are timed with HIP events on the solver's stream,
-after --warmup W untimed steps.  Inputs are resident in HBM before timing.
+Headline workload: the 512^3 dielectric-scatterer cavity (16-entry material
+table, 200 seeded spheres, soft sources on Ex, Ey and Ez, 16 probes), FP32
+storage, fused kernel with T steps per HBM pass.  A "step" is one leapfrog
+time step of the whole grid (H and E half-steps with materials, PEC walls,
+sources, probes); --steps K steps are timed with HIP events on the solver's
+stream, after --warmup W untimed steps, --repeats R times, and the median is
+reported.  Inputs are resident in HBM before timing.
 
 Prints one JSON line: G cell-updates/s, the HBM roofline fraction of the
 dominant kernel at B_alg = 49 B per cell-update (no temporal reuse counted),
-the FP16-storage rate beside it, p50/p99 per-solve latency, and the CPU
-oracle timed on the host cores.
+the FP16/BF16-storage rates beside it -- on the headline grid and on the two
+precision grids (512^3 and 1024x512x256), each with its relative L2 error
+against the FP64 oracle after a stated number of steps from zero fields --
+p50/p99 per-solve latency, the serving run, and the CPU oracle timed on the
+host cores.
 """
 import argparse
 import hashlib
@@ -65,6 +69,26 @@ def measured_traffic(workload: str, storage: str, T):
         return None
 
 
+def median_rate(solver, cells, n, reps, torch, stream):
+    """Median G cell-updates/s over `reps` timed runs of n steps, and the
+    per-run rates."""
+    runs = [cells * n / time_steps(solver, n, torch, stream) / 1e9 for _ in range(max(1, reps))]
+    return float(np.median(runs)), runs
+
+
+def rel_l2_chunked(a, b):
+    """||a-b||_2/||b||_2 over all six components, FP64 accumulation (b is the
+    FP64 reference), one z-slab at a time to bound host memory."""
+    num = den = 0.0
+    for c in range(a.shape[0]):
+        for k0 in range(0, a.shape[1], 64):
+            x = a[c, k0:k0 + 64].astype(np.float64)
+            y = b[c, k0:k0 + 64]
+            num += float(np.sum((x - y) ** 2))
+            den += float(np.sum(y * y))
+    return float(np.sqrt(num / den)) if den > 0 else float("nan")
+
+
 def time_steps(solver, n, torch, stream):
     solver.synchronize()
     torch.cuda.synchronize()
@@ -78,10 +102,13 @@ def time_steps(solver, n, torch, stream):
     return ev0.elapsed_time(ev1) / 1e3
 
 
-def launches_for(steps_done, n, T):
+def launches_for(steps_done, n, T, storage):
+    """Fused launches of one fdtd_step(n) call from step `steps_done`: full
+    blocks from the current step for FP32 storage, blocks ending at absolute
+    multiples of T for 16-bit storage."""
     c, s = 0, steps_done
     while n > 0:
-        ln = min(T - s % T, n)
+        ln = min(T if storage == "fp32" else T - s % T, n)
         s += ln
         n -= ln
         c += 1
@@ -145,23 +172,70 @@ def serving_leg(rate, n, torch):
     return out
 
 
+WORKLOADS = ("spheres512", "spheres256", "precision512", "precision1024", "cavity402", "sphere402",
+             "graded256", "open256")
+
+
+def make_workload(W, name, storage):
+    return {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402,
+            "sphere402": W.sphere402, "graded256": W.graded256, "open256": W.open256,
+            "precision512": lambda: W.precision512(storage), "precision1024": lambda: W.precision1024(storage)}[name]()
+
+
+class Fp64Reference:
+    """FP64 oracle states of the precision grids after `steps` steps from zero
+    fields, computed on the host cores in a background thread while the GPU
+    legs run (the oracle's C loops release the interpreter lock)."""
+
+    def __init__(self, W, names, steps):
+        import threading
+        import oracle
+        self.steps = steps
+        self.out, self.secs, self.err = {}, {}, None
+        self.threads = max(1, oracle.threads() - 2)      # leave cores to the launching thread
+
+        def work():
+            try:
+                oracle.set_threads(self.threads)         # this thread's own OpenMP setting
+                for name in names:
+                    wl = make_workload(W, name, W.FP16)
+                    prob = oracle.Problem.from_workload(wl)
+                    f = oracle.zero_fields(wl.nx, wl.ny, wl.nz)
+                    t0 = time.perf_counter()
+                    prob.run_f64(f, 0, steps)
+                    self.secs[name] = time.perf_counter() - t0
+                    self.out[name] = f
+            except Exception as e:          # reported by get()
+                self.err = e
+        self._t = threading.Thread(target=work, daemon=True)
+        self._t.start()
+
+    def get(self, name):
+        self._t.join()
+        if self.err is not None:
+            raise self.err
+        return self.out[name]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--repeats", type=int, default=5, help="timed runs of --steps steps; the median is reported")
     ap.add_argument("--T", type=int, default=4, help="steps per HBM pass of the fused kernel (1..6)")
-    ap.add_argument("--workload", default="spheres256",
-                    choices=["spheres256", "spheres512", "cavity402", "sphere402", "graded256", "open256"])
+    ap.add_argument("--workload", default="spheres512", choices=WORKLOADS)
     ap.add_argument("--kernel", default="fused", choices=["fused", "plain"],
                     help="kernel family of the timed run (open256's CPML layers need plain)")
     ap.add_argument("--tiling", type=int, default=0, help="fused-kernel tile variant (0 = auto, 1..3)")
     ap.add_argument("--zchunk", type=int, default=0, help="planes per z chunk (0 = automatic)")
     ap.add_argument("--solves", type=int, default=5, help="full solves for the latency percentiles")
+    ap.add_argument("--error-steps", type=int, default=100,
+                    help="steps from zero fields after which the 16-bit forms are compared with the FP64 oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the FP16 and latency measurements")
+    ap.add_argument("--no-extras", action="store_true", help="skip every leg but the timed one")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"],
-                    help="storage of the timed run (the JSON line reports fp32)")
+                    help="storage of the timed run")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the 256-request serving workload (Poisson arrivals, mixed FP32/FP16)")
     ap.add_argument("--serving-rate", type=float, default=SERVING_RATE,
@@ -191,18 +265,18 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    wl = {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402,
-          "sphere402": W.sphere402, "graded256": W.graded256, "open256": W.open256}[args.workload]()
+    storage = {"fp32": W.FP32, "fp16": W.FP16, "bf16": W.BF16}[args.storage]
+    wl = make_workload(W, args.workload, storage)
     cells = wl.cells
     T = args.T
+    reps = args.repeats
     plain = args.kernel == "plain"
     if wl.cpml and not plain:
         print("bench.py: CPML layers run on the plain kernels; pass --kernel plain", file=sys.stderr)
         sys.exit(2)
 
-    print(f"[bench] workload {wl.name} {wl.nx}x{wl.ny}x{wl.nz}, T={T}, warmup {args.warmup}, "
-          f"steps {args.steps}", file=sys.stderr, flush=True)
-    storage = {"fp32": W.FP32, "fp16": W.FP16, "bf16": W.BF16}[args.storage]
+    print(f"[bench] workload {wl.name} {wl.nx}x{wl.ny}x{wl.nz}, {args.storage}, T={T}, warmup {args.warmup}, "
+          f"{reps} x {args.steps} steps", file=sys.stderr, flush=True)
     # One-time library start-up outside the timed region, whatever --warmup
     # says: a small solver with the same kernel, storage, T and tile shape
     # loads the code object and sizes the launch (occupancy query) once.
@@ -222,18 +296,25 @@ def main():
     if args.warmup:
         s.step(args.warmup)
     start = s.steps_done()
-    t = time_steps(s, args.steps, torch, stream)
-    # a plain "launch" is one step's H and E kernel pair
-    launches = args.steps if plain else launches_for(start, args.steps, T)
-    value = cells * args.steps / t / 1e9
+    value, runs = median_rate(s, cells, args.steps, reps, torch, stream)
+    t = cells * args.steps / value / 1e9                     # seconds of the median run
+    # a plain "launch" is one step's H and E kernel pair; every timed run
+    # starts at a multiple of --steps past the warm-up
+    launches = args.steps if plain else launches_for(start, args.steps, T, args.storage)
     b_alg = roofline.algorithmic_bytes(4 if storage == W.FP32 else 2)
     achieved = b_alg * cells * args.steps / t / 1e9          # GB/s, algorithmic
     traffic = measured_traffic(wl.name, args.storage, "plain" if plain else T)
-    print(f"[bench] {args.storage}: {value:.2f} G cell-updates/s, {t * 1e3 / launches:.3f} ms per launch",
+    print(f"[bench] {args.storage}: {value:.2f} G cell-updates/s (median of {reps}: "
+          f"{', '.join(f'{r:.1f}' for r in runs)}), {t * 1e3 / launches:.3f} ms per launch",
           file=sys.stderr, flush=True)
 
-    extras = {}
+    extras = {"runs_G": runs}
     if not args.no_extras:
+        # FP64 references of the precision grids, computed on the host while
+        # the GPU legs below run
+        prec_names = ("precision512", "precision1024")
+        ref64 = Fp64Reference(W, prec_names, args.error_steps) if args.error_steps > 0 else None
+
         # FP64 diagnostics (energy, div E, div H, max |value|) of the final
         # state, outside the timed region: cost per call, and its share of a
         # run that asks for them every 250 steps
@@ -249,52 +330,98 @@ def main():
         s.close()
 
         # per-solve latency: full solves of the workload (a fresh solver each,
-        # so its source runs from step 0), from zero fields resident in HBM
-        def solve_ms(skip):
-            sx = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=T)
+        # so its sources run from step 0), from zero fields resident in HBM
+        def solve_ms(w, skip, st=storage, tb=T):
+            sx = fdtd.Solver.from_workload(w, storage=st, kernel=fdtd.KERNEL_FUSED, time_block=tb)
             try:
                 sx.set_zero_skip(skip)
-                return time_steps(sx, wl.n_steps, torch, stream) * 1e3
+                return time_steps(sx, w.n_steps, torch, stream) * 1e3
             finally:
                 sx.close()
-        lat = [solve_ms(True) for _ in range(args.solves)]
-        lat0 = [solve_ms(False) for _ in range(max(1, args.solves // 2))]
-        extras["latency_ms"] = {"solve": f"{wl.n_steps} steps from zero fields", "p50": float(np.percentile(lat, 50)),
+        lat = [solve_ms(wl, True) for _ in range(args.solves)]
+        lat0 = [solve_ms(wl, False) for _ in range(max(1, args.solves // 2))]
+        extras["latency_ms"] = {"solve": f"{wl.n_steps} steps of {wl.name} from zero fields",
+                                "p50": float(np.percentile(lat, 50)),
                                 "p99": float(np.percentile(lat, 99)), "n": len(lat),
                                 "p50_without_zero_skip": float(np.percentile(lat0, 50))}
 
-        def rate(st, tb):
-            """G cell-updates/s of the fused kernel for storage st at time block tb."""
-            sx = fdtd.Solver.from_workload(wl, storage=st, kernel=fdtd.KERNEL_FUSED, time_block=tb)
+        def rate(w, st, tb):
+            """Median G cell-updates/s of the fused kernel on workload w, storage
+            st, time block tb, full launches as in the timed leg."""
+            sx = fdtd.Solver.from_workload(w, storage=st, kernel=fdtd.KERNEL_FUSED, time_block=tb)
             try:
-                sx.set_zero_skip(False)             # full launches, as in the timed leg
+                sx.set_zero_skip(False)
                 if args.warmup:
                     sx.step(args.warmup)
-                return cells * args.steps / time_steps(sx, args.steps, torch, stream) / 1e9
+                return median_rate(sx, w.cells, args.steps, reps, torch, stream)[0]
             finally:
                 sx.close()
 
-        # 16-bit storage, each at its fastest T (FP32 storage is compute-bound
-        # at T=4, 16-bit storage at T=3), and at matched T (4, and 1 where
-        # both forms are bandwidth-bound)
+        # 16-bit storage on the headline grid, each at its fastest T (FP32
+        # storage is compute-bound at T=4, 16-bit storage at T=3), and at
+        # matched T (4, and 1 where both forms are bandwidth-bound)
         t16 = serve.DEFAULT_T[W.FP16]
-        v16 = rate(W.FP16, t16)
-        v16_4 = rate(W.FP16, 4) if t16 != 4 else v16
-        v32_1, v16_1 = rate(W.FP32, 1), rate(W.FP16, 1)
-        vbf = rate(W.BF16, serve.DEFAULT_T[W.BF16])
+        v16 = rate(wl, W.FP16, t16)
+        v16_4 = rate(wl, W.FP16, 4) if t16 != 4 else v16
+        v32_1, v16_1 = rate(wl, W.FP32, 1), rate(wl, W.FP16, 1)
+        vbf = rate(wl, W.BF16, serve.DEFAULT_T[W.BF16])
         extras["fp16_store"] = {"value": v16, "T": t16, "ratio_vs_fp32": v16 / value,
+                                "target_ratio": 1.7,
                                 "roofline_frac": roofline.algorithmic_bytes(2) * v16 / roofline.HBM_PEAK_GBPS,
                                 "matched_T": {"T4": {"fp32": value, "fp16": v16_4, "ratio": v16_4 / value},
-                                              "T1": {"fp32": v32_1, "fp16": v16_1, "ratio": v16_1 / v32_1}}}
-        extras["fp16_store"]["traffic"] = measured_traffic(wl.name, "fp16", t16)
+                                              "T1": {"fp32": v32_1, "fp16": v16_1, "ratio": v16_1 / v32_1}},
+                                "traffic": measured_traffic(wl.name, "fp16", t16)}
         extras["bf16_store"] = {"value": vbf, "T": serve.DEFAULT_T[W.BF16], "ratio_vs_fp32": vbf / value}
         print(f"[bench] fp16 (T={t16}): {v16:.2f} G cell-updates/s, x{v16 / value:.2f}; matched T=4 "
               f"x{v16_4 / value:.2f}, T=1 x{v16_1 / v32_1:.2f}; bf16 {vbf:.2f}", file=sys.stderr, flush=True)
+
+        # the precision grids: 512^3 and 1024x512x256 (200 spheres, three
+        # sources), FP16 and BF16 storage at T=3: rate, roofline fraction at
+        # 25 B per cell-update, and relative L2 against the FP64 oracle after
+        # --error-steps steps from zero fields (FP32 storage beside them)
+        prec = {}
+        for name in prec_names:
+            entry = {}
+            for fname, st, tb in (("fp16", W.FP16, t16), ("bf16", W.BF16, serve.DEFAULT_T[W.BF16]),
+                                  ("fp32", W.FP32, T)):
+                w = make_workload(W, name, st)
+                e = {"T": tb}
+                if fname != "fp32":
+                    v = rate(w, st, tb)
+                    e.update({"value": v, "roofline_frac": roofline.algorithmic_bytes(2) * v / roofline.HBM_PEAK_GBPS})
+                if ref64 is not None:
+                    sx = fdtd.Solver.from_workload(w, storage=st, kernel=fdtd.KERNEL_FUSED, time_block=tb)
+                    try:
+                        sx.step(args.error_steps)
+                        got = sx.read_fields()
+                    finally:
+                        sx.close()
+                    e["rel_l2_vs_fp64"] = rel_l2_chunked(got, ref64.get(name))
+                    del got
+                entry[fname] = e
+            entry.update({"grid": [w.nx, w.ny, w.nz], "error_after_steps": args.error_steps,
+                          "error_from": "zero fields, three Gaussian-modulated soft sources",
+                          "oracle_fp64_s": ref64.secs.get(name) if ref64 else None,
+                          "oracle_threads": ref64.threads if ref64 else None})
+            prec[name] = entry
+            print(f"[bench] {name}: fp16 {entry['fp16']['value']:.1f} G/s rel-L2 "
+                  f"{entry['fp16'].get('rel_l2_vs_fp64', float('nan')):.2e}, bf16 {entry['bf16']['value']:.1f} G/s "
+                  f"rel-L2 {entry['bf16'].get('rel_l2_vs_fp64', float('nan')):.2e}, fp32 rel-L2 "
+                  f"{entry['fp32'].get('rel_l2_vs_fp64', float('nan')):.2e}", file=sys.stderr, flush=True)
+        if ref64 is not None:
+            ref64.out.clear()
+        extras["precision"] = prec
+
+        # the 256^3 grid of 40 spheres and one source, FP32 T=4 and FP16 T=3
+        w256 = W.spheres256()
+        extras["spheres256"] = {"fp32": {"value": rate(w256, W.FP32, 4), "T": 4},
+                                "fp16": {"value": rate(w256, W.FP16, t16), "T": t16}}
         # deeper step gathering, T = 5 and 6: past the register file (slower),
         # but 16-bit storage is re-encoded less often
-        extras["deep_blocks"] = {f: {f"T{tb}": rate(st, tb) for tb in (5, 6)}
+        extras["deep_blocks"] = {f: {f"T{tb}": rate(wl, st, tb) for tb in (5, 6)}
                                  for f, st in (("fp32", W.FP32), ("fp16", W.FP16))}
-        print(f"[bench] deep blocks: {extras['deep_blocks']}", file=sys.stderr, flush=True)
+        print(f"[bench] 256^3: {extras['spheres256']}; deep blocks: {extras['deep_blocks']}",
+              file=sys.stderr, flush=True)
         # graded cell sizes (per-index coefficient arrays), FP32, automatic T and tile shape
         wg = W.graded256()
 
@@ -304,12 +431,12 @@ def main():
                 sg.set_zero_skip(False)
                 if args.warmup:
                     sg.step(args.warmup)
-                return wg.cells * args.steps / time_steps(sg, args.steps, torch, stream) / 1e9
+                return median_rate(sg, wg.cells, args.steps, reps, torch, stream)[0]
             finally:
                 sg.close()
         vg, vg16 = graded_rate(W.FP32), graded_rate(W.FP16)
         extras["graded_spacing"] = {"workload": wg.name, "value": vg, "unit": "G cell-updates/s",
-                                    "ratio_vs_uniform": vg / value, "T": 3,
+                                    "ratio_vs_spheres256": vg / extras["spheres256"]["fp32"]["value"], "T": 3,
                                     "traffic": measured_traffic(wg.name, "fp32", 3), "fp16": vg16}
         print(f"[bench] graded spacing ({wg.name}): {vg:.2f} G cell-updates/s, FP16 storage {vg16:.2f}",
               file=sys.stderr, flush=True)
@@ -320,11 +447,11 @@ def main():
             try:
                 n = max(1, args.steps // 5)
                 sp.step(10)
-                return w.cells * n / time_steps(sp, n, torch, stream) / 1e9
+                return median_rate(sp, w.cells, n, reps, torch, stream)[0]
             finally:
                 sp.close()
         vo = plain_rate(W.open256())
-        vp = plain_rate(wl)
+        vp = plain_rate(w256)
         extras["cpml"] = {"workload": "open256", "value": vo, "unit": "G cell-updates/s", "kernel": "plain",
                           "plain_without_layers": vp, "layer": W.CPML_LAYER,
                           "traffic_per_step": measured_traffic("open256", "fp32", "plain")}
@@ -334,18 +461,18 @@ def main():
         # host initial state, the solve, read-back of fields and probes
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sx = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=T)
-        sx.set_fields(np.zeros((6, wl.nz + 1, wl.ny + 1, wl.nx + 1), np.float32))
-        sx.step(wl.n_steps)
+        sx = fdtd.Solver.from_workload(w256, kernel=fdtd.KERNEL_FUSED, time_block=4)
+        sx.set_fields(np.zeros((6, w256.nz + 1, w256.ny + 1, w256.nx + 1), np.float32))
+        sx.step(w256.n_steps)
         sx.read_fields()
-        sx.read_probes(0, wl.n_steps)
+        sx.read_probes(0, w256.n_steps)
         sx.close()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        extras["pcie_inclusive"] = {"value": cells * wl.n_steps / dt / 1e9, "unit": "G cell-updates/s",
+        extras["pcie_inclusive"] = {"value": w256.cells * w256.n_steps / dt / 1e9, "unit": "G cell-updates/s",
                                     "wall_ms": dt * 1e3,
-                                    "what": f"create + set_fields(host) + {wl.n_steps} steps + read_fields + "
-                                            f"read_probes, FP32 T={T}"}
+                                    "what": f"spheres256: create + set_fields(host) + {w256.n_steps} steps + "
+                                            f"read_fields + read_probes, FP32 T=4"}
         # the paper's case S: a 400-cell perfect-conductor sphere in 402^3, a
         # 1300-step solve from zero fields, with the conductor interior's
         # tiles skipped and without (rates count every cell, as the paper does)
@@ -394,13 +521,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "fp16": "f32 math, f16 storage", "bf16": "f32 math, bf16 storage"}[args.storage],
         "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "storage": args.storage,
                    "kernel": args.kernel, "T": None if plain else T, "materials": len(wl.eps_r),
-                   "spheres": {"spheres256": 40, "spheres512": 200, "graded256": 40, "open256": 40}.get(wl.name, 0),
-                   "sources": len(wl.sources),
-                   "probes": len(wl.probes), "zero_skip": False, "parallelism": "single-gpu"},
+                   "spheres": {"spheres256": 40, "spheres512": 200, "precision512": 200, "precision1024x512x256": 200,
+                               "graded256": 40, "open256": 40}.get(wl.name, 0),
+                   "sources": len(wl.sources), "probes": len(wl.probes), "zero_skip": False,
+                   "repeats": reps, "statistic": "median", "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": roofline.HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / roofline.HBM_PEAK_GBPS,
                      "traffic": traffic,

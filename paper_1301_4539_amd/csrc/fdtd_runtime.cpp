@@ -3,8 +3,9 @@
 // Responsibilities: argument validation, coefficient precompute (FP64,
 // rounded once to FP32), device workspace layout, upload/readback of fields
 // (with the reduced-storage codec), source/probe tables, and the step
-// scheduler, which cuts fdtd_step(n) into blocks of at most T steps ending at
-// absolute step counts that are multiples of T (a pin-point output never
+// scheduler, which cuts fdtd_step(n) into blocks of at most T steps -- full
+// blocks from the current step with FP32 storage, blocks ending at absolute
+// step counts that are multiples of T with 16-bit storage (a pin-point output never
 // forces an extra block: probes are recorded inside the kernels, the GPU
 // counterpart of Sec. 3.4's advice not to start a multi-step block the step
 // before an output is needed).
@@ -605,10 +606,14 @@ int read_ctrl(fdtd_solver *s, yee::Ctrl *out)
     return e ? hip_fail(e, "hipMemcpy(ctrl)") : FDTD_OK;
 }
 
-// Length of the next block: blocks end at absolute multiples of T.
+// Length of the next block.  With FP32 storage the result does not depend on
+// where blocks fall, so full blocks of T are packed from the current step;
+// 16-bit storage re-encodes at every block end, so its blocks end at absolute
+// multiples of T (a run split over several calls then rounds where one call
+// would).
 int next_block(const fdtd_solver *s, int left)
 {
-    const int len = s->T - (int)(s->steps % s->T);
+    const int len = s->storage == FDTD_FP32 ? s->T : s->T - (int)(s->steps % s->T);
     return std::min(len, left);
 }
 
@@ -1645,9 +1650,18 @@ int fdtd_load_state(fdtd_solver *s, const void *host_src, size_t bytes)
         (e = hipMemsetAsync(s->fbuf[1], 0, s->d.fbytes, s->st)) ||
         (e = hipMemcpyAsync(s->ctrl, src + sizeof(h) + s->d.fbytes, sizeof(yee::Ctrl), hipMemcpyHostToDevice, s->st)) ||
         (s->psi_bytes && (e = hipMemcpyAsync(s->psi_d, src + sizeof(h) + s->d.fbytes + sizeof(yee::Ctrl), s->psi_bytes,
-                                             hipMemcpyHostToDevice, s->st))) ||
-        (e = hipStreamSynchronize(s->st)))
+                                             hipMemcpyHostToDevice, s->st))))
         return hip_fail(e, "load state");
+    // Probe rows from the restored step on start again at 0: a tile that the
+    // zero-tile skip or the dead-tile list leaves out never writes its probes'
+    // rows, which must then read 0, not what a later history wrote there.
+    if (s->probe_out_d && s->probe_cap > h.steps) {
+        const size_t np = s->probe_pos.size();
+        if ((e = hipMemsetAsync(s->probe_out_d + (size_t)h.steps * np, 0,
+                                (size_t)(s->probe_cap - h.steps) * np * sizeof(double), s->st)))
+            return hip_fail(e, "load state");
+    }
+    if ((e = hipStreamSynchronize(s->st))) return hip_fail(e, "load state");
     s->cur = 0;
     s->steps = h.steps;
     s->block = h.block;

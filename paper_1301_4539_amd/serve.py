@@ -71,12 +71,21 @@ class Engine:
     """Continuous batching.  Every tick advances each admitted solve by
     `chunk` steps, or by a multiple of it for solves that have waited long:
     k = ceil(age / age_step) chunks, at most `max_boost` (age from arrival).
-    Multiples of the chunk keep every solve's blocks where a solo run puts
-    them; the boost bounds the tail latency of long solves."""
+    A 16-bit solve re-encodes its fields at the end of every block, and its
+    blocks end at absolute multiples of its T, so a chunk that is a multiple
+    of every T the backend runs (`backend.block_lengths()`) keeps each
+    solve's blocks, and so its result, where a solo run puts them; the
+    default 48 is a multiple of 1, 2, 3 and 4.  The boost bounds the tail
+    latency of long solves."""
 
-    def __init__(self, backend, budget_bytes: int = 24 << 30, max_slots: int = 64, chunk: int = 64,
+    def __init__(self, backend, budget_bytes: int = 24 << 30, max_slots: int = 64, chunk: int = 48,
                  age_step: float = 0.5, max_boost: int = 3):
         assert chunk > 0 and max_boost >= 1 and age_step > 0
+        lens = backend.block_lengths() if hasattr(backend, "block_lengths") else ()
+        bad = [t for t in lens if chunk % t]
+        if bad:
+            raise ValueError(f"chunk {chunk} is not a multiple of the block lengths {sorted(set(bad))}: "
+                             f"16-bit solves would round differently in the mix than alone")
         self.b = backend
         self.budget = budget_bytes
         self.max_slots = max_slots
@@ -171,6 +180,11 @@ class GpuBackend:
         tb = DEFAULT_T if time_block is None else time_block
         self.T = dict(tb) if isinstance(tb, dict) else {k: int(tb) for k in DEFAULT_T}
         self.alone = set()      # solves fdtd_step_batch does not take: stepped one by one
+
+    def block_lengths(self):
+        """Every block length T a solve may run: the per-storage T of the
+        batched solves and 1..4, the automatic T of graded-spacing solves."""
+        return sorted(set(self.T.values()) | {1, 2, 3, 4})
 
     def solver_options(self, wl):
         """(kernel, T, batched) for a request: uniform grids run the fused

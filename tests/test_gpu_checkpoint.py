@@ -79,3 +79,33 @@ def test_state_does_not_load_into_another_configuration():
         a.close()
         b.close()
         c.close()
+
+
+def test_rewind_clears_probe_rows_written_by_a_later_history():
+    """Save at step 10 of a run from zero fields, perturb the whole state and
+    step on (every probe row from 10 on gets a nonzero value), then restore
+    the step-10 state and step again with the zero-tile skip on: probes in
+    tiles the field has not reached are never written by the replayed run,
+    so their rows must read 0 again -- the oracle's record of the same run."""
+    from tests.test_gpu_zero_skip import spreading
+    wl = spreading(n_steps=40)
+    print("checkpoint rewind over written probe rows, 200x120x150, skip on", flush=True)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    try:
+        s.set_zero_skip(True)
+        s.step(10)
+        state = s.save_state()
+        rng = np.random.default_rng(77)
+        s.set_fields(rng.standard_normal((6, wl.nz + 1, wl.ny + 1, wl.nx + 1)).astype(np.float32))
+        s.step(30)
+        s.synchronize()
+        assert np.count_nonzero(s.read_probes(10, 30)) == 30 * len(wl.probes)
+        s.load_state(state)
+        s.step(30)
+        f, p = s.read_fields(), s.read_probes(0, 40)
+    finally:
+        s.close()
+    fo, po = G.oracle_f32(wl, 40)
+    assert np.count_nonzero(po[39] == 0.0) > 0          # some probes are still out of the field's reach
+    _assert_same(f, fo, "fields")
+    _assert_same(p, po, "probes")

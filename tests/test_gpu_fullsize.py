@@ -48,19 +48,24 @@ def test_fullsize_fp32_short_run_bitexact(name):
         s.close()
 
 
+@pytest.mark.parametrize("T", [3, 4])
 @pytest.mark.parametrize("fmt", [W.FP16, W.BF16])
 @pytest.mark.parametrize("grid", ["512", "1024x512x256"])
-def test_fullsize_reduced_storage_bitexact_with_emulation(fmt, grid):
-    wl = W.precision512(fmt, n_steps=4) if grid == "512" else W.precision1024(fmt, n_steps=4)
+def test_fullsize_reduced_storage_bitexact_with_emulation(fmt, grid, T):
+    """T=3 is the 16-bit default (what the bench times), T=4 the FP32 one;
+    two blocks at T=3 so that the second block runs on the first one's scales."""
+    steps = 2 * T if T == 3 else T
+    wl = W.precision512(fmt, n_steps=steps) if grid == "512" else W.precision1024(fmt, n_steps=steps)
     init = _random_init(wl, 12)
-    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    print(f"fullsize {grid} fmt={fmt} T={T} steps={steps}", flush=True)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=T)
     try:
         s.set_fields(init)
-        s.step(4)
+        s.step(steps)
         prob = oracle.Problem.from_workload(wl)
         ref = init.copy()
         st = prob.quantize_upload(ref, fmt)
-        prob.run_q(ref, 0, 4, fmt, 4, st)
+        prob.run_q(ref, 0, steps, fmt, T, st)
         scales, sat = s.storage_state()
         assert scales == list(st["scales"]) and not sat
         for c in range(6):

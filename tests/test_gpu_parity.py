@@ -141,6 +141,37 @@ def test_step_splitting_and_kernel_variants_identical():
         _assert_same(p, pref, f"probes T={T}")
 
 
+@pytest.mark.parametrize("T", [3, 4])
+def test_fp32_blocks_packed_from_the_current_step(T):
+    """FP32 storage packs full T-step blocks from wherever a call starts (its
+    results do not depend on where blocks fall): after 5 steps, 20 more run
+    as ceil(20 / T) launches, not ending at absolute multiples of T, and the
+    run at odd offsets stays bit-exact with the oracle."""
+    wl = ragged(n_steps=37)
+    one = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=T)
+    try:
+        one.set_zero_skip(False)
+        one.step(T)
+        full_T = one.tile_stats()[1]          # tiles of one full-block launch
+    finally:
+        one.close()
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=T)
+    try:
+        s.set_zero_skip(False)
+        s.step(5)
+        before = s.tile_stats()[1]
+        s.step(4 * T)
+        assert s.tile_stats()[1] - before == 4 * full_T      # four full blocks from step 5
+        s.step(37 - 5 - 4 * T)
+        s.synchronize()
+        f, p = s.read_fields(), s.read_probes(0, 37)
+    finally:
+        s.close()
+    fo, po = G.oracle_f32(wl, 37)
+    _assert_same(f, fo, f"fields T={T}")
+    _assert_same(p, po, f"probes T={T}")
+
+
 def test_probes_equal_field_reads():
     wl = ragged(n_steps=20)
     s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=3)

@@ -139,3 +139,57 @@ def test_fp32_op_order_by_exact_fma():
                 dhy = np.float32(g[4, k, j, i] - g[4, k - 1, j, i])
                 t = np.float32(cfm[0] * g[0, k, j, i])
                 assert h[0, k, j, i] == fma(-cfm[3], dhy, fma(cfm[2], dhz, t))
+
+
+def test_fp32_op_order_by_exact_fma_all_components():
+    """Every component follows the stated order: H = fmaf(-ch_b, d_b, fmaf(ch_a,
+    d_a, H)) and E = fmaf(-Cb_b, d_b, fmaf(Cb_a, d_a, Ca E)), with (a, b) =
+    (z, y) for x, (x, z) for y and (y, x) for z (the printed hx loop's term
+    order, permuted cyclically; Sec. 2.1-2.2).  The swapped order differs
+    from the oracle somewhere, so the check can tell the two apart."""
+    n, d = (4, 3, 5), (1e-3, 1.2e-3, 0.9e-3)
+    nx, ny, nz = n
+    dt = W.courant_dt(*d)
+    rng = np.random.default_rng(12)
+    eps = np.array([1.0, 3.7, 9.1]); sig = np.array([0.0, 0.03, 0.011])
+    mat = rng.integers(0, 3, size=(nz, ny, nx)).astype(np.uint8)
+    prob = oracle.Problem(*n, *d, dt, eps, sig, mat)
+    f = rng.standard_normal((6, nz + 1, ny + 1, nx + 1)).astype(np.float32)
+    g = f.copy()
+    prob.h_half_f32(g)
+    chx, chy, chz = prob.ch32
+    fma = cf.exact_fma32
+    swapped = 0
+    for k in range(nz + 1):
+        for j in range(ny + 1):
+            for i in range(nx + 1):
+                if i < nx and k < nz:          # Hy: z term (Ex), then x term (Ez)
+                    dez_x = np.float32(f[2, k, j, i + 1] - f[2, k, j, i])
+                    dex_z = np.float32(f[0, k + 1, j, i] - f[0, k, j, i])
+                    assert g[4, k, j, i] == fma(-chz, dex_z, fma(chx, dez_x, f[4, k, j, i]))
+                    swapped += g[4, k, j, i] != fma(chx, dez_x, fma(-chz, dex_z, f[4, k, j, i]))
+                if i < nx and j < ny:          # Hz: y term (Ex), then x term (Ey)
+                    dex_y = np.float32(f[0, k, j + 1, i] - f[0, k, j, i])
+                    dey_x = np.float32(f[1, k, j, i + 1] - f[1, k, j, i])
+                    assert g[5, k, j, i] == fma(-chx, dey_x, fma(chy, dex_y, f[5, k, j, i]))
+                    swapped += g[5, k, j, i] != fma(chy, dex_y, fma(-chx, dey_x, f[5, k, j, i]))
+    h = g.copy()
+    prob.e_half_f32(h)
+    for k in range(nz + 1):
+        for j in range(ny + 1):
+            for i in range(nx + 1):
+                if 0 < i < nx and j < ny and 0 < k < nz:     # interior Ey
+                    ca, cbx, cby, cbz = prob.coef32[mat[k, j, i]]
+                    dhx_z = np.float32(g[3, k, j, i] - g[3, k - 1, j, i])
+                    dhz_x = np.float32(g[5, k, j, i] - g[5, k, j, i - 1])
+                    t = np.float32(ca * g[1, k, j, i])
+                    assert h[1, k, j, i] == fma(-cbx, dhz_x, fma(cbz, dhx_z, t))
+                    swapped += h[1, k, j, i] != fma(cbz, dhx_z, fma(-cbx, dhz_x, t))
+                if 0 < i < nx and 0 < j < ny and k < nz:     # interior Ez
+                    ca, cbx, cby, cbz = prob.coef32[mat[k, j, i]]
+                    dhy_x = np.float32(g[4, k, j, i] - g[4, k, j, i - 1])
+                    dhx_y = np.float32(g[3, k, j, i] - g[3, k, j - 1, i])
+                    t = np.float32(ca * g[2, k, j, i])
+                    assert h[2, k, j, i] == fma(-cby, dhx_y, fma(cbx, dhy_x, t))
+                    swapped += h[2, k, j, i] != fma(cbx, dhy_x, fma(-cby, dhx_y, t))
+    assert swapped > 0
