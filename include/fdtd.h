@@ -288,8 +288,26 @@ int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst);
  * The steps must have been run.  Synchronises the stream. */
 int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int n_steps);
 
-/* Compute diagnostics of the current state.  Synchronises the stream. */
+/* Compute diagnostics of the current state (fdtd_diag; the energy is the
+ * quantity the leapfrog conserves by the antisymmetry of its two half-steps,
+ * Sec. 2.1).  FDTD_EINVAL with CPML layers.  The first call allocates the
+ * block partials (kept until fdtd_destroy).  Synchronises the stream. */
 int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out);
+
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the
+ * same diagnostics, bit for bit, with the block partials and the reduced
+ * values in a static device array of 4 MiB that the library holds once per
+ * GPU until the process ends, instead of memory allocated per solver.  No
+ * device memory is allocated or freed.  Grids whose diagnostics need more
+ * block partials than the array holds (about 47 000: one per 64 x 4 nodes of
+ * a plane, times min(8, nz+1) plane runs -- e.g. planes up to about
+ * 1500 x 1000 nodes) are rejected with FDTD_EINVAL before any device work.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (several host threads, or solvers on different streams still running)
+ * race and may return each other's values.  Call with the solver's device
+ * current.  Synchronises the stream. */
+int fdtd_diagnostics_noalloc(fdtd_solver *s, fdtd_diag *out);
 
 /* Number of steps enqueued so far. */
 int fdtd_steps_done(const fdtd_solver *s, long long *n);

@@ -1548,17 +1548,15 @@ int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int
     return e ? hip_fail(e, "read probes") : FDTD_OK;
 }
 
-int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
+}  // extern "C"
+
+namespace {
+
+// Diagnostics of the current state with the block partials in `partial`
+// and the 11 reduced values in `dout` (device), copied to *out.
+int run_diagnostics(fdtd_solver *s, double *partial, double *dout, fdtd_diag *out)
 {
-    if (!s || !out) return fail(FDTD_EINVAL, "NULL argument");
-    if (s->pml.n > 0) return fail(FDTD_EINVAL, "diagnostics are not defined with CPML layers");
     hipError_t e;
-    if (!s->diag_part_d) {
-        const size_t nb = (size_t)yee::diag_blocks(s->L);
-        if ((e = hipMalloc(&s->diag_part_d, nb * yee::DIAG_W * sizeof(double))) ||
-            (e = hipMalloc(&s->diag_out_d, yee::DIAG_W * sizeof(double))))
-            return hip_fail(e, "hipMalloc(diagnostics)");
-    }
     yee::DiagArgs a;
     a.L = s->L;
     a.f = s->fbuf[s->cur];
@@ -1570,11 +1568,11 @@ int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
     a.idx = 1.0 / s->dx; a.idy = 1.0 / s->dy; a.idz = 1.0 / s->dz;
     a.gc = s->gc_d;
     a.gsz = s->gsz_d;
-    a.partial = s->diag_part_d;
+    a.partial = partial;
     a.sb = storage_block(s);
-    if ((e = yee::launch_diag(s->storage, a, s->diag_out_d, s->st))) return hip_fail(e, "diagnostics");
+    if ((e = yee::launch_diag(s->storage, a, dout, s->st))) return hip_fail(e, "diagnostics");
     double v[yee::DIAG_W];
-    e = hipMemcpyAsync(v, s->diag_out_d, sizeof(v), hipMemcpyDeviceToHost, s->st);
+    e = hipMemcpyAsync(v, dout, sizeof(v), hipMemcpyDeviceToHost, s->st);
     if (!e) e = hipStreamSynchronize(s->st);
     if (e) return hip_fail(e, "diagnostics");
     out->energy = v[0];
@@ -1584,6 +1582,37 @@ int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
     out->div_h_max = v[4];
     for (int c = 0; c < 6; ++c) out->max_abs[c] = v[5 + c];
     return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
+{
+    if (!s || !out) return fail(FDTD_EINVAL, "NULL argument");
+    if (s->pml.n > 0) return fail(FDTD_EINVAL, "diagnostics are not defined with CPML layers");
+    hipError_t e;
+    if (!s->diag_part_d) {
+        const size_t nb = (size_t)yee::diag_blocks(s->L);
+        if ((e = hipMalloc(&s->diag_part_d, nb * yee::DIAG_W * sizeof(double))) ||
+            (e = hipMalloc(&s->diag_out_d, yee::DIAG_W * sizeof(double))))
+            return hip_fail(e, "hipMalloc(diagnostics)");
+    }
+    return run_diagnostics(s, s->diag_part_d, s->diag_out_d, out);
+}
+
+int fdtd_diagnostics_noalloc(fdtd_solver *s, fdtd_diag *out)
+{
+    if (!s || !out) return fail(FDTD_EINVAL, "NULL argument");
+    if (s->pml.n > 0) return fail(FDTD_EINVAL, "diagnostics are not defined with CPML layers");
+    const long long nb = yee::diag_blocks(s->L);
+    if (nb > yee::diag_static_max_blocks())
+        return fail(FDTD_EINVAL, "grid needs " + std::to_string(nb) + " diagnostics partials; the static scratch holds " +
+                                     std::to_string(yee::diag_static_max_blocks()) + " (use fdtd_diagnostics)");
+    double *dout = nullptr, *partial = nullptr;
+    if (hipError_t e = yee::diag_static_scratch(&dout, &partial)) return hip_fail(e, "diagnostics scratch");
+    return run_diagnostics(s, partial, dout, out);
 }
 
 // Saved state: a header, the current field buffer as stored on the device,

@@ -19,6 +19,7 @@
 // the per-index update factors.
 
 #include <algorithm>
+#include <mutex>
 
 #include "yee_device.hpp"
 #include "yee_internal.hpp"
@@ -176,7 +177,42 @@ hipError_t launch_diag_t(const DiagArgs &a, double *out, hipStream_t st)
     return hipGetLastError();
 }
 
+// Scratch of the diagnostics entry point that allocates nothing: 11 result
+// doubles at the start (padded to 256 bytes), then the per-block partials.
+// One copy per GPU, held until the process ends; host code never names it
+// directly (its host-side name is not a device address) but only through the
+// per-device address that diag_static_scratch() looks up.
+constexpr size_t DIAG_SCRATCH_BYTES = size_t(4) << 20;
+constexpr size_t DIAG_OUT_DOUBLES = 32;   // 256 bytes ahead of the partials
+static __device__ __align__(256) double scratch[DIAG_SCRATCH_BYTES / sizeof(double)];
+
 }  // namespace
+
+long long diag_static_max_blocks()
+{
+    return (long long)((DIAG_SCRATCH_BYTES / sizeof(double) - DIAG_OUT_DOUBLES) / DIAG_W);
+}
+
+hipError_t diag_static_scratch(double **out, double **partial)
+{
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static double *per_dev[MAX_DEV] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!per_dev[dev]) {            // once per device, with that device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        per_dev[dev] = static_cast<double *>(p);
+    }
+    *out = per_dev[dev];
+    *partial = per_dev[dev] + DIAG_OUT_DOUBLES;
+    return hipSuccess;
+}
 
 int diag_blocks(const Layout &L)
 {

@@ -186,5 +186,11 @@ int auto_shape(int storage, int T, bool graded = false);
 int fastest_T(const Layout &L, int storage, bool graded = false);
 hipError_t launch_diag(int storage, const DiagArgs &a, double *out11, hipStream_t st);
 int diag_blocks(const Layout &L);
+// The diagnostics scratch that needs no allocation: a static device array,
+// one per GPU.  Looks up the current device's copy (once per device) and
+// returns where the 11 results and the block partials go; at most
+// diag_static_max_blocks() partials fit.
+hipError_t diag_static_scratch(double **out11, double **partial);
+long long diag_static_max_blocks();
 
 }  // namespace yee

@@ -63,6 +63,7 @@ def lib():
         L.fdtd_read_fields.argtypes = [vp, i, vp]
         L.fdtd_read_probes.argtypes = [vp, vp, ll, i]
         L.fdtd_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
+        L.fdtd_diagnostics_noalloc.argtypes = [vp, C.POINTER(_Diag)]
         L.fdtd_steps_done.argtypes = [vp, C.POINTER(ll)]
         L.fdtd_state_bytes.argtypes = [vp]
         L.fdtd_state_bytes.restype = sz
@@ -82,13 +83,19 @@ def lib():
         L.fdtd_live_nodes.argtypes = [C.POINTER(_Material), i, vp, i, i, i, vp, i, vp]
         L.fdtd_tile_stats.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_zero_skip", "fdtd_set_poison", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
-                     "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_steps_done",
+                     "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_diagnostics_noalloc",
+                     "fdtd_steps_done",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
                      "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
                      "fdtd_load_state", "fdtd_live_nodes", "fdtd_tile_stats"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
+
+
+def _diag_dict(d):
+    return {"energy": d.energy, "div_e_max": d.div_e_max, "div_e_sumsq": d.div_e_sumsq,
+            "div_h_max": d.div_h_max, "div_h_sumsq": d.div_h_sumsq, "max_abs": list(d.max_abs)}
 
 
 def _check(rc):
@@ -283,8 +290,14 @@ class Solver:
     def diagnostics(self) -> dict:
         d = _Diag()
         _check(lib().fdtd_diagnostics(self._h, C.byref(d)))
-        return {"energy": d.energy, "div_e_max": d.div_e_max, "div_e_sumsq": d.div_e_sumsq,
-                "div_h_max": d.div_h_max, "div_h_sumsq": d.div_h_sumsq, "max_abs": list(d.max_abs)}
+        return _diag_dict(d)
+
+    def diagnostics_noalloc(self) -> dict:
+        """The same diagnostics through the entry point that allocates no
+        device memory (a static per-GPU scratch array)."""
+        d = _Diag()
+        _check(lib().fdtd_diagnostics_noalloc(self._h, C.byref(d)))
+        return _diag_dict(d)
 
     def tile_stats(self):
         """(workgroups dispatched, tiles of the full tiling) of the fused
