@@ -230,7 +230,7 @@ def main():
     ap.add_argument("--tiling", type=int, default=0, help="fused-kernel tile variant (0 = auto, 1..3)")
     ap.add_argument("--zchunk", type=int, default=0, help="planes per z chunk (0 = automatic)")
     ap.add_argument("--solves", type=int, default=5, help="full solves for the latency percentiles")
-    ap.add_argument("--error-steps", type=int, default=100,
+    ap.add_argument("--error-steps", type=int, default=250,
                     help="steps from zero fields after which the 16-bit forms are compared with the FP64 oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip every leg but the timed one")

@@ -1402,7 +1402,9 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         const int len = next_block(s, left);
         yee::FusedArgs a;
         fill_fused(s, &a);
-        const int shape = s->tiling > 0 ? s->tiling - 1 : yee::auto_shape(s->storage, len, s->gc_d != nullptr);
+        const int shape = s->tiling > 0 ? s->tiling - 1
+                                        : yee::auto_shape(s->storage, len, s->gc_d != nullptr,
+                                                          (long long)s->L.nx * s->L.ny * s->L.nz);
         if (!yee::fused_fits(s->L, s->storage, len))      // never launch a chunk beyond its addressing
             return fail(FDTD_EINVAL, "grid planes too large for the fused kernel at this T");
         box_take_sources(s);

@@ -43,14 +43,22 @@ hipError_t launch_any(int storage, int T, const FusedArgs *a, int n, bool batch,
 // Fastest tile shape per (storage, T) measured on MI355X with the 256^3 and
 // 512^3 dielectric workloads (shape indices of the fused kernel's tile table:
 // 0 = 2 rows x 16 waves, 1 = 4 x 8, 2 = 3 x 12; 4 x 4, 2 x 8, 2 x 16 for T=1).
-// Graded spacing (FP32) was measured on its own 256^3 workload.
-int auto_shape(int storage, int T, bool graded)
+// With FP32 storage at T = 4 and 5 the 8-wave shape is the faster one on
+// grids of 64 M cells and more (512^3: 250 against 240 G/s at T = 4, 254
+// against 248 at T = 5) and the 16-wave one below (256^3: 216 against 205 at
+// T = 4).  Graded spacing (FP32) was measured on its own 256^3 workload.
+int auto_shape(int storage, int T, bool graded, long long cells)
 {
-    static const int f32[5] = {0, 2, 1, 1, 0};
-    static const int f32g[5] = {0, 0, 1, 0, 2};
-    static const int f16[5] = {0, 2, 0, 0, 0};
-    static const int bf16[5] = {0, 2, 0, 0, 1};
-    if (storage == 0) return graded ? f32g[T] : f32[T];
+    static const int f32[MAX_T + 1] = {0, 2, 1, 1, 0, 0, 0};
+    static const int f32g[MAX_T_GRADED + 1] = {0, 0, 1, 0, 2};
+    static const int f16[MAX_T + 1] = {0, 2, 0, 0, 0, 1, 1};
+    static const int bf16[MAX_T + 1] = {0, 2, 0, 0, 0, 1, 1};
+    if (T < 1 || T > MAX_T || (graded && T > MAX_T_GRADED)) return 0;
+    if (storage == 0) {
+        if (graded) return f32g[T];
+        if ((T == 4 || T == 5) && cells >= (64LL << 20)) return 1;
+        return f32[T];
+    }
     return storage == 1 ? f16[T] : bf16[T];
 }
 

@@ -111,13 +111,20 @@ constexpr int MAX_LOCAL = 256;   // sources / probes per solver
 
 template <int T, int NW>
 struct TileShared {
+    // The exchange rows come first, so that every access is one per-lane base
+    // register plus an immediate offset.
+    // (Hx, Hz) of each wave's last row, in slot w+1, in buffer t % NHB at level
+    // t: consecutive levels, also across z steps, use different buffers, so
+    // one barrier per level orders both the write and the reuse; slot 0 stays
+    // zero.
+    static constexpr int NHB = (T & 1) ? 3 : 2;
+    float2 h[NHB][NW + 1][64];
+    // (Ex, Ez) of each wave's first row, per time level 0..T-1: level t's row
+    // of z step K is written once level t+1 has read step K-1's row (after
+    // that level's barrier) and read by level t+1 in step K+1; slot NW stays
+    // zero.
+    float2 e[T][NW + 1][64];
     float4 coef[256];
-    // (Ex, Ez) of each wave's first row, per time level 0..T-1, double-buffered
-    // by the parity of the z step that wrote it; slot NW stays zero
-    float2 e[2][T][NW + 1][64];
-    // (Hx, Hz) of each wave's last row, in slot w+1, double-buffered by level;
-    // slot 0 stays zero
-    float2 h[2][NW + 1][64];
     int4 src[MAX_LOCAL];     // sources this workgroup computes: (comp, lane, row, plane)
     int srcn[MAX_LOCAL];     // how many of this launch's T steps have a sample
     float srcv[MAX_LOCAL][T];  // those samples, staged so the z march issues no
@@ -173,10 +180,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int q = tid; q < a.n_mat; q += 64 * NW) s_coef[q] = a.coef[q];
     if (tid < 64) {
-        for (int b = 0; b < 2; ++b) {
-            for (int t = 0; t < T; ++t) s_e[b][t][NW][tid] = make_float2(0.0f, 0.0f);
-            s_h[b][0][tid] = make_float2(0.0f, 0.0f);
-        }
+        for (int t = 0; t < T; ++t) s_e[t][NW][tid] = make_float2(0.0f, 0.0f);
+        for (int b = 0; b < TileShared<T, NW>::NHB; ++b) s_h[b][0][tid] = make_float2(0.0f, 0.0f);
     }
 
     float dn[6], up[6];
@@ -246,13 +251,26 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     const int nsrc = sm.nsrc, nprb = sm.nprb;
 
     // lane and row predicates
-    const bool xin = x >= 0 && x <= nx;
-    const bool xlt = x >= 0 && x < nx;
-    const bool xint = x > 0 && x < nx;
+    // Walls.  Values at positions outside their component's range (Hy, Hz
+    // and Ex at x = nx; Hx, Hz and Ey at y = ny) and on lanes and rows beyond
+    // the walls are computed like the rest and never feed a value in range:
+    // every difference that reaches across a wall ends on a tangential E of
+    // that wall, which is held at its stored zero.  So the updates mask only
+    // the walls' tangential E (and the z walls, per plane), and the stores
+    // write zero at the positions outside each component's range.
+    const bool xwall = x == 0 || x == nx;
+    const bool xlt = x < nx;
     const bool xown = lane >= T && lane < T + OX && x <= nx;
     const int xc = min(max(x, 0), nx);
     const int vo = xc * ES;             // per-lane byte offset of the field arrays
-    const int vom = xc;                 // per-lane byte offset of the material index
+    // The material index's per-lane byte offset, xc, is formed from vo at each
+    // load (one shift; the asm keeps the compiler from hoisting it into a
+    // register of its own, one more live value through the whole march).
+    auto mat_offset = [&]() __attribute__((always_inline)) -> int {
+        int m;
+        asm volatile("v_lshrrev_b32 %0, %1, %2" : "=v"(m) : "n"(ES == 4 ? 2 : 1), "v"(vo));
+        return m;
+    };
 
     // buffer resources based at this chunk's first plane
     const long long cs = L.cstride, ks = L.kstride;
@@ -286,8 +304,10 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
 
     float E[T + 1][3][RY], H[T + 1][3][RY];
     // Material indices of the planes the levels are on, one byte per level:
-    // byte t of MP[r] is the index of plane K-t (level t's plane) in row r.
-    using MPack = typename std::conditional<(T >= 4), uint64_t, uint32_t>::type;
+    // byte t-1 of MP[r] is the index of plane K-t (level t's plane) in row r,
+    // for t = 1..T.  The material of plane K-1 is loaded during step K-1 and
+    // shifted in at step K.
+    using MPack = typename std::conditional<(T >= 5), uint64_t, uint32_t>::type;
     MPack MP[RY];
 #pragma unroll
     for (int t = 0; t <= T; ++t)
@@ -305,20 +325,19 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
 #define YEE_LOAD_PLANE(KK)                                                                  \
     do {                                                                                    \
         const int pofs_ = ((KK) - kb) * (int)ks;                                            \
-        const int mofs_ = ((KK) - kb) * (int)L.plane;                                       \
+        const int mofs_ = (max((KK) - 1, kb) - kb) * (int)L.plane;                         \
         _Pragma("unroll") for (int r = 0; r < RY; ++r) {                                    \
             const int so_ = pofs_ + rowoff[r];                                              \
             _Pragma("unroll") for (int c = 0; c < 3; ++c) {                                 \
                 PE[c][r] = B::load(rin, vo, (so_ + c * (int)cs) * ES);                      \
                 PH[c][r] = B::load(rin, vo, (so_ + (3 + c) * (int)cs) * ES);                \
             }                                                                               \
-            PM[r] = __builtin_amdgcn_raw_buffer_load_b8(rmat, vom, mofs_ + rowoff[r], 0);   \
+            PM[r] = __builtin_amdgcn_raw_buffer_load_b8(rmat, mat_offset(), mofs_ + rowoff[r], 0); \
         }                                                                                   \
         if constexpr (GR) PZ = make_float2(gcu[2 * (nx + ny + 2 + (KK))],                   \
                                            gcu[2 * (nx + ny + 2 + (KK)) + 1]);              \
     } while (0)
 
-    YEE_LOAD_PLANE(kb);
 
     uint32_t mx[6] = {0u, 0u, 0u, 0u, 0u, 0u};   // largest |value * 2^s| seen, as bits
 
@@ -327,7 +346,11 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     // an offset 2^31 beyond its address, which the buffer range check drops.
     // (Loads and stores share one completion counter; stores inside branches
     // make the compiler's wait for the next plane's loads also wait for them.)
-    auto store_plane = [&](const int q) __attribute__((always_inline)) {
+    // INNER tiles own no position outside a component's range; elsewhere those
+    // positions are stored as zero (Ex, Hy at x = nx; Ey, Hx at y = ny; Hz on
+    // both; the z walls keep their zeros through the plane masks).
+    auto store_plane = [&](const int q, auto inner_c) __attribute__((always_inline)) {
+        constexpr bool INNER = decltype(inner_c)::value;
         const int pofs = (q - kb) * (int)ks;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -336,10 +359,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
             const bool own = xown && row >= T && row < T + OY && y <= ny;
             const int vs = own ? vo : (int)((uint32_t)vo | 0x80000000u);
             const int so = (pofs + rowoff[r]) * ES;
+            float ev[3] = {E[T][0][r], E[T][1][r], E[T][2][r]};
+            float hv[3] = {H[T][0][r], H[T][1][r], H[T][2][r]};
+            if constexpr (!INNER) {
+                const bool ylt = y < ny;                // uniform over the wave
+                ev[0] = xlt ? ev[0] : 0.0f;
+                ev[1] = ylt ? ev[1] : 0.0f;
+                hv[0] = ylt ? hv[0] : 0.0f;
+                hv[1] = xlt ? hv[1] : 0.0f;
+                hv[2] = (xlt && ylt) ? hv[2] : 0.0f;
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                B::store(rout, vs, so + c * (int)cs * ES, E[T][c][r], up[c], mx[c], own);
-                B::store(rout, vs, so + (3 + c) * (int)cs * ES, H[T][c][r], up[3 + c], mx[3 + c], own);
+                B::store(rout, vs, so + c * (int)cs * ES, ev[c], up[c], mx[c], own);
+                B::store(rout, vs, so + (3 + c) * (int)cs * ES, hv[c], up[3 + c], mx[3 + c], own);
             }
         }
     };
@@ -349,6 +382,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     // per-level branches remain.
     // INNER: every lane and row of the tile lies strictly inside the grid in
     // x and y (no wall in reach), so only the plane tests remain in the masks.
+    // Otherwise only the tangential E of the x and y walls is held.
     auto iterate = [&](const int K, auto all_c, auto inner_c) __attribute__((always_inline)) {
         constexpr bool ALL = decltype(all_c)::value;
         constexpr bool INNER = decltype(inner_c)::value;
@@ -375,10 +409,6 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
             }
         }
         if (ALL || K + 1 <= ke) YEE_LOAD_PLANE(K + 1);
-        // The first row of this plane is the row above for wave w-1 at level 1
-        // in the next z step.
-        const int wb = K & 1, rb = wb ^ 1;   // exchange buffer written / read this step
-        if constexpr (NW > 1) s_e[wb][0][w][lane] = make_float2(E[0][0][0], E[0][2][0]);
 
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
@@ -393,14 +423,13 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                 const bool plt = ALL || p < nz, pint = ALL || (p > 0 && p < nz);
                 // ---- Faraday: H^(t) at plane p from E^(t-1) at p and p+1 ----
                 // E^(t-1) at plane p was computed in the previous z step, so the
-                // row above comes from the other exchange buffer without a barrier.
-                const float2 eup = NW > 1 ? s_e[rb][t - 1][w + 1][lane] : make_float2(0.0f, 0.0f);
+                // row above is read from the exchange rows without a barrier.
+                const float2 eup = NW > 1 ? s_e[t - 1][w + 1][lane] : make_float2(0.0f, 0.0f);
                 float Hn[3][RY];
                 const float chz = GR ? gzh[t] : a.chz;
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
                     const int y = yw + r;
-                    const bool yin = y >= 0 && y <= ny;
                     const float chx = GR ? gxh : a.chx, chy = GR ? gyh[r] : a.chy;
                     const float exu = r + 1 < RY ? Eo[0][(r + 1) % RY] : eup.x;
                     const float ezu = r + 1 < RY ? Eo[2][(r + 1) % RY] : eup.y;
@@ -415,15 +444,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     const float dex_y = exu - Eo[0][r];
                     const float dey_x = eyr - Eo[1][r];
                     const float hz = __builtin_fmaf(-chx, dey_x, __builtin_fmaf(chy, dex_y, Ho[2][r]));
-                    if constexpr (INNER) {
-                        Hn[0][r] = plt ? hx : Ho[0][r];
-                        Hn[1][r] = plt ? hy : Ho[1][r];
-                        Hn[2][r] = hz;
-                    } else {
-                        Hn[0][r] = (xin && yin && y < ny && plt) ? hx : Ho[0][r];
-                        Hn[1][r] = (xlt && yin && plt) ? hy : Ho[1][r];
-                        Hn[2][r] = (xlt && y >= 0 && y < ny) ? hz : Ho[2][r];
-                    }
+                    Hn[0][r] = plt ? hx : Ho[0][r];
+                    Hn[1][r] = plt ? hy : Ho[1][r];
+                    Hn[2][r] = hz;
                 }
                 // ---- Ampere: E^(t) at plane p from H^(t) at p and p-1 ----
                 // Only row 0 needs the H row of the wave below: rows 1..RY-1 are
@@ -433,10 +456,10 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                 float En[3][RY];
                 auto e_row = [&](const int r, const float hxd, const float hzd) __attribute__((always_inline)) {
                     const int y = yw + r;
-                    const bool yint = y > 0 && y < ny;
+                    const bool ywall = y == 0 || y == ny;   // uniform over the wave
                     const float hzl = from_left(Hn[2][r]);
                     const float hyl = from_left(Hn[1][r]);
-                    const float4 cf = s_coef[(uint32_t)(MP[r] >> (8 * t)) & 0xffu];
+                    const float4 cf = s_coef[(uint32_t)(MP[r] >> (8 * (t - 1))) & 0xffu];
                     float cbx = cf.y, cby = cf.z, cbz = cf.w;
                     if constexpr (GR) {   // cf.y holds G
                         cbx = cf.y * gxe;
@@ -457,18 +480,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                         En[1][r] = pint ? ey : Eo[1][r];
                         En[2][r] = plt ? ez : Eo[2][r];
                     } else {
-                        En[0][r] = (xlt && yint && pint) ? ex : Eo[0][r];
-                        En[1][r] = (xint && y >= 0 && y < ny && pint) ? ey : Eo[1][r];
-                        En[2][r] = (xint && yint && plt) ? ez : Eo[2][r];
+                        En[0][r] = (!ywall && pint) ? ex : Eo[0][r];
+                        En[1][r] = (!xwall && pint) ? ey : Eo[1][r];
+                        En[2][r] = (!xwall && !ywall && plt) ? ez : Eo[2][r];
                     }
                 };
-                const int hb = (T & 1) ? ((K + t) & 1) : (t & 1);
-                if constexpr (NW > 1) s_h[hb][w + 1][lane] = make_float2(Hn[0][RY - 1], Hn[2][RY - 1]);
+                constexpr int NHB = TileShared<T, NW>::NHB;
+                if constexpr (NW > 1) s_h[t % NHB][w + 1][lane] = make_float2(Hn[0][RY - 1], Hn[2][RY - 1]);
 #pragma unroll
                 for (int r = 1; r < RY; ++r) e_row(r, Hn[0][r - 1], Hn[2][r - 1]);
                 if constexpr (NW > 1) {
                     __syncthreads();
-                    const float2 hdn = s_h[hb][w][lane];
+                    const float2 hdn = s_h[t % NHB][w][lane];
+                    // every wave has read level t-1's previous row: publish this step's
+                    if constexpr (ALL) s_e[t - 1][w][lane] = make_float2(E[t - 1][0][0], E[t - 1][2][0]);
                     e_row(0, hdn.x, hdn.y);
                 } else {
                     e_row(0, 0.0f, 0.0f);
@@ -488,9 +513,6 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                                 else En[2][r] = En[2][r] + val;
                             }
                     }
-                }
-                if constexpr (NW > 1) {
-                    if (t < T) s_e[wb][t < T ? t : 0][w][lane] = make_float2(En[0][0], En[2][0]);
                 }
                 // ---- probes, recorded by the owning tile only (planes outside
                 // [z0, z1) are this chunk's halo, where upper levels are incomplete) ----
@@ -533,11 +555,17 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         }
 
         // ---- store the owned part of level T (plane K-T) ----
-        if constexpr (ALL) store_plane(K - T);
-        else if (K - T >= z0 && K - T < z1) store_plane(K - T);
-        // With some levels idle, the per-level barriers no longer separate the
-        // exchange writes of this step from the reads of the next one.
-        if constexpr (!ALL && NW > 1) __syncthreads();
+        if constexpr (ALL) store_plane(K - T, inner_c);
+        else if (K - T >= z0 && K - T < z1) store_plane(K - T, inner_c);
+        // With some levels idle, every level's exchange row is published at the
+        // end of the step (an active level t+1 has read the previous one before
+        // its barrier), and a barrier separates them from the next step's
+        // reads.  T = 1 has no level between the write and the next read.
+        if constexpr (!ALL && NW > 1) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) s_e[t][w][lane] = make_float2(E[t][0][0], E[t][2][0]);
+        }
+        if constexpr ((!ALL || T == 1) && NW > 1) __syncthreads();
     };
 
     // warm-up (upper levels not yet in their cone), steady state (every level
@@ -546,6 +574,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     auto march = [&](auto inner_c) __attribute__((always_inline)) {
         using F = std::false_type;
         using Tr = std::true_type;
+        YEE_LOAD_PLANE(kb);   // here, so that its registers are live on one branch only
         int K = kb;
         const int kw = min(max(kb > 0 ? kb + 2 * T - 1 : T + 1, z0 + T), ke);
         const int kend = ke < nz ? ke : nz + T;
@@ -607,21 +636,21 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     fused_tile<T, RY, NW, Codec, GR>(a, logical, tx, ty, tz, sm);
 }
 
-// Several solves in one persistent launch: the workgroups stride over the
-// concatenated tile lists of up to MAX_BATCH solves (same storage format and
-// block length), so small grids that could not fill the GPU alone share it.
+// Several solves in one launch: the workgroups take the concatenated tile
+// lists of up to MAX_BATCH solves (same storage format and block length), one
+// tile each, so small grids that could not fill the GPU alone share it.
 template <int T, int RY, int NW, class Codec>
 __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
 {
     __shared__ TileShared<T, NW> sm;
-    const int total = a.start[a.n];
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        int i = 0;
-        while (i + 1 < a.n && item >= a.start[i + 1]) ++i;
-        int tx, ty, tz;
-        tile_coords(a.s[i], item - a.start[i], tx, ty, tz);   // a range: always true
-        fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], tx, ty, tz, sm);
-    }
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int item = (b & 7) * (nb >> 3) + (b >> 3);      // contiguous runs per XCD
+    if (item >= a.start[a.n]) return;
+    int i = 0;
+    while (i + 1 < a.n && item >= a.start[i + 1]) ++i;
+    int tx, ty, tz;
+    tile_coords(a.s[i], item - a.start[i], tx, ty, tz);   // a range: always true
+    fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], tx, ty, tz, sm);
 }
 
 // ---- tilings ---------------------------------------------------------------
@@ -790,9 +819,8 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
         }
         b.start[i + 1] = b.start[i] + a.nwg;
     }
-    // persistent: at most ~4 resident workgroups per CU, each striding over the work list
     if (b.start[n] == 0) return hipSuccess;        // every solve all +0 (unscaled storage)
-    const int grid = std::min(b.start[n], 1024);
+    const int grid = (b.start[n] + 7) / 8 * 8;
     hipLaunchKernelGGL((yee_fused_batch<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, b);
     return hipGetLastError();
 }

@@ -182,7 +182,8 @@ hipError_t launch_fused_batch(int storage, int T, const FusedArgs *args, int n, 
 bool fused_fits(const Layout &L, int storage, int T);
 // Tile shape (index into the fused kernel's table) and steps per pass chosen
 // when the caller does not: measured fastest on MI355X.
-int auto_shape(int storage, int T, bool graded = false);
+// cells: of the grid (0 for batched solves, which take the small-grid shape).
+int auto_shape(int storage, int T, bool graded = false, long long cells = 0);
 int fastest_T(const Layout &L, int storage, bool graded = false);
 hipError_t launch_diag(int storage, const DiagArgs &a, double *out11, hipStream_t st);
 int diag_blocks(const Layout &L);
