@@ -341,7 +341,16 @@ int orc_run_f32(int nx, int ny, int nz, const float *ch, const float *coef,
 /* the largest |source sample|.  If m is 0, the largest M over all six     */
 /* components is used; if that is 0 too, s_c = 0.  The stored magnitudes   */
 /* then stay below 2^10, 64x under the binary16 limit, so fields may grow  */
-/* 64-fold within one block before saturating.                             */
+/* 64-fold within one block before overflowing.                            */
+/*                                                                          */
+/* Overflow retry: if some finite value of component c at a block's end    */
+/* would round beyond the largest finite value with s_c, the block's end   */
+/* is quantised instead with s_c = 10 - ceil(log2 max(m', A)), m' the      */
+/* largest |value| of component c before quantisation (the block's own     */
+/* FP32 values do not depend on the scale it ends with, so a GPU re-run of */
+/* the block from its intact input gives the same values).  Only what     */
+/* still overflows then saturates and raises the flag (an infinite value), */
+/* as does a NaN.                                                           */
 /* ------------------------------------------------------------------------ */
 
 static uint32_t f2u(float x) { uint32_t u; memcpy(&u, &x, 4); return u; }
@@ -460,9 +469,34 @@ static float quantize_array(int fmt, int s, size_t n, float *x, int *flag)
     return mx;
 }
 
+/* 1 if some finite x * 2^s rounds beyond the largest finite value of the
+ * format (NaN excluded). */
+static int would_overflow(int fmt, int s, size_t n, const float *x)
+{
+    int ov = 0;
+    const float up = ldexpf(1.0f, s);
+    #pragma omp parallel for schedule(static) reduction(| : ov)
+    for (size_t p = 0; p < n; p++) {
+        if (isnan(x[p])) continue;
+        const float y = x[p] * up;
+        if (fmt == 1) ov |= (f32_to_f16_bits(y) & 0x7fffu) == 0x7c00u;
+        else ov |= (f32_to_bf16_bits(y) & 0x7fffu) == 0x7f80u;
+    }
+    return ov;
+}
+
+/* largest |x| (NaN ignored) */
+static float max_abs(size_t n, const float *x)
+{
+    float mx = 0.0f;
+    #pragma omp parallel for schedule(static) reduction(max : mx)
+    for (size_t p = 0; p < n; p++) if (fabsf(x[p]) > mx) mx = fabsf(x[p]);
+    return mx;
+}
+
 /* Quantise all six components.  upload != 0: M comes from the values
- * themselves; otherwise from m_stored (the previous quantisation).
- * scales[6] and m_stored[6] are updated. */
+ * themselves; otherwise from m_stored (the previous quantisation), with the
+ * overflow retry above.  scales[6] and m_stored[6] are updated. */
 void orc_quantize_state(int nx, int ny, int nz, int fmt, int upload, float a_max,
                         float *f, int *scales, float *m_stored, int *flag)
 {
@@ -479,8 +513,14 @@ void orc_quantize_state(int nx, int ny, int nz, int fmt, int upload, float a_max
         }
     }
     orc_choose_scales(m, a_max, scales);
-    for (int c = 0; c < 6; c++)
-        m_stored[c] = quantize_array(fmt, scales[c], g.n, f + (size_t)c * g.n, flag);
+    for (int c = 0; c < 6; c++) {
+        float *x = f + (size_t)c * g.n;
+        if (!upload && would_overflow(fmt, scales[c], g.n, x)) {
+            const float mp = max_abs(g.n, x);
+            scales[c] = scale_from(mp > a_max ? mp : a_max);
+        }
+        m_stored[c] = quantize_array(fmt, scales[c], g.n, x, flag);
+    }
 }
 
 /* f32 arithmetic with quantisation at the end of every block.  Blocks end

@@ -97,20 +97,51 @@ def test_block_boundaries_change_result_and_t_matters():
     assert 0 < e4 < e1 < 1e-2
 
 
-def test_overflow_saturates_and_flags():
+def test_overflow_block_retried_with_its_own_scale():
     """A component whose stored maximum is tiny, driven hard by H within one
-    block, exceeds the 64x headroom: it saturates at the largest finite
-    binary16 value and raises the flag (bfloat16 has the range of binary32
-    and does not overflow)."""
+    block, would exceed the 64x headroom at the block's end: that component
+    is quantised instead with the scale of its own end-of-block maximum,
+    10 - ceil(log2 max(m', A)), and nothing saturates (the overflow retry).
+    Checked against the same block in plain FP32 quantised by numpy's
+    binary16 (RNE), with the scale computed here from frexp; the other
+    components keep the scale rule's choice.  bfloat16 has the range of
+    binary32 and keeps the rule's scales."""
     wl, _ = _small_problem()
     p = oracle.Problem(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.dt, wl.eps_r, wl.sigma, wl.mat)
-    for fmt, expect in ((1, 1), (2, 0)):
+    for fmt in (1, 2):
         f = oracle.zero_fields(wl.nx, wl.ny, wl.nz, np.float32)
         f[3, 3:5, 3:5, 3:6] = 1.0               # Hx block
         f[2, 2, 2, 2] = 1e-6                    # Ez max 1e-6 -> scale 10+19 = 29
         st = p.quantize_upload(f, fmt)
         assert st["scales"][2] == 29
+        rule = oracle.choose_scales(st["m_stored"], 0.0)     # the scales the rule picks for this block
+        g = f.copy()
         p.run_q(f, 0, 2, fmt, 2, st)
-        assert st["flag"][0] == expect
+        p.run_f32(g, 0, 2)                      # the block's own values, before quantisation
+        assert st["flag"][0] == 0
+        for c in range(6):
+            x = g[c].astype(np.float64)
+            if fmt == 1 and np.max(np.abs(x)) * 2.0 ** rule[c] >= 65520.0:
+                fr, e = np.frexp(np.max(np.abs(x)))
+                sc = 10 - (e - 1 if fr == 0.5 else e)
+                assert c == 2 and sc < 29 - 6       # Ez grew far past its headroom
+            else:
+                sc = rule[c]
+            assert st["scales"][c] == sc, c
+            if fmt == 1:
+                q = (g[c] * np.float32(2.0 ** sc)).astype(np.float16).astype(np.float32) * np.float32(2.0 ** -sc)
+                assert np.array_equal(f[c], q), c
         if fmt == 1:
-            assert np.max(np.abs(f[2])) == np.float32(65504.0 * 2.0 ** -29)
+            assert np.max(np.abs(f[2])) < 1024.0 * 2.0 ** -st["scales"][2]
+
+
+def test_non_finite_value_still_flags():
+    """A NaN cannot be stored: the flag is raised whatever the retry."""
+    wl, _ = _small_problem()
+    p = oracle.Problem(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, wl.dt, wl.eps_r, wl.sigma, wl.mat)
+    f = oracle.zero_fields(wl.nx, wl.ny, wl.nz, np.float32)
+    f[3, 3:5, 3:5, 3:6] = 1.0
+    st = p.quantize_upload(f, 1)
+    f[4, 4, 4, 4] = np.nan
+    p.run_q(f, 0, 2, 1, 2, st)
+    assert st["flag"][0] == 1
