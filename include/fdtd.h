@@ -32,7 +32,13 @@
  * Fields may instead be stored as binary16 or bfloat16 with one power-of-two
  * scale per component; they are then re-encoded at the end of every block
  * of T steps (blocks end at absolute step counts that are multiples of T and
- * at the end of each fdtd_step call).
+ * at the end of each fdtd_step call), with the scale s_c = 10 -
+ * ceil(log2 max(M_c, A)), M_c the largest stored |value| of the component at
+ * the previous block's end and A the largest |source sample|.  A component
+ * that would overflow the format at a block's end is instead encoded with
+ * the scale of its own end-of-block maximum: the block runs again from its
+ * input (still intact: fields ping-pong between two buffers), on the GPU,
+ * without a host round trip.
  *
  * Ownership and errors
  * --------------------
@@ -62,7 +68,7 @@ enum fdtd_status {
     FDTD_ENOMEM = -2,   /* device or host allocation failed, workspace too small */
     FDTD_EDEVICE = -3,  /* a HIP call or kernel launch failed */
     FDTD_ECFL = -4,     /* dt above the 3-D Courant limit */
-    FDTD_ERANGE = -5,   /* reduced storage saturated or a non-finite value was stored */
+    FDTD_ERANGE = -5,   /* reduced storage held a non-finite value, or a value beyond the format at any scale */
     FDTD_ESTATE = -6    /* call not allowed in the solver's current state */
 };
 
@@ -327,11 +333,13 @@ int fdtd_save_state(fdtd_solver *s, void *host_dst, size_t bytes);
 int fdtd_load_state(fdtd_solver *s, const void *host_src, size_t bytes);
 
 /* Current per-component storage scales (2^scale multiplies a value before
- * encoding; all 0 for FP32 storage) and the saturation flag.  Synchronises. */
+ * encoding; all 0 for FP32 storage) and the sticky flag of FDTD_ERANGE (a
+ * non-finite value stored, or a value beyond the format even at the scale
+ * its overflow retry chose, stored saturated).  Synchronises. */
 int fdtd_storage_state(fdtd_solver *s, int scales[6], int *saturated);
 
-/* Wait for all work enqueued on the solver's stream; reports FDTD_ERANGE if
- * reduced storage saturated. */
+/* Wait for all work enqueued on the solver's stream; reports FDTD_ERANGE when
+ * reduced storage raised its flag (see fdtd_storage_state). */
 int fdtd_synchronize(fdtd_solver *s);
 
 /* Release the solver and everything the library allocated for it. */

@@ -61,7 +61,7 @@ Dims dims_for(int nx, int ny, int nz, int storage)
     d.kstride = 6 * d.plane;
     d.fbytes = round_up((size_t)d.kstride * (nz + 1) * es, 256);
     d.matbytes = round_up((size_t)d.plane * (nz + 1), 256);
-    d.total = 2 * d.fbytes + d.matbytes + 256;
+    d.total = 2 * d.fbytes + d.matbytes + round_up(sizeof(yee::Ctrl), 256);   // then the control block
     return d;
 }
 
@@ -565,6 +565,7 @@ yee::StorageBlock storage_block(const fdtd_solver *s)
     b.slot_clear = (int)((s->block + 2) % 3);
     b.par = (int)(s->block % 2);
     b.a_max = s->a_max;
+    b.retry = 0;
     return b;
 }
 
@@ -1742,7 +1743,7 @@ int fdtd_synchronize(fdtd_solver *s)
         yee::Ctrl c;
         int rc = read_ctrl(s, &c);
         if (rc) return rc;
-        if (c.flag) return fail(FDTD_ERANGE, "reduced storage saturated or stored a non-finite value");
+        if (c.flag) return fail(FDTD_ERANGE, "reduced storage stored a non-finite value, or overflowed after its block was re-run with new scales");
     }
     return FDTD_OK;
 }

@@ -14,11 +14,11 @@ namespace yee {
 // A stored value q of component c represents q * 2^-s_c.  Encoding rounds
 // y = x * 2^s_c to nearest-even after clamping y to +-(largest finite value):
 // for every finite y this equals rounding and then saturating what would
-// overflow.  Stores track the largest |y| (as bits; NaN compares above every
-// number); finish() turns it into the largest stored magnitude (rounding is
-// monotone, so max |Q(y)| = Q(max |y|)) and the saturation flag (|y| at or
-// above the first value that would round beyond the largest finite one, or
-// NaN).
+// overflow.  Stores track the largest |x| (as bits; NaN compares above every
+// number); finish_max() turns it into the largest stored magnitude (scaling
+// by 2^s and rounding are monotone, so max |Q(y)| = Q(max |x| 2^s)), the
+// overflow test (|y| at or above the first value that would round beyond the
+// largest finite one) and the NaN test.
 
 struct CodecF32 {
     using T = float;
@@ -39,13 +39,12 @@ struct CodecF16 {
     {
         return __builtin_bit_cast(uint16_t, (_Float16)__builtin_amdgcn_fmed3f(y, -kMax, kMax));
     }
-    // Encode v * 2^s; fold |v * 2^s| into mx when `track` (owned values only).
+    // Encode v * 2^s; fold |v| into mx when `track` (owned values only).
     __device__ static inline uint16_t encode_tracked(float v, float up, uint32_t &mx, bool track)
     {
-        const float y = v * up;
-        const uint32_t a = __builtin_bit_cast(uint32_t, y) & 0x7fffffffu;
+        const uint32_t a = __builtin_bit_cast(uint32_t, v) & 0x7fffffffu;
         mx = (track && a > mx) ? a : mx;
-        return encode(y);
+        return encode(v * up);
     }
     __device__ static inline float stored_mag(float ymax)
     {
@@ -68,13 +67,12 @@ struct CodecBF16 {
         const uint32_t u = __builtin_bit_cast(uint32_t, __builtin_amdgcn_fmed3f(y, -m, m));
         return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
     }
-    // Encode v * 2^s; fold |v * 2^s| into mx when `track` (owned values only).
+    // Encode v * 2^s; fold |v| into mx when `track` (owned values only).
     __device__ static inline uint16_t encode_tracked(float v, float up, uint32_t &mx, bool track)
     {
-        const float y = v * up;
-        const uint32_t a = __builtin_bit_cast(uint32_t, y) & 0x7fffffffu;
+        const uint32_t a = __builtin_bit_cast(uint32_t, v) & 0x7fffffffu;
         mx = (track && a > mx) ? a : mx;
-        return encode(y);
+        return encode(v * up);
     }
     __device__ static inline float stored_mag(float ymax)
     {
@@ -82,16 +80,20 @@ struct CodecBF16 {
     }
 };
 
-// Largest stored magnitude (times 2^-s via `down`) and saturation flag from
-// the largest |y| bits a thread saw.
+// From the largest |x| bits a thread saw (values before encoding, scale
+// 2^s = up): the largest stored magnitude (in field units), whether a NaN was
+// stored, whether |x| 2^s would round beyond the largest finite value
+// (overflow), and the largest |x| itself.
 template <class Codec>
-__device__ inline void finish_max(uint32_t ybits, float down, float *m, bool *flag)
+__device__ inline void finish_max(uint32_t xbits, float up, float *m, bool *nan, bool *over, float *pre)
 {
-    if (ybits > 0x7f800000u) { *flag = true; *m = 0.0f; return; }         // NaN
-    const float ymax = __builtin_bit_cast(float, ybits);
-    if constexpr (std::is_same<Codec, CodecF16>::value) *flag = ymax >= CodecF16::kOver;
-    else *flag = ybits >= CodecBF16::kOverBits;
-    *m = Codec::stored_mag(ymax) * down;
+    *nan = xbits > 0x7f800000u;
+    if (*nan) { *over = false; *m = 0.0f; *pre = 0.0f; return; }
+    *pre = __builtin_bit_cast(float, xbits);
+    const float ymax = *pre * up;
+    if constexpr (std::is_same<Codec, CodecF16>::value) *over = ymax >= CodecF16::kOver;
+    else *over = __builtin_bit_cast(uint32_t, ymax) >= CodecBF16::kOverBits;
+    *m = Codec::stored_mag(ymax) * (1.0f / up);   // 2^-s: exact
 }
 
 // ---- scale rule --------------------------------------------------------------

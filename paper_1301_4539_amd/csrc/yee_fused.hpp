@@ -132,7 +132,7 @@ struct TileShared {
     int4 prb[MAX_LOCAL];     // probes this workgroup owns: (comp, lane, row, plane)
     int prbid[MAX_LOCAL];
     int nsrc, nprb;
-    uint32_t vmax[6];        // largest |value * 2^s| per component over the tile, as bits
+    uint32_t vmax[6];        // largest |value| per component over the tile, as bits
 };
 
 // One tile (x-y tile x z chunk) of one solve: T steps of the owned region.
@@ -188,11 +188,22 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     if constexpr (Codec::scaled) {
         float mprev[6];
         int s_in[6], s_out[6];
+        Ctrl *const ctrl = a.sb.ctrl;
+        // the stored maxima of the input: of its block's second pass if it ran
+        const bool retried_in = ctrl->ovf[a.sb.slot_in] != 0u;
         for (int c = 0; c < 6; ++c) {
-            mprev[c] = __uint_as_float(a.sb.ctrl->maxbits[a.sb.slot_in][c]);
-            s_in[c] = a.sb.ctrl->scale[a.sb.par][c];
+            mprev[c] = __uint_as_float(retried_in ? ctrl->rmaxbits[a.sb.slot_in][c] : ctrl->maxbits[a.sb.slot_in][c]);
+            s_in[c] = ctrl->scale[a.sb.par][c];
         }
         choose_scales(mprev, a.sb.a_max, s_out);
+        if (a.sb.retry) {                // the components that overflowed take their own block's scale
+            const uint32_t ov = ctrl->ovf[a.sb.slot_out];
+            for (int c = 0; c < 6; ++c)
+                if ((ov >> c) & 1u) {
+                    const float pm = __uint_as_float(ctrl->premax[a.sb.slot_out][c]);
+                    s_out[c] = scale_from(pm > a.sb.a_max ? pm : a.sb.a_max);
+                }
+        }
         for (int c = 0; c < 6; ++c) {   // uniform: keep them in scalar registers
             dn[c] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                         __builtin_bit_cast(int, ldexpf(1.0f, -s_in[c]))));
@@ -200,8 +211,13 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                         __builtin_bit_cast(int, ldexpf(1.0f, s_out[c]))));
         }
         if (logical == 0 && tid < 6) {
-            a.sb.ctrl->scale[a.sb.par ^ 1][tid] = s_out[tid];
-            a.sb.ctrl->maxbits[a.sb.slot_clear][tid] = 0u;
+            ctrl->scale[a.sb.par ^ 1][tid] = s_out[tid];
+            if (!a.sb.retry) {
+                ctrl->maxbits[a.sb.slot_clear][tid] = 0u;
+                ctrl->rmaxbits[a.sb.slot_clear][tid] = 0u;
+                ctrl->premax[a.sb.slot_clear][tid] = 0u;
+                if (tid == 0) ctrl->ovf[a.sb.slot_clear] = 0u;
+            }
         }
     } else {
         for (int c = 0; c < 6; ++c) dn[c] = up[c] = 1.0f;
@@ -339,7 +355,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     } while (0)
 
 
-    uint32_t mx[6] = {0u, 0u, 0u, 0u, 0u, 0u};   // largest |value * 2^s| seen, as bits
+    uint32_t mx[6] = {0u, 0u, 0u, 0u, 0u, 0u};   // largest |value| stored, as bits
 
     // Store the owned part of level T, which holds plane q.  Every lane and row
     // issues its stores, without branches: a value this tile does not own gets
@@ -596,8 +612,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         // reduce over the wave, then over the workgroup in LDS, and only then
         // touch the six global words (one atomic per component per workgroup;
         // per-wave atomics on the same six addresses serialise at the cache).
-        // The maxima are bit patterns of |y| >= 0, so unsigned order is float
-        // order, and a NaN (bits above infinity) wins and raises the flag.
+        // The maxima are bit patterns of |value| >= 0, so unsigned order is
+        // float order, and a NaN (bits above infinity) wins and raises the flag.
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             uint32_t b = mx[c];
@@ -610,14 +626,23 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         __syncthreads();
         if (tid < 6) {
             const uint32_t b = sm.vmax[tid];
-            float m;
-            bool fl;
+            float m, pre;
+            bool nan, over;
             float upc = up[0];
 #pragma unroll
             for (int c = 1; c < 6; ++c) upc = tid == c ? up[c] : upc;
-            finish_max<Codec>(b, 1.0f / upc, &m, &fl);
-            if (m > 0.0f) atomicMax(&a.sb.ctrl->maxbits[a.sb.slot_out][tid], __float_as_uint(m));
-            if (fl) atomicOr(&a.sb.ctrl->flag, 1u);
+            finish_max<Codec>(b, upc, &m, &nan, &over, &pre);
+            Ctrl *const ctrl = a.sb.ctrl;
+            const int so = a.sb.slot_out;
+            if (!a.sb.retry) {           // first pass: an overflow asks for the second pass
+                if (m > 0.0f) atomicMax(&ctrl->maxbits[so][tid], __float_as_uint(m));
+                if (pre > 0.0f) atomicMax(&ctrl->premax[so][tid], __float_as_uint(pre));
+                if (over) atomicOr(&ctrl->ovf[so], 1u << tid);
+                if (nan) atomicOr(&ctrl->flag, 1u);
+            } else {
+                if (m > 0.0f) atomicMax(&ctrl->rmaxbits[so][tid], __float_as_uint(m));
+                if (nan || over) atomicOr(&ctrl->flag, 1u);
+            }
         }
     }
     __syncthreads();   // LDS is reused by the next tile of a batched launch
@@ -633,6 +658,8 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     const int logical = (b & 7) * (nb >> 3) + (b >> 3);
     int tx, ty, tz;
     if (logical >= a.nwg || !tile_coords(a, logical, tx, ty, tz)) return;   // uniform per workgroup
+    if constexpr (Codec::scaled)         // a second pass runs only after an overflow
+        if (a.sb.retry && a.sb.ctrl->ovf[a.sb.slot_out] == 0u) return;
     fused_tile<T, RY, NW, Codec, GR>(a, logical, tx, ty, tz, sm);
 }
 
@@ -648,6 +675,8 @@ __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
     if (item >= a.start[a.n]) return;
     int i = 0;
     while (i + 1 < a.n && item >= a.start[i + 1]) ++i;
+    if constexpr (Codec::scaled)         // a second pass runs only after an overflow
+        if (a.s[i].sb.retry && a.s[i].sb.ctrl->ovf[a.s[i].sb.slot_out] == 0u) return;
     int tx, ty, tz;
     tile_coords(a.s[i], item - a.start[i], tx, ty, tz);   // a range: always true
     fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], tx, ty, tz, sm);
@@ -655,10 +684,12 @@ __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
 
 // ---- tilings ---------------------------------------------------------------
 // (RY rows per lane, NW waves) per time-block length; variant 0 is the default.
-// T = 5 and 6 exceed the register file at every shape: 2 x 16 waves is capped
-// at 128 VGPRs per lane and spills a few values in the steady loop, the
-// 8-wave shapes (256 VGPRs) spill less.  They serve uniform-spacing solves
-// alone (no batches, no graded sizes).
+// At 16 waves a lane has 128 VGPRs, at 12 waves 168, at 8 waves 256.  The
+// shapes the library picks by itself (T <= 4 for FP32, T <= 3 for 16-bit
+// storage; auto_shape) fit without spilling; 16-bit storage at T = 4, the
+// 3 x 12 shapes and T = 5, 6 at every shape exceed the register file (the
+// 8-wave shapes least: T = 5 FP32 at 4 x 8 spills 7 VGPRs).  T = 5 and 6
+// serve uniform-spacing solves alone (no batches, no graded sizes).
 struct Tiling { int ry, nw; };
 constexpr Tiling kTilings[MAX_T + 1][3] = {
     {},
@@ -789,6 +820,12 @@ hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
     }
     const int grid = (a.nwg + 7) / 8 * 8;
     hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR>), dim3(grid), dim3(threads), 0, st, a);
+    if constexpr (Codec::scaled) {       // the block again, with new scales, if it overflowed
+        if (hipError_t e = hipGetLastError()) return e;
+        a.sb.retry = 1;
+        a.tile_stats = nullptr;
+        hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR>), dim3(grid), dim3(threads), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -822,6 +859,11 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
     if (b.start[n] == 0) return hipSuccess;        // every solve all +0 (unscaled storage)
     const int grid = (b.start[n] + 7) / 8 * 8;
     hipLaunchKernelGGL((yee_fused_batch<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, b);
+    if constexpr (Codec::scaled) {       // solves whose block overflowed run it again
+        if (hipError_t e = hipGetLastError()) return e;
+        for (int i = 0; i < n; ++i) b.s[i].sb.retry = 1;
+        hipLaunchKernelGGL((yee_fused_batch<T, tl.ry, tl.nw, Codec>), dim3(grid), dim3(threads), 0, st, b);
+    }
     return hipGetLastError();
 }
 

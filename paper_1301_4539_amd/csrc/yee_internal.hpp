@@ -25,13 +25,22 @@ struct Layout {
 // Reduced-storage control block (device).  maxbits holds, per component,
 // the largest |stored value| as float bits (non-negative floats order like
 // their bit patterns); three slots rotate so that the block that reads one
-// slot fills the next and clears the one after.  scale[par] is the scale
-// of the currently stored fields.
+// slot fills the next and clears the one after, and so do the arrays below.
+// scale[par] is the scale of the currently stored fields.  Overflow retry:
+// a block's first pass records in ovf (bit c) the components whose encoding
+// would overflow and in premax their largest |value| before encoding; its
+// second pass, which runs only when ovf is set, encodes those components with
+// a scale from premax and records its stored maxima in rmaxbits, where the
+// next block reads them.  flag is sticky: a NaN, or an overflow left after
+// the retry.
 struct Ctrl {
     uint32_t maxbits[3][6];
+    uint32_t rmaxbits[3][6];
+    uint32_t premax[3][6];
+    uint32_t ovf[3];
     int32_t scale[2][6];
     uint32_t flag;
-    uint32_t pad[3];
+    uint32_t pad[2];
 };
 
 struct SourceTable {
@@ -52,6 +61,7 @@ struct StorageBlock {
     Ctrl *ctrl;
     int slot_in, slot_out, slot_clear, par;
     float a_max;          // largest |source sample|
+    int retry;            // 1: the block's second pass (runs only if its first pass overflowed)
 };
 
 // Live nodes of a solve: a node is dead when its six values are +0 and stay

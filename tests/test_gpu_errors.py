@@ -77,14 +77,80 @@ def test_caller_workspace_equals_library_allocation():
     assert np.array_equal(outs[0], outs[1])
 
 
-def test_fp16_saturation_reported_as_erange():
+def _overflowing_state(wl):
+    """Hx of order 1 next to an Ez whose largest value is 1e-6: Ez's scale
+    leaves it no room for the curl of Hx within one block."""
+    f = np.zeros((6, wl.nz + 1, wl.ny + 1, wl.nx + 1), np.float32)
+    f[3, 3:5, 3:5, 3:6] = 1.0            # Hx
+    f[2, 2, 2, 2] = 1e-6                 # Ez maximum 1e-6 -> large scale
+    return f
+
+
+def test_fp16_overflow_block_rerun_bitexact_with_oracle():
     """A component scaled for a tiny maximum and then driven hard within one
-    block saturates: fdtd_synchronize reports FDTD_ERANGE."""
+    block would overflow binary16: the block runs again from its input with
+    that component's scale taken from the block's own maximum (the oracle's
+    overflow retry), bit for bit, and nothing is reported."""
+    import oracle
+    from tests import gpu_helpers as G
+    wl, s = _solver(W.FP16)
+    f = _overflowing_state(wl)
+    try:
+        s.set_fields(f)
+        s.step(2)
+        s.step(3)
+        s.synchronize()                    # no FDTD_ERANGE
+        got = s.read_fields()
+        scales, sat = s.storage_state()
+    finally:
+        s.close()
+    prob = oracle.Problem.from_workload(wl)
+    ref = G.pec_clean(wl, f)
+    st = prob.quantize_upload(ref, W.FP16)
+    rule = oracle.choose_scales(st["m_stored"], prob.a_max)
+    prob.run_q(ref, 0, 2, W.FP16, 2, st)
+    assert st["scales"][2] < rule[2] - 6          # the first block was re-run with a new Ez scale
+    prob.run_q(ref, 2, 3, W.FP16, 2, st)
+    assert not sat and not st["flag"][0]
+    assert scales == list(st["scales"])
+    assert G.first_mismatch(got, ref) is None, G.first_mismatch(got, ref)
+
+
+def test_fp16_overflow_rerun_in_a_batch():
+    """The same in a batched launch beside a solve that does not overflow:
+    only the overflowing solve's block runs again; both equal the oracle."""
+    import oracle
+    from tests import gpu_helpers as G
+    wl, a = _solver(W.FP16)
+    wl2 = W.spheres(20, 14, 11, 3, 12, seed=9, n_sources=1, n_probes=2, rmin=1, rmax=3, storage=W.FP16)
+    b = fdtd.Solver.from_workload(wl2, kernel=fdtd.KERNEL_FUSED, time_block=2)
+    f = _overflowing_state(wl)
+    try:
+        a.set_fields(f)
+        fdtd.step_batch([a, b], [4, 4])
+        a.synchronize()
+        b.synchronize()
+        got_a, got_b = a.read_fields(), b.read_fields()
+    finally:
+        a.close()
+        b.close()
+    prob = oracle.Problem.from_workload(wl)
+    ref = G.pec_clean(wl, f)
+    st = prob.quantize_upload(ref, W.FP16)
+    prob.run_q(ref, 0, 4, W.FP16, 2, st)
+    ref_b, _, st_b = G.oracle_q(wl2, 4, W.FP16, 2)
+    assert not st["flag"][0] and not st_b["flag"][0]
+    assert G.first_mismatch(got_a, ref) is None, G.first_mismatch(got_a, ref)
+    assert G.first_mismatch(got_b, ref_b) is None, G.first_mismatch(got_b, ref_b)
+
+
+def test_value_beyond_the_format_reported_as_erange():
+    """A value that binary16 cannot hold at any scale (1e25 > 65504 x 2^64)
+    is stored saturated and reported: fdtd_synchronize gives FDTD_ERANGE."""
     wl, s = _solver(W.FP16)
     try:
-        f = np.zeros((6, wl.nz + 1, wl.ny + 1, wl.nx + 1), np.float32)
-        f[3, 3:5, 3:5, 3:6] = 1.0            # Hx
-        f[2, 2, 2, 2] = 1e-6                 # Ez maximum 1e-6 -> large scale
+        f = _overflowing_state(wl)
+        f[3, 3, 3, 3] = 1e25
         s.set_fields(f)
         s.step(2)
         assert _code(s.synchronize) == fdtd.ERANGE
