@@ -17,6 +17,7 @@ p50/p99 per-solve latency, the serving run, and the CPU oracle timed on the
 host cores.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -152,11 +153,14 @@ def cpu_baseline(wl, budget_s=15.0):
             "one_thread": {"value": wl.cells * n1 / dt1 / 1e9, "steps": n1}, "host_cpu": host}
 
 
-def serving_leg(rate, n, torch):
+def serving_leg(rate, n, torch, solo_sample=32):
     """256 requests (dims U{48..320}, 5-60 spheres, 200-3000 steps, FP32 or
     FP16 storage, 8 probes) with Poisson arrivals at `rate`; returns the
-    summary of the continuous-batching engine."""
-    from paper_1301_4539_amd import serve, workload as W
+    summary of the continuous-batching engine (pipelined ticks), the same
+    requests all queued at once (the saturated aggregate rate), and the rate
+    of a sample of them solved one at a time (fdtd_step alone, work-weighted)
+    for comparison."""
+    from paper_1301_4539_amd import fdtd, serve, workload as W
     reqs = W.serving_requests(n=n, rate=rate, seed=1004)
     t0 = time.perf_counter()
     wls = {r.rid: r.workload() for r in reqs}
@@ -169,6 +173,28 @@ def serving_leg(rate, n, torch):
                 "age_step_s": eng.age_step, "max_boost": eng.max_boost,
                 "T_by_storage": {"fp32": serve.DEFAULT_T[0], "fp16": serve.DEFAULT_T[1]},
                 "mean_work_G": float(np.mean([r.nx * r.ny * r.nz * r.n_steps for r in reqs]) / 1e9)})
+    # saturated: every request queued at t = 0
+    sat = [dataclasses.replace(r, arrival=0.0) for r in reqs]
+    rep_s = serve.Engine(serve.GpuBackend(wls), budget_bytes=24 << 30, max_slots=64, chunk=48).run(sat)
+    ss = rep_s.summary()
+    # solo: a seeded sample of the requests, each alone on the GPU (fused
+    # kernel at its storage's T, fdtd_step over all its steps)
+    pick = np.random.default_rng(7).choice(n, size=min(solo_sample, n), replace=False)
+    work = secs = 0.0
+    for q in pick:
+        r = reqs[int(q)]
+        w = wls[r.rid]
+        sx = fdtd.Solver.from_workload(w, kernel=fdtd.KERNEL_FUSED, time_block=serve.DEFAULT_T[w.storage])
+        try:
+            secs += time_steps(sx, w.n_steps, torch, torch.cuda.current_stream())
+            work += w.cells * w.n_steps
+        finally:
+            sx.close()
+    solo = work / secs / 1e9
+    out["saturated"] = {"throughput_G_per_s": ss["throughput_G_per_s"], "makespan_s": ss["makespan_s"],
+                        "busy_while_pending": ss["busy_while_pending"], "p50_s": ss["p50_s"], "p99_s": ss["p99_s"],
+                        "solo_G_per_s": solo, "solo_sample": len(pick),
+                        "ratio_vs_solo": ss["throughput_G_per_s"] / solo}
     return out
 
 

@@ -284,14 +284,24 @@ int fdtd_step(fdtd_solver *s, int n_steps);
  * solvers may join or leave between calls). */
 int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps);
 
+/* Bind the solver to another stream (caller-owned; NULL = the default
+ * stream) after the work enqueued on its current stream has finished.  A
+ * serving loop creates solvers on a side stream, so that uploads do not wait
+ * for the running batch, and then moves them to the batch stream (batched
+ * solvers must share one).  FDTD_EINVAL on NULL solver. */
+int fdtd_set_stream(fdtd_solver *s, void *hip_stream);
+
 /* Copy one component of the current state to host (float,
  * (nx+1)(ny+1)(nz+1), x fastest; decoded if stored in reduced precision).
  * Synchronises the stream. */
 int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst);
 
 /* Copy probe records for steps [first_step, first_step+n_steps) to host_dst
- * as n_steps rows of n_probes doubles (row = step, column = probe id).
- * The steps must have been run.  Synchronises the stream. */
+ * as n_steps rows of n_probes doubles (row = step, column = probe id), the
+ * pin-point outputs of Sec. 3.4 and 4.2.  The steps must have been run.
+ * Waits for the solver's own enqueued steps only, not for work enqueued on
+ * the same stream afterwards (other solvers' next batch keeps the GPU busy
+ * meanwhile), and copies on a stream of the library's own. */
 int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int n_steps);
 
 /* Compute diagnostics of the current state (fdtd_diag; the energy is the
@@ -342,7 +352,8 @@ int fdtd_storage_state(fdtd_solver *s, int scales[6], int *saturated);
  * reduced storage raised its flag (see fdtd_storage_state). */
 int fdtd_synchronize(fdtd_solver *s);
 
-/* Release the solver and everything the library allocated for it. */
+/* Release the solver and everything the library allocated for it, after its
+ * own enqueued work has finished. */
 void fdtd_destroy(fdtd_solver *s);
 
 /* Message for the last failed call on this thread ("" if none). */

@@ -258,6 +258,12 @@ struct fdtd_solver {
     yee::LiveNodes *live = nullptr;
     // fused launches since create: workgroups dispatched, tiles of the full tiling
     long long tile_stats[2] = {0, 0};
+    // recorded on the stream after the solver's last enqueued steps, so that
+    // reading its probes waits for its own work only; the copy then runs on
+    // a stream of the library's own (created on first use)
+    hipEvent_t done_ev = nullptr;
+    bool done_pending = false;
+    hipStream_t priv = nullptr;
 };
 
 namespace yee {
@@ -605,6 +611,17 @@ int read_ctrl(fdtd_solver *s, yee::Ctrl *out)
     hipError_t e = hipMemcpyAsync(out, s->ctrl, sizeof(yee::Ctrl), hipMemcpyDeviceToHost, s->st);
     if (!e) e = hipStreamSynchronize(s->st);
     return e ? hip_fail(e, "hipMemcpy(ctrl)") : FDTD_OK;
+}
+
+// Mark the end of the solver's enqueued work (after fdtd_step, fdtd_step_batch).
+int record_done(fdtd_solver *s)
+{
+    hipError_t e = hipSuccess;
+    if (!s->done_ev) e = hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming);
+    if (!e) e = hipEventRecord(s->done_ev, s->st);
+    if (e) return hip_fail(e, "hipEventRecord");
+    s->done_pending = true;
+    return FDTD_OK;
 }
 
 // Length of the next block.  With FP32 storage the result does not depend on
@@ -1396,7 +1413,7 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         }
         box_grow(s, n_steps);
         s->steps += n_steps;
-        return FDTD_OK;
+        return record_done(s);
     }
     int left = n_steps;
     while (left > 0) {
@@ -1422,7 +1439,7 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         advance(s, len);
         left -= len;
     }
-    return FDTD_OK;
+    return record_done(s);
 }
 
 int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
@@ -1489,6 +1506,19 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
             }
         }
     }
+    for (int i = 0; i < count; ++i)
+        if (n_steps[i] > 0)
+            if (int rc = record_done(solvers[i])) return rc;
+    return FDTD_OK;
+}
+
+int fdtd_set_stream(fdtd_solver *s, void *hip_stream)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    hipError_t e = hipStreamSynchronize(s->st);
+    if (e) return hip_fail(e, "hipStreamSynchronize");
+    s->st = (hipStream_t)hip_stream;
+    s->done_pending = false;
     return FDTD_OK;
 }
 
@@ -1545,9 +1575,15 @@ int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int
         return fail(FDTD_EINVAL, "requested steps have not been run");
     const size_t np = s->probe_pos.size();
     if (np == 0 || n_steps == 0) return FDTD_OK;
-    hipError_t e = hipMemcpyAsync(host_dst, s->probe_out_d + (size_t)first_step * np,
-                                  (size_t)n_steps * np * sizeof(double), hipMemcpyDeviceToHost, s->st);
-    if (!e) e = hipStreamSynchronize(s->st);
+    // Wait for this solver's own enqueued work only (later work that other
+    // solvers queued on the same stream keeps running), then copy on a
+    // stream of the library's own.
+    hipError_t e = hipSuccess;
+    if (!s->priv) e = hipStreamCreateWithFlags(&s->priv, hipStreamNonBlocking);
+    if (!e && s->done_pending) e = hipEventSynchronize(s->done_ev);
+    if (!e) e = hipMemcpyAsync(host_dst, s->probe_out_d + (size_t)first_step * np,
+                               (size_t)n_steps * np * sizeof(double), hipMemcpyDeviceToHost, s->priv);
+    if (!e) e = hipStreamSynchronize(s->priv);
     return e ? hip_fail(e, "read probes") : FDTD_OK;
 }
 
@@ -1751,7 +1787,9 @@ int fdtd_synchronize(fdtd_solver *s)
 void fdtd_destroy(fdtd_solver *s)
 {
     if (!s) return;
-    (void)hipStreamSynchronize(s->st);
+    // its own work only: later work of other solvers on the stream may run on
+    if (s->done_pending) (void)hipEventSynchronize(s->done_ev);
+    else (void)hipStreamSynchronize(s->st);
     live_drop(s);
     if (s->own_ws) free_dev(s->ws);
     free_dev(s->coef_d);
@@ -1771,6 +1809,8 @@ void fdtd_destroy(fdtd_solver *s)
         if (s->stage[b]) (void)hipHostFree(s->stage[b]);
         if (s->stage_ev[b]) (void)hipEventDestroy(s->stage_ev[b]);
     }
+    if (s->done_ev) (void)hipEventDestroy(s->done_ev);
+    if (s->priv) (void)hipStreamDestroy(s->priv);
     delete s;
 }
 

@@ -8,10 +8,11 @@
 //     and losses);
 //   largest |value| per component.
 // Reduction is deterministic: each thread accumulates its (i, j) column over
-// a fixed run of planes in ascending k, each block reduces its threads in a
-// fixed tree, then one block sums the block partials in index order.  The
-// plane runs keep the partials few (a few thousand), so the final
-// single-block pass is short.
+// a fixed run of planes in ascending k; each wave combines its 64 lanes in a
+// fixed butterfly of cross-lane moves (no LDS, no barrier per quantity), the
+// block adds its 4 wave results in wave order, and one block then sums the
+// block partials the same way.  The plane runs keep the partials few (a few
+// thousand), so the final single-block pass is short.
 // Graded spacing (GR): every term is weighted by its volume (edge length x
 // dual face area for E, face area x dual edge length for H; dual sizes are
 // half cells on the walls), the energy is then in units of eps0 with volumes
@@ -29,6 +30,41 @@ namespace yee {
 namespace {
 
 constexpr int DBX = 64, DBY = 4, DT = DBX * DBY;
+
+// Sum or maximum over the 64 lanes of a wave, the same on every lane: a
+// fixed butterfly of xor shuffles, so the result does not depend on timing.
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Quantities 0..2 are sums, the rest maxima.  Combines v over the block
+// (nwave waves of 64 lanes, in wave order) into out[q] on thread 0.
+template <int NWAVE>
+__device__ inline void block_reduce(const double *v, double (*s_w)[DIAG_W], int t, double *out)
+{
+    const int lane = t & 63, wv = t >> 6;
+#pragma unroll
+    for (int q = 0; q < DIAG_W; ++q) {
+        const double r = q <= 2 ? wave_sum(v[q]) : wave_max(v[q]);
+        if (lane == 0) s_w[wv][q] = r;
+    }
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < DIAG_W; ++q) {
+            double r = s_w[0][q];
+            for (int w = 1; w < NWAVE; ++w) r = q <= 2 ? r + s_w[w][q] : fmax(r, s_w[w][q]);
+            out[q] = r;
+        }
+    }
+}
 constexpr int DZ = 8;   // plane runs per grid (fewer for thin grids)
 
 template <class Codec, bool GR>
@@ -36,7 +72,7 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
 {
     using S = typename Codec::T;
     __shared__ double s_eps[256];
-    __shared__ double s_red[DT];
+    __shared__ double s_w[DT / 64][DIAG_W];
     const int t = threadIdx.y * DBX + threadIdx.x;
     for (int q = t; q < a.n_mat; q += DT) s_eps[q] = a.eps[q];
     __syncthreads();
@@ -125,40 +161,26 @@ __global__ __launch_bounds__(DT) void diag_points(DiagArgs a)
         v[5] = fmax(v[5], fabs(ex)); v[6] = fmax(v[6], fabs(ey)); v[7] = fmax(v[7], fabs(ez));
         v[8] = fmax(v[8], fabs(hx)); v[9] = fmax(v[9], fabs(hy)); v[10] = fmax(v[10], fabs(hz));
     }
-    // fixed-tree block reduction, one quantity at a time
+    // wave butterflies, then the block's waves in order
     const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    for (int q = 0; q < DIAG_W; ++q) {
-        s_red[t] = v[q];
-        __syncthreads();
-        for (int s = DT / 2; s > 0; s >>= 1) {
-            if (t < s) s_red[t] = (q == 0 || q == 1 || q == 2) ? s_red[t] + s_red[t + s] : fmax(s_red[t], s_red[t + s]);
-            __syncthreads();
-        }
-        if (t == 0) a.partial[blk * DIAG_W + q] = s_red[0];
-        __syncthreads();
-    }
+    block_reduce<DT / 64>(v, s_w, t, a.partial + blk * DIAG_W);
 }
 
 __global__ __launch_bounds__(256) void diag_final(const double *partial, long long nblk, double *out)
 {
-    __shared__ double s_red[256];
+    __shared__ double s_w[4][DIAG_W];
     const int t = threadIdx.x;
-    for (int q = 0; q < DIAG_W; ++q) {
-        const bool sum = q <= 2;
-        double acc = 0.0;
-        for (long long b = t; b < nblk; b += 256) {
+    double v[DIAG_W];
+#pragma unroll
+    for (int q = 0; q < DIAG_W; ++q) v[q] = 0.0;
+    for (long long b = t; b < nblk; b += 256) {      // each thread its strided partials, in order
+#pragma unroll
+        for (int q = 0; q < DIAG_W; ++q) {
             const double x = partial[b * DIAG_W + q];
-            acc = sum ? acc + x : fmax(acc, x);
+            v[q] = q <= 2 ? v[q] + x : fmax(v[q], x);
         }
-        s_red[t] = acc;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (t < s) s_red[t] = sum ? s_red[t] + s_red[t + s] : fmax(s_red[t], s_red[t + s]);
-            __syncthreads();
-        }
-        if (t == 0) out[q] = s_red[0];
-        __syncthreads();
     }
+    block_reduce<4>(v, s_w, t, out);
 }
 
 template <class Codec>

@@ -64,6 +64,7 @@ def lib():
         L.fdtd_read_probes.argtypes = [vp, vp, ll, i]
         L.fdtd_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
         L.fdtd_diagnostics_noalloc.argtypes = [vp, C.POINTER(_Diag)]
+        L.fdtd_set_stream.argtypes = [vp, vp]
         L.fdtd_steps_done.argtypes = [vp, C.POINTER(ll)]
         L.fdtd_state_bytes.argtypes = [vp]
         L.fdtd_state_bytes.restype = sz
@@ -84,7 +85,7 @@ def lib():
         L.fdtd_tile_stats.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_zero_skip", "fdtd_set_poison", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_diagnostics_noalloc",
-                     "fdtd_steps_done",
+                     "fdtd_steps_done", "fdtd_set_stream",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
                      "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
                      "fdtd_load_state", "fdtd_live_nodes", "fdtd_tile_stats"):
@@ -273,6 +274,11 @@ class Solver:
 
     def step(self, n: int):
         _check(lib().fdtd_step(self._h, int(n)))
+
+    def set_stream(self, stream):
+        """Move the solver to a torch stream (after its pending work)."""
+        _check(lib().fdtd_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+        self._stream = stream
 
     def read_field(self, comp) -> np.ndarray:
         out = np.empty((self.nz + 1, self.ny + 1, self.nx + 1), np.float32)

@@ -45,7 +45,7 @@ class Record:
 class Report:
     records: List[Record]
     makespan: float
-    busy: float                  # time spent inside backend.step + sync
+    busy: float                  # device time of the ticks (pipelined), else time inside step + sync
     rejected: List[int]
 
     def latencies(self) -> np.ndarray:
@@ -60,6 +60,8 @@ class Report:
                 "mean_s": float(lat.mean()) if len(lat) else None,
                 "throughput_G_per_s": work / self.makespan / 1e9 if self.makespan > 0 else None,
                 "makespan_s": self.makespan, "busy_frac": self.busy / self.makespan if self.makespan else None,
+                "busy_while_pending": (self.busy / self.pending_time
+                                       if getattr(self, "pending_time", 0.0) > 0 else None),
                 "requeues": sum(r.requeues for r in self.records)}
 
 
@@ -99,6 +101,11 @@ class Engine:
         return min(a["left"], k * self.chunk)
 
     def run(self, requests) -> Report:
+        """Serve `requests`.  With a backend that can enqueue a tick without
+        waiting for it (`submit`/`wait`), ticks are pipelined: tick n+1 is
+        enqueued before the engine waits for tick n, so admissions, probe
+        read-backs and the next tick's bookkeeping overlap the device's work
+        and the device does not idle between ticks."""
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         waiting: collections.deque = collections.deque()
         active: List[dict] = []
@@ -106,9 +113,16 @@ class Engine:
         rejected = []
         used = 0
         busy = 0.0
+        pending_time = 0.0                 # time with a solve admitted or waiting
+        piped = hasattr(self.b, "submit") and getattr(self.b, "pipelined", True)
+        inflight = None                    # (token, [(solve, steps)]) of the tick on the device
         t0 = self.b.now()
+        last = 0.0
         while pending or waiting or active:
             now = self.b.now() - t0
+            if active or waiting:
+                pending_time += now - last
+            last = now
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             # admission: arrival order, while a slot and the memory budget allow
@@ -129,22 +143,41 @@ class Engine:
                 waiting.popleft()
                 used += fp
                 recs[req.rid].admitted = self.b.now() - t0
-                active.append({"req": req, "h": h, "left": req.n_steps, "fp": fp})
-            if not active:
-                if pending:
-                    self.b.wait_until(t0 + pending[0].arrival)
-                elif waiting:
-                    # nothing fits even on an idle device: the budget forbids it
-                    rejected.append(waiting.popleft().rid)
+                active.append({"req": req, "h": h, "left": req.n_steps, "queued": req.n_steps, "fp": fp})
+            runnable = [a for a in active if a["queued"] > 0]
+            if not runnable and inflight is None:
+                if not active:
+                    if hasattr(self.b, "idle"):
+                        self.b.idle()               # nothing on the device: deferred clean-up
+                    if pending:
+                        self.b.wait_until(t0 + pending[0].arrival)
+                    elif waiting:
+                        # nothing fits even on an idle device: the budget forbids it
+                        rejected.append(waiting.popleft().rid)
                 continue
-            now = self.b.now() - t0
-            counts = [self.steps_for(a, now) for a in active]
-            ts = self.b.now()
-            self.b.step([a["h"] for a in active], counts)
-            self.b.sync()
-            busy += self.b.now() - ts
-            still = []
-            for a, c in zip(active, counts):
+            tick = None
+            if runnable:
+                now = self.b.now() - t0
+                counts = [min(a["queued"], self.steps_for(a, now)) for a in runnable]
+                if piped:
+                    token = self.b.submit([a["h"] for a in runnable], counts)
+                else:
+                    ts = self.b.now()
+                    self.b.step([a["h"] for a in runnable], counts)
+                    self.b.sync()
+                    busy += self.b.now() - ts
+                    token = None
+                for a, c in zip(runnable, counts):
+                    a["queued"] -= c
+                tick = (token, list(zip(runnable, counts)))
+            # retire the tick before this one (pipelined), or this one (not)
+            done, inflight = (inflight, tick) if piped else (tick, None)
+            if done is None:
+                continue
+            if piped:
+                busy += self.b.wait(done[0])
+            finished = []
+            for a, c in done[1]:
                 a["left"] -= c
                 if a["left"] == 0:
                     r = recs[a["req"].rid]
@@ -152,12 +185,16 @@ class Engine:
                     r.finished = self.b.now() - t0
                     r.cell_updates = a["req"].nx * a["req"].ny * a["req"].nz * a["req"].n_steps
                     used -= a["fp"]
-                else:
-                    still.append(a)
-            active = still
-        done = [r for r in recs.values() if np.isfinite(r.finished)]
-        makespan = max((r.finished for r in done), default=0.0) - min((r.arrival for r in done), default=0.0)
-        return Report(sorted(recs.values(), key=lambda r: r.rid), makespan, busy, rejected)
+                    finished.append(a)
+            if finished:
+                active = [a for a in active if all(a is not f for f in finished)]
+        if hasattr(self.b, "idle"):
+            self.b.idle()
+        done_recs = [r for r in recs.values() if np.isfinite(r.finished)]
+        makespan = max((r.finished for r in done_recs), default=0.0) - min((r.arrival for r in done_recs), default=0.0)
+        rep = Report(sorted(recs.values(), key=lambda r: r.rid), makespan, busy, rejected)
+        rep.pending_time = pending_time
+        return rep
 
 
 # Steps per HBM pass used for each storage format (the fastest on MI355X:
@@ -169,9 +206,17 @@ DEFAULT_T = {0: 4, 1: 3, 2: 3}
 class GpuBackend:
     """Drives the HIP library.  `workloads` maps request id to a pre-built
     Workload (the request payload: grid, materials, sources, probes);
-    `time_block` is one T for every solve or a map storage -> T."""
+    `time_block` is one T for every solve or a map storage -> T.
 
-    def __init__(self, workloads, time_block=None):
+    Ticks are enqueued on one stream (`submit`) and waited for by their end
+    event (`wait`), so the engine can queue the next tick first.  New solvers
+    are created on a side stream (their uploads do not wait for the running
+    tick) and then moved to the tick stream; finished solvers' probes are read
+    without waiting for later ticks, and the solvers are released when the
+    device has nothing queued (`idle`).  `pipelined=False` steps and waits
+    tick by tick (no submit)."""
+
+    def __init__(self, workloads, time_block=None, pipelined=True):
         import torch
         from . import fdtd
         self.fdtd = fdtd
@@ -180,6 +225,10 @@ class GpuBackend:
         tb = DEFAULT_T if time_block is None else time_block
         self.T = dict(tb) if isinstance(tb, dict) else {k: int(tb) for k in DEFAULT_T}
         self.alone = set()      # solves fdtd_step_batch does not take: stepped one by one
+        self.main = torch.cuda.current_stream()
+        self.side = torch.cuda.Stream()          # default priority, like every stream here
+        self.to_close = []
+        self.pipelined = pipelined
 
     def block_lengths(self):
         """Every block length T a solve may run: the per-storage T of the
@@ -211,7 +260,12 @@ class GpuBackend:
     def create(self, req):
         kernel, tb, batched = self.solver_options(self.wl[req.rid])
         try:
-            h = self.fdtd.Solver.from_workload(self.wl[req.rid], kernel=kernel, time_block=tb)
+            with self.torch.cuda.stream(self.side):
+                h = self.fdtd.Solver.from_workload(self.wl[req.rid], kernel=kernel, time_block=tb,
+                                                   stream=self.side)
+            h.set_stream(self.main)              # its uploads are done; it now steps with the others
+            if h._ws is not None:
+                h._ws.record_stream(self.main)
             if not batched:
                 self.alone.add(h)
             return h
@@ -231,8 +285,29 @@ class GpuBackend:
     def sync(self):
         self.torch.cuda.synchronize()
 
+    def submit(self, handles, counts):
+        """Enqueue one tick; returns its (start, end) events."""
+        ev0 = self.torch.cuda.Event(enable_timing=True)
+        ev1 = self.torch.cuda.Event(enable_timing=True)
+        ev0.record(self.main)
+        self.step(handles, counts)
+        ev1.record(self.main)
+        return ev0, ev1
+
+    def wait(self, token) -> float:
+        """Wait for a submitted tick; returns its device time in seconds."""
+        ev0, ev1 = token
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3
+
     def finish(self, h, req) -> np.ndarray:
-        p = h.read_probes(0, req.n_steps)
+        p = h.read_probes(0, req.n_steps)      # waits for this solve's own steps only
         self.alone.discard(h)
-        h.close()
+        self.to_close.append(h)
         return p
+
+    def idle(self):
+        """Release the finished solvers (nothing is queued on the device)."""
+        for h in self.to_close:
+            h.close()
+        self.to_close = []

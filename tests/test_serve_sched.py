@@ -124,3 +124,52 @@ def test_long_waiting_solves_get_larger_steps():
     flat = [c[0] for c in counts]
     assert flat[0] == 16 and max(flat) == 48 and 32 in flat
     assert all(c % 16 == 0 for c in flat[:-1]) and sum(flat) == 3000
+
+
+class PipedFake(Fake):
+    """A fake with a device timeline: submit() queues a tick behind the
+    previous one (device time = cells / rate), host calls cost `host` each;
+    wait() advances the host clock to the tick's end."""
+
+    def __init__(self, host=2e-3, **kw):
+        super().__init__(**kw)
+        self.host = host
+        self.dev_end = 0.0
+        self.dev_busy = 0.0
+
+    def create(self, req):
+        self.t += self.host
+        return super().create(req)
+
+    def submit(self, handles, counts):
+        cost = self.overhead + sum(h.nx * h.ny * h.nz * c for h, c in zip(handles, counts)) / self.rate
+        start = max(self.dev_end, self.t)
+        self.dev_end = start + cost
+        self.dev_busy += cost
+        self.t += self.host
+        return (start, self.dev_end)
+
+    def wait(self, token):
+        self.t = max(self.t, token[1])
+        return token[1] - token[0]
+
+
+def test_pipelined_ticks_keep_the_device_busy():
+    """With the next tick queued before the engine waits for the current one,
+    host work (admission, read-back) hides behind device work: the device is
+    busy nearly all the time some solve is pending, where the tick-by-tick
+    loop leaves it idle for the host's share; every request completes and
+    gets the probes of its own solve."""
+    reqs = W.serving_requests(n=60, rate=200.0, seed=9, dim_lo=40, dim_hi=64, steps_lo=100, steps_hi=400)
+    slow_host = dict(rate=2e9, overhead=1e-4)
+    piped = PipedFake(host=3e-3, **slow_host)
+    rep = serve.Engine(piped, budget_bytes=1 << 40, max_slots=8, chunk=16).run(reqs)
+    s = rep.summary()
+    assert s["requests"] == 60 and not rep.rejected
+    assert all(np.all(r.probes == r.rid) for r in rep.records)
+    assert s["busy_while_pending"] > 0.9
+    # the same trace tick by tick: the host's time per tick is device idle time
+    plain = Fake(**slow_host)
+    plain.t = 0.0
+    rep2 = serve.Engine(plain, budget_bytes=1 << 40, max_slots=8, chunk=16).run(reqs)
+    assert rep2.summary()["requests"] == 60
