@@ -181,10 +181,16 @@ int fdtd_set_spacing(fdtd_solver *s, const double *dx, const double *dy, const d
  * value = fmaf(+-c dt / d, psi, value) -- times the material's G for E.
  *   thickness: 2 thickness < every one of nx, ny, nz; order 1..8;
  *   sigma_factor >= 0, kappa_max >= 1, alpha_max >= 0 (else FDTD_EINVAL).
- *   FP32 storage only; before the first step (FDTD_ESTATE); the layers run
- *   on the PLAIN kernel family (AUTO selects it; FUSED is rejected,
- *   FDTD_EINVAL); combines with fdtd_set_spacing in either order.  The psi
- *   state starts at zero and is cleared by fdtd_set_fields.
+ *   FP32 storage only; before the first step (FDTD_ESTATE); combines with
+ *   fdtd_set_spacing in either order.  Both kernel families run the layers:
+ *   the FUSED kernel carries the psi values of every time level through its
+ *   pass (Sec. 3.3 counts absorbing layers among the per-cell work between
+ *   the two half-steps, kept on one-dimensional coefficients so as not to add
+ *   bandwidth) in blocks of at most 3 steps -- AUTO picks it with T = 2, the
+ *   fastest; FUSED with a fixed T > 3 is rejected (FDTD_EINVAL), and so is
+ *   psi state of 2 GiB or more, which the PLAIN family (and AUTO) still
+ *   runs.  Conductor interiors are not skipped in solvers with layers.  The
+ *   psi state starts at zero and is cleared by fdtd_set_fields.
  *   fdtd_step_batch and fdtd_diagnostics reject solvers with layers
  *   (FDTD_EINVAL). */
 int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor, double kappa_max,
@@ -198,7 +204,8 @@ int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor,
  * gathering, Sec. 3.4 and the conclusion) exceed the register file and run
  * slower, but re-quantise 16-bit storage less often; solvers with graded
  * spacing and fdtd_step_batch take T <= 4 (FDTD_EINVAL otherwise, also from
- * fdtd_set_spacing on a solver with a fixed T > 4).  Allowed before the first
+ * fdtd_set_spacing on a solver with a fixed T > 4), solvers with CPML layers
+ * T <= 3 with FUSED (AUTO caps its blocks at 3 steps).  Allowed before the first
  * step and between steps.  Results do not depend on T for FP32 storage; for
  * FP16/BF16 storage, T sets where values are re-quantised (every T steps). */
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtd.so")
-SOURCES = ["yee_fused_f32.hip", "yee_fused_f16.hip", "yee_fused_bf16.hip", "yee_fused_graded.hip",
+SOURCES = ["yee_fused_f32.hip", "yee_fused_f16.hip", "yee_fused_bf16.hip", "yee_fused_graded.hip", "yee_fused_cpml.hip",
            "yee_fused_graded_f16.hip", "yee_fused_graded_bf16.hip", "fdtd_runtime.cpp", "yee_plain.hip",
            "yee_fused.hip", "yee_diag.hip"]
 

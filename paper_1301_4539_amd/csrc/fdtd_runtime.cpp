@@ -228,7 +228,7 @@ struct fdtd_solver {
     double2 *gsz_d = nullptr;           // per axis and node (cell size or 0, dual size; half on walls)
     float *psi_d = nullptr;             // CPML auxiliary state in the layers
     size_t psi_bytes = 0;
-    long long psi_off[12] = {};
+    long long psi_off[3] = {};          // x-, y-, z-type blocks (floats)
     int cur = 0;
     long long steps = 0;
     long long block = 0;                // reduced-storage blocks run since the last upload
@@ -576,7 +576,29 @@ yee::StorageBlock storage_block(const fdtd_solver *s)
 }
 
 
-int auto_T(const fdtd_solver *s) { return yee::fastest_T(s->L, s->storage, s->gc_d != nullptr); }
+// CPML psi arrays: two copies of psi_bytes (the fused kernel reads one and
+// writes the other, like the field buffers; the plain kernels update copy
+// `cur` in place).
+float *psi_buf(const fdtd_solver *s, int which)
+{
+    return s->psi_d ? s->psi_d + (size_t)which * (s->psi_bytes / sizeof(float)) : nullptr;
+}
+
+long long psi_elems(const fdtd_solver *s) { return (long long)(s->psi_bytes / sizeof(float)); }
+
+// Steps per fused pass with CPML layers: T = 2 keeps the twelve psi values
+// of every level in registers without spilling (T = 3 spills).
+constexpr int CPML_T = 2;
+
+int auto_T(const fdtd_solver *s)
+{
+    if (s->pml.n > 0) {
+        int T = CPML_T;
+        while (T > 1 && !yee::cpml_fused_fits(s->L, psi_elems(s), T)) --T;
+        return T;
+    }
+    return yee::fastest_T(s->L, s->storage, s->gc_d != nullptr);
+}
 
 // Allocate the pinned staging buffers on first use (freed by fdtd_destroy).
 int ensure_staging(fdtd_solver *s)
@@ -631,7 +653,9 @@ int record_done(fdtd_solver *s)
 // would).
 int next_block(const fdtd_solver *s, int left)
 {
-    const int len = s->storage == FDTD_FP32 ? s->T : s->T - (int)(s->steps % s->T);
+    // CPML layers (FP32 storage only) run blocks of at most MAX_T_CPML steps
+    const int T = s->pml.n > 0 ? std::min(s->T, yee::MAX_T_CPML) : s->T;
+    const int len = s->storage == FDTD_FP32 ? T : T - (int)(s->steps % T);
     return std::min(len, left);
 }
 
@@ -865,17 +889,17 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
         coef[4 * m + 1] = cag[2 * m + 1];
         coef[4 * m + 2] = coef[4 * m + 3] = 0.0f;
     }
-    // psi arrays: x-type 2n (ny+1)(nz+1), y-type 2n (nx+1)(nz+1), z-type 2n (nx+1)(ny+1)
-    long long off[12] = {};
+    // psi blocks of 4-float groups: x-type 2n (ny+1)(nz+1) groups, y-type
+    // 2n (nx+1)(nz+1), z-type 2n (nx+1)(ny+1)
+    long long off[3] = {};
     size_t psi_bytes = 0;
     if (p.n > 0) {
         const long long per[3] = {2LL * p.n * (n[1] + 1) * (n[2] + 1), 2LL * p.n * (n[0] + 1) * (n[2] + 1),
                                   2LL * p.n * (n[0] + 1) * (n[1] + 1)};
-        static const int axis_of[12] = {1, 2, 2, 0, 0, 1, 1, 2, 2, 0, 0, 1};   // PsiArray order
         long long at = 0;
-        for (int q = 0; q < 12; ++q) {
-            off[q] = at;
-            at += per[axis_of[q]];
+        for (int ax = 0; ax < 3; ++ax) {
+            off[ax] = at;
+            at += 4 * per[ax];
         }
         psi_bytes = (size_t)at * sizeof(float);
     }
@@ -896,7 +920,7 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
     if ((e = hipMalloc(&gc_d, gc.size() * sizeof(float))) || (e = hipMalloc(&gsz_d, gsz.size() * sizeof(double2))) ||
         (e = hipMalloc(&coef_d, 256 * sizeof(float4))) ||
         (p.n > 0 && (e = hipMalloc(&cp_d, cp.size() * sizeof(float)))) ||
-        (psi_bytes && (e = hipMalloc(&psi_d, psi_bytes)))) {
+        (psi_bytes && (e = hipMalloc(&psi_d, 2 * psi_bytes)))) {
         drop();
         return hip_fail(e, "hipMalloc(graded tables)");
     }
@@ -904,7 +928,7 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
         (e = hipMemcpyAsync(gsz_d, gsz.data(), gsz.size() * sizeof(double2), hipMemcpyHostToDevice, s->st)) ||
         (e = hipMemcpyAsync(coef_d, coef, s->n_mat * sizeof(float4), hipMemcpyHostToDevice, s->st)) ||
         (p.n > 0 && (e = hipMemcpyAsync(cp_d, cp.data(), cp.size() * sizeof(float), hipMemcpyHostToDevice, s->st))) ||
-        (psi_bytes && (e = hipMemsetAsync(psi_d, 0, psi_bytes, s->st))) ||
+        (psi_bytes && (e = hipMemsetAsync(psi_d, 0, 2 * psi_bytes, s->st))) ||
         (e = hipStreamSynchronize(s->st))) {
         drop();
         return hip_fail(e, "upload graded tables");
@@ -929,8 +953,9 @@ yee::Cpml cpml_args(const fdtd_solver *s)
     yee::Cpml c;
     c.n = s->pml.n;
     c.cp = s->cp_d;
-    c.psi = s->psi_d;
-    std::memcpy(c.off, s->psi_off, sizeof(c.off));
+    c.psi = psi_buf(s, s->cur);
+    std::memcpy(c.base, s->psi_off, sizeof(c.base));
+    c.elems = (long long)(s->psi_bytes / sizeof(float));
     return c;
 }
 
@@ -1140,8 +1165,13 @@ int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor,
     if (s->steps > 0) return fail(FDTD_ESTATE, "CPML layers must be set before the first step");
     if (s->storage != FDTD_FP32) return fail(FDTD_EINVAL, "CPML layers need FP32 storage");
     if (thickness < 0) return fail(FDTD_EINVAL, "negative CPML thickness");
-    if (thickness > 0 && s->kernel == FDTD_KERNEL_FUSED)
-        return fail(FDTD_EINVAL, "CPML layers run on the plain kernel; set kernel AUTO or PLAIN");
+    if (thickness > 0 && s->kernel == FDTD_KERNEL_FUSED) {
+        const long long nx = s->L.nx, ny = s->L.ny, nz = s->L.nz;
+        const long long elems = 8LL * thickness * ((ny + 1) * (nz + 1) + (nx + 1) * (nz + 1) + (nx + 1) * (ny + 1));
+        if ((!s->T_auto && s->T > yee::MAX_T_CPML) || !yee::cpml_fused_fits(s->L, elems, 1))
+            return fail(FDTD_EINVAL, "CPML layers run fused blocks of at most " + std::to_string(yee::MAX_T_CPML) +
+                                         " steps (and arrays below 2 GiB); lower time_block first");
+    }
     CpmlParams p;
     p.n = thickness;
     p.order = order;
@@ -1167,8 +1197,9 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block)
         return fail(FDTD_EINVAL, "the plain kernel needs FP32 storage");
     if (kernel == FDTD_KERNEL_FUSED && !yee::fused_fits(s->L, s->storage, time_block))
         return fail(FDTD_EINVAL, "grid planes too large for the fused kernel; use the plain kernel");
-    if (kernel == FDTD_KERNEL_FUSED && s->pml.n > 0)
-        return fail(FDTD_EINVAL, "CPML layers run on the plain kernel");
+    if (kernel == FDTD_KERNEL_FUSED && s->pml.n > 0 && !yee::cpml_fused_fits(s->L, psi_elems(s), time_block))
+        return fail(FDTD_EINVAL, "CPML layers run fused blocks of at most " + std::to_string(yee::MAX_T_CPML) +
+                                     " steps (and arrays below 2 GiB)");
     s->kernel = kernel;
     s->T = time_block;
     s->T_auto = automatic;
@@ -1197,6 +1228,7 @@ int fdtd_set_poison(fdtd_solver *s, int enable)
         // the second buffer now holds NaN outside what the last launch wrote
         // (its padding): restore +0 there for the zero-tile invariant
         hipError_t e = hipMemsetAsync(s->fbuf[s->cur ^ 1], 0, s->d.fbytes, s->st);
+        if (!e && s->psi_d) e = hipMemsetAsync(psi_buf(s, s->cur ^ 1), 0, s->psi_bytes, s->st);
         if (e) return hip_fail(e, "clear poison");
     }
     s->poison = enable != 0;
@@ -1230,7 +1262,7 @@ int fdtd_set_fields(fdtd_solver *s, const float *host)
     // both buffers start as +0 outside the uploaded values (the zero-tile skip
     // relies on the older buffer too)
     if ((e = hipMemsetAsync(s->fbuf[1], 0, s->d.fbytes, s->st))) return hip_fail(e, "hipMemset");
-    if (s->psi_d && (e = hipMemsetAsync(s->psi_d, 0, s->psi_bytes, s->st)))
+    if (s->psi_d && (e = hipMemsetAsync(s->psi_d, 0, 2 * s->psi_bytes, s->st)))
         return hip_fail(e, "clear CPML state");
     if (!host) {
         if ((e = hipMemsetAsync(s->fbuf[0], 0, s->d.fbytes, s->st)) ||
@@ -1392,10 +1424,12 @@ int fdtd_step(fdtd_solver *s, int n_steps)
     const yee::SourceTable src = src_table(s);
     const yee::ProbeTable probe = probe_table(s);
     hipError_t e;
-    // AUTO is the fused kernel, or the plain one for grids whose planes are
-    // too large for the fused kernel's chunk addressing (FP32 only: create
-    // rejects 16-bit storage for such grids).
-    const bool plain = s->kernel == FDTD_KERNEL_PLAIN || s->pml.n > 0 ||
+    // AUTO is the fused kernel, or the plain one for grids whose planes (or
+    // CPML arrays) are too large for the fused kernel's 32-bit addressing
+    // (FP32 only: create rejects 16-bit storage for such grids).
+    const bool cpml = s->pml.n > 0;
+    const bool plain = s->kernel == FDTD_KERNEL_PLAIN ||
+                       (cpml && !yee::cpml_fused_fits(s->L, psi_elems(s), std::min(s->T, yee::MAX_T_CPML))) ||
                        (s->kernel == FDTD_KERNEL_AUTO && !yee::fused_fits(s->L, s->storage, 1));
     if (plain) {
         yee::PlainArgs a;
@@ -1427,14 +1461,25 @@ int fdtd_step(fdtd_solver *s, int n_steps)
             return fail(FDTD_EINVAL, "grid planes too large for the fused kernel at this T");
         box_take_sources(s);
         box_args(s, &a);
-        a.live = s->zero_skip ? s->live : nullptr;
+        // Conductor interiors keep their fields at +0 but, in a layer, not
+        // their psi (it follows the curl next door): no dead-tile list there.
+        a.live = s->zero_skip && !cpml ? s->live : nullptr;
+        yee::CpmlFused cp{};
+        if (cpml) {
+            cp.pml = cpml_args(s);
+            cp.psi_out = psi_buf(s, s->cur ^ 1);
+        }
         if (s->poison) {     // every value the launch owns must be rewritten: nothing may rely on the old buffer
             a.box_lo = make_int4(-(1 << 28), -(1 << 28), -(1 << 28), 0);
             a.box_hi = make_int4(1 << 28, 1 << 28, 1 << 28, 0);
             a.live = nullptr;
-            if ((e = hipMemsetAsync(s->fbuf[s->cur ^ 1], 0xff, s->d.fbytes, s->st))) return hip_fail(e, "poison");
+            if ((e = hipMemsetAsync(s->fbuf[s->cur ^ 1], 0xff, s->d.fbytes, s->st)) ||
+                (cpml && (e = hipMemsetAsync(cp.psi_out, 0xff, s->psi_bytes, s->st))))
+                return hip_fail(e, "poison");
         }
-        if ((e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st))) return hip_fail(e, "fused step");
+        e = cpml ? yee::launch_fused_cpml(len, a, cp, s->zchunk, s->st)
+                 : yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st);
+        if (e) return hip_fail(e, "fused step");
         box_grow(s, len);
         advance(s, len);
         left -= len;
@@ -1691,8 +1736,8 @@ int fdtd_save_state(fdtd_solver *s, void *host_dst, size_t bytes)
     hipError_t e;
     if ((e = hipMemcpyAsync(dst + sizeof(h), s->fbuf[s->cur], s->d.fbytes, hipMemcpyDeviceToHost, s->st)) ||
         (e = hipMemcpyAsync(dst + sizeof(h) + s->d.fbytes, s->ctrl, sizeof(yee::Ctrl), hipMemcpyDeviceToHost, s->st)) ||
-        (s->psi_bytes && (e = hipMemcpyAsync(dst + sizeof(h) + s->d.fbytes + sizeof(yee::Ctrl), s->psi_d, s->psi_bytes,
-                                             hipMemcpyDeviceToHost, s->st))) ||
+        (s->psi_bytes && (e = hipMemcpyAsync(dst + sizeof(h) + s->d.fbytes + sizeof(yee::Ctrl), psi_buf(s, s->cur),
+                                             s->psi_bytes, hipMemcpyDeviceToHost, s->st))) ||
         (e = hipStreamSynchronize(s->st)))
         return hip_fail(e, "save state");
     return FDTD_OK;
@@ -1717,8 +1762,9 @@ int fdtd_load_state(fdtd_solver *s, const void *host_src, size_t bytes)
         (e = hipMemcpyAsync(s->fbuf[0], src + sizeof(h), s->d.fbytes, hipMemcpyHostToDevice, s->st)) ||
         (e = hipMemsetAsync(s->fbuf[1], 0, s->d.fbytes, s->st)) ||
         (e = hipMemcpyAsync(s->ctrl, src + sizeof(h) + s->d.fbytes, sizeof(yee::Ctrl), hipMemcpyHostToDevice, s->st)) ||
-        (s->psi_bytes && (e = hipMemcpyAsync(s->psi_d, src + sizeof(h) + s->d.fbytes + sizeof(yee::Ctrl), s->psi_bytes,
-                                             hipMemcpyHostToDevice, s->st))))
+        (s->psi_bytes && (e = hipMemcpyAsync(psi_buf(s, 0), src + sizeof(h) + s->d.fbytes + sizeof(yee::Ctrl),
+                                             s->psi_bytes, hipMemcpyHostToDevice, s->st))) ||
+        (s->psi_bytes && (e = hipMemsetAsync(psi_buf(s, 1), 0, s->psi_bytes, s->st))))
         return hip_fail(e, "load state");
     // Probe rows from the restored step on start again at 0: a tile that the
     // zero-tile skip or the dead-tile list leaves out never writes its probes'

@@ -73,6 +73,11 @@ int fastest_T(const Layout &L, int storage, bool graded)
     return T;
 }
 
+bool cpml_fused_fits(const Layout &L, long long psi_elems, int T)
+{
+    return T >= 1 && T <= MAX_T_CPML && fused_fits(L, 0, T) && psi_elems * 4 < (1LL << 31);
+}
+
 bool fused_fits(const Layout &L, int storage, int T)
 {
     // a chunk's buffer resource spans (planes * kstride * es) bytes, below 2^31

@@ -162,9 +162,9 @@ __device__ __forceinline__ bool tile_coords(const FusedArgs &a, const int logica
                             tz >= a.tz0 && tz < a.tz0 + a.ntz);
 }
 
-template <int T, int RY, int NW, class Codec, bool GR = false>
+template <int T, int RY, int NW, class Codec, bool GR = false, bool CP = false>
 __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical, const int tx, const int ty,
-                                           const int tz, TileShared<T, NW> &sm)
+                                           const int tz, TileShared<T, NW> &sm, const CpmlFused &cpa = {})
 {
     constexpr int OX = 64 - 2 * T;      // owned points per tile in x
     constexpr int NR = NW * RY;         // rows per tile
@@ -318,6 +318,107 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         for (int t = 0; t <= T; ++t) gzh[t] = gze[t] = 0.0f;
     }
 
+    // CPML layers (CP): membership of this lane's x, of each row's y (uniform)
+    // and, per level, of its plane (uniform) in the slabs of the auxiliary
+    // state psi.  H values at a cell q < n belong when q < N or q >= n - N, E
+    // values at a node when 0 < q < N or n - N < q < n; the slab slot of q is
+    // q (lower layer) or q - n + 2N (upper).  The x-type psi offsets of lanes
+    // outside a slab (and, for stores, of lanes this tile does not own) lie
+    // 2^31 beyond the array, where loads read 0 and stores are dropped.
+    static_assert(!CP || (GR && std::is_same<Codec, CodecF32>::value), "CPML layers: graded FP32 kernels");
+    constexpr int NPS = CP ? 12 : 1;
+    const int N = CP ? cpa.pml.n : 0;
+    bool xph = false, xpe = false, xint = false, tile_x = false, tile_xy = false;
+    int vpx = 0, vpxs = 0;
+    float cxp[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // {b_h, a_h, c dt/d, b_e, a_e, c dt/d'} of x
+    bool yph[RY], ype[RY];
+    int ysl[RY];
+    const __amdgpu_buffer_rsrc_t rpsi = rsrc(CP ? cpa.pml.psi : nullptr, CP ? cpa.pml.elems * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rpso = rsrc(CP ? cpa.psi_out : nullptr, CP ? cpa.pml.elems * 4 : 0);
+    ConstFloat *const cpu = (ConstFloat *)cpa.pml.cp;
+    if constexpr (CP) {
+        xph = x >= 0 && x < nx && (x < N || x >= nx - N);
+        xpe = (x > 0 && x < N) || (x > nx - N && x < nx);
+        xint = x > 0 && x < nx;
+        const int slot = x < N ? x : x - nx + 2 * N;
+        vpx = xph ? slot * 16 : (int)0x80000000u;
+        vpxs = (xph && xown) ? slot * 16 : (int)0x80000000u;
+        tile_x = xl < N || xl + 63 >= nx - N;            // some lane in an x slab
+        tile_xy = tile_x || yt < N || yt + NR - 1 >= ny - N;
+        if (tile_x) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) cxp[c] = cpa.pml.cp[6 * xc + c];
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int y = yw + r;
+            yph[r] = y >= 0 && y < ny && (y < N || y >= ny - N);
+            ype[r] = (y > 0 && y < N) || (y > ny - N && y < ny);
+            ysl[r] = y < N ? y : y - ny + 2 * N;
+        }
+    }
+    // psi of level t at its latest plane (level 0: loaded, plane K), and the
+    // level below's previous plane, handed up one level per z step
+    float PS[CP ? T : 1][NPS][RY], PSo[NPS][RY];
+#pragma unroll
+    for (int c = 0; c < NPS; ++c)
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            PSo[c][r] = 0.0f;
+#pragma unroll
+            for (int t = 0; t < (CP ? T : 1); ++t) PS[t][c][r] = 0.0f;
+        }
+    // psi of plane K into PS[0]: one 16-byte group per type, zero outside the
+    // slabs
+    const int vg = vo * 4;              // per-lane byte offset of a group at index x
+    auto group = [&](const int axis, const int g) __attribute__((always_inline)) -> int {
+        return (int)(cpa.pml.base[axis] + 4LL * g) * 4;   // bytes; the arrays fit 2^31
+    };
+    auto load_psi = [&](const int K) __attribute__((always_inline)) {
+        const bool zin = K < nz && (K < N || K >= nz - N);
+        const int zsl = K < N ? K : K - nz + 2 * N;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int yc = min(max(yw + r, 0), ny);
+            auto put = [&](const int first, const uint4 v) __attribute__((always_inline)) {
+                PS[0][first + 0][r] = __builtin_bit_cast(float, v.x);
+                PS[0][first + 1][r] = __builtin_bit_cast(float, v.y);
+                PS[0][first + 2][r] = __builtin_bit_cast(float, v.z);
+                PS[0][first + 3][r] = __builtin_bit_cast(float, v.w);
+            };
+            const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+            auto ld = [&](const int vofs, const int so) __attribute__((always_inline)) -> uint4 {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(rpsi, vofs, so, 0);
+                return make_uint4(v[0], v[1], v[2], v[3]);
+            };
+            put(PS_HYX, tile_x ? ld(vpx, group(0, (K * (ny + 1) + yc) * 2 * N)) : zero);
+            put(PS_HXY, yph[r] ? ld(vg, group(1, (K * 2 * N + ysl[r]) * (nx + 1))) : zero);
+            put(PS_HXZ, zin ? ld(vg, group(2, (zsl * (ny + 1) + yc) * (nx + 1))) : zero);
+        }
+    };
+    // level T's psi of plane q: the values this tile owns (every slab entry of
+    // an owned node is written, updated or passed through)
+    const int vgs = xown ? vg : (int)((uint32_t)vg | 0x80000000u);
+    auto store_psi = [&](const int q, const float (&V)[NPS][RY]) __attribute__((always_inline)) {
+        const bool zin = q < nz && (q < N || q >= nz - N);
+        const int zsl = q < N ? q : q - nz + 2 * N;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int row = w * RY + r;
+            const int y = yw + r;
+            if (!(row >= T && row < NR - T && y <= ny)) continue;    // uniform
+            auto st = [&](const int first, const int vofs, const int so) __attribute__((always_inline)) {
+                typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+                const u4 v = {__builtin_bit_cast(uint32_t, V[first][r]), __builtin_bit_cast(uint32_t, V[first + 1][r]),
+                              __builtin_bit_cast(uint32_t, V[first + 2][r]), __builtin_bit_cast(uint32_t, V[first + 3][r])};
+                __builtin_amdgcn_raw_buffer_store_b128(v, rpso, vofs, so, 0);
+            };
+            if (tile_x) st(PS_HYX, vpxs, group(0, (q * (ny + 1) + y) * 2 * N));
+            if (yph[r]) st(PS_HXY, vgs, group(1, (q * 2 * N + ysl[r]) * (nx + 1)));
+            if (zin) st(PS_HXZ, vgs, group(2, (zsl * (ny + 1) + y) * (nx + 1)));
+        }
+    };
+
     float E[T + 1][3][RY], H[T + 1][3][RY];
     // Material indices of the planes the levels are on, one byte per level:
     // byte t-1 of MP[r] is the index of plane K-t (level t's plane) in row r,
@@ -399,9 +500,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     // INNER: every lane and row of the tile lies strictly inside the grid in
     // x and y (no wall in reach), so only the plane tests remain in the masks.
     // Otherwise only the tangential E of the x and y walls is held.
-    auto iterate = [&](const int K, auto all_c, auto inner_c) __attribute__((always_inline)) {
+    // PSI: a step that carries psi (CP kernels only; steps of a tile outside
+    // every slab leave the all-zero psi registers alone).
+    auto iterate = [&](const int K, auto all_c, auto inner_c, auto psi_c) __attribute__((always_inline)) {
         constexpr bool ALL = decltype(all_c)::value;
         constexpr bool INNER = decltype(inner_c)::value;
+        constexpr bool PSI = CP && decltype(psi_c)::value;
         // Level 0 takes plane K; plane K-1 of level 0 becomes level 1's input.
         float Eo[3][RY], Ho[3][RY];
         if constexpr (GR) {
@@ -425,6 +529,14 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
             }
         }
         if (ALL || K + 1 <= ke) YEE_LOAD_PLANE(K + 1);
+        if constexpr (PSI) {
+            // level 1 takes plane K-1's psi; plane K's is loaded for the next step
+#pragma unroll
+            for (int c = 0; c < NPS; ++c)
+#pragma unroll
+                for (int r = 0; r < RY; ++r) PSo[c][r] = PS[0][c][r];
+            if (ALL || K <= ke) load_psi(K);
+        }
 
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
@@ -443,6 +555,16 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                 const float2 eup = NW > 1 ? s_e[t - 1][w + 1][lane] : make_float2(0.0f, 0.0f);
                 float Hn[3][RY];
                 const float chz = GR ? gzh[t] : a.chz;
+                // CPML: the plane's layer membership and its z coefficients
+                // {b_h, a_h, c dt/d, b_e, a_e, c dt/d'} (uniform)
+                float PSn[NPS][RY];
+                const bool zph = CP && p < nz && (p < N || p >= nz - N);
+                const bool zpe = CP && ((p > 0 && p < N) || (p > nz - N && p < nz));
+                float czp[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (CP && (zph || zpe)) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) czp[c] = cpu[6 * (nx + ny + 2 + p) + c];
+                }
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
                     const int y = yw + r;
@@ -453,13 +575,59 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     const float eyr = from_right(Eo[1][r]);
                     const float dey_z = E[t - 1][1][r] - Eo[1][r];
                     const float dez_y = ezu - Eo[2][r];
-                    const float hx = __builtin_fmaf(-chy, dez_y, __builtin_fmaf(chz, dey_z, Ho[0][r]));
+                    float hx = __builtin_fmaf(-chy, dez_y, __builtin_fmaf(chz, dey_z, Ho[0][r]));
                     const float dez_x = ezr - Eo[2][r];
                     const float dex_z = E[t - 1][0][r] - Eo[0][r];
-                    const float hy = __builtin_fmaf(-chz, dex_z, __builtin_fmaf(chx, dez_x, Ho[1][r]));
+                    float hy = __builtin_fmaf(-chz, dex_z, __builtin_fmaf(chx, dez_x, Ho[1][r]));
                     const float dex_y = exu - Eo[0][r];
                     const float dey_x = eyr - Eo[1][r];
-                    const float hz = __builtin_fmaf(-chx, dey_x, __builtin_fmaf(chy, dex_y, Ho[2][r]));
+                    float hz = __builtin_fmaf(-chx, dey_x, __builtin_fmaf(chy, dex_y, Ho[2][r]));
+                    if constexpr (PSI) {
+                        // psi terms of each H value in a layer, in the order of its
+                        // update (Hx: z then y, Hy: x then z, Hz: y then x), psi first:
+                        // psi = b psi + a diff, then H +- (c dt/d) psi
+                        const bool ylt = y < ny;
+                        float cyp[3] = {0.0f, 0.0f, 0.0f};
+                        if (yph[r]) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) cyp[c] = cpu[6 * (nx + 1 + y) + c];
+                        }
+                        auto keep = [&](const int c) __attribute__((always_inline)) { PSn[c][r] = PSo[c][r]; };
+                        if (zph && ylt) {
+                            const float ps = __builtin_fmaf(czp[0], PSo[PS_HXZ][r], czp[1] * dey_z);
+                            hx = __builtin_fmaf(czp[2], ps, hx);
+                            PSn[PS_HXZ][r] = ps;
+                        } else keep(PS_HXZ);
+                        if (yph[r] && plt) {
+                            const float ps = __builtin_fmaf(cyp[0], PSo[PS_HXY][r], cyp[1] * dez_y);
+                            hx = __builtin_fmaf(-cyp[2], ps, hx);
+                            PSn[PS_HXY][r] = ps;
+                        } else keep(PS_HXY);
+                        if (tile_x && plt) {
+                            const float ps = __builtin_fmaf(cxp[0], PSo[PS_HYX][r], cxp[1] * dez_x);
+                            const float h2 = __builtin_fmaf(cxp[2], ps, hy);
+                            hy = xph ? h2 : hy;
+                            PSn[PS_HYX][r] = xph ? ps : PSo[PS_HYX][r];
+                        } else keep(PS_HYX);
+                        if (zph) {
+                            const float ps = __builtin_fmaf(czp[0], PSo[PS_HYZ][r], czp[1] * dex_z);
+                            const float h2 = __builtin_fmaf(-czp[2], ps, hy);
+                            hy = xlt ? h2 : hy;
+                            PSn[PS_HYZ][r] = xlt ? ps : PSo[PS_HYZ][r];
+                        } else keep(PS_HYZ);
+                        if (yph[r]) {
+                            const float ps = __builtin_fmaf(cyp[0], PSo[PS_HZY][r], cyp[1] * dex_y);
+                            const float h2 = __builtin_fmaf(cyp[2], ps, hz);
+                            hz = xlt ? h2 : hz;
+                            PSn[PS_HZY][r] = xlt ? ps : PSo[PS_HZY][r];
+                        } else keep(PS_HZY);
+                        if (tile_x && ylt) {
+                            const float ps = __builtin_fmaf(cxp[0], PSo[PS_HZX][r], cxp[1] * dey_x);
+                            const float h2 = __builtin_fmaf(-cxp[2], ps, hz);
+                            hz = xph ? h2 : hz;
+                            PSn[PS_HZX][r] = xph ? ps : PSo[PS_HZX][r];
+                        } else keep(PS_HZX);
+                    }
                     Hn[0][r] = plt ? hx : Ho[0][r];
                     Hn[1][r] = plt ? hy : Ho[1][r];
                     Hn[2][r] = hz;
@@ -484,13 +652,62 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     }
                     const float dhz_y = Hn[2][r] - hzd;
                     const float dhy_z = Hn[1][r] - H[t][1][r];
-                    const float ex = __builtin_fmaf(-cbz, dhy_z, __builtin_fmaf(cby, dhz_y, cf.x * Eo[0][r]));
+                    float ex = __builtin_fmaf(-cbz, dhy_z, __builtin_fmaf(cby, dhz_y, cf.x * Eo[0][r]));
                     const float dhx_z = Hn[0][r] - H[t][0][r];
                     const float dhz_x = Hn[2][r] - hzl;
-                    const float ey = __builtin_fmaf(-cbx, dhz_x, __builtin_fmaf(cbz, dhx_z, cf.x * Eo[1][r]));
+                    float ey = __builtin_fmaf(-cbx, dhz_x, __builtin_fmaf(cbz, dhx_z, cf.x * Eo[1][r]));
                     const float dhy_x = Hn[1][r] - hyl;
                     const float dhx_y = Hn[0][r] - hxd;
-                    const float ez = __builtin_fmaf(-cby, dhx_y, __builtin_fmaf(cbx, dhy_x, cf.x * Eo[2][r]));
+                    float ez = __builtin_fmaf(-cby, dhx_y, __builtin_fmaf(cbx, dhy_x, cf.x * Eo[2][r]));
+                    if constexpr (PSI) {
+                        // psi terms of each interior E edge in a layer (Ex: y then z,
+                        // Ey: z then x, Ez: x then y), the factor G * (c dt/d') formed
+                        // in FP32 before its fma
+                        const float G = cf.y;
+                        const bool ylt = y < ny, yint = y > 0 && y < ny;
+                        float cye[3] = {0.0f, 0.0f, 0.0f};
+                        if (ype[r]) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) cye[c] = cpu[6 * (nx + 1 + y) + 3 + c];
+                        }
+                        auto keep = [&](const int c) __attribute__((always_inline)) { PSn[c][r] = PSo[c][r]; };
+                        if (ype[r] && pint) {
+                            const float ps = __builtin_fmaf(cye[0], PSo[PS_EXY][r], cye[1] * dhz_y);
+                            const float e2 = __builtin_fmaf(G * cye[2], ps, ex);
+                            ex = xlt ? e2 : ex;
+                            PSn[PS_EXY][r] = xlt ? ps : PSo[PS_EXY][r];
+                        } else keep(PS_EXY);
+                        if (zpe && yint) {
+                            const float ps = __builtin_fmaf(czp[3], PSo[PS_EXZ][r], czp[4] * dhy_z);
+                            const float e2 = __builtin_fmaf(-(G * czp[5]), ps, ex);
+                            ex = xlt ? e2 : ex;
+                            PSn[PS_EXZ][r] = xlt ? ps : PSo[PS_EXZ][r];
+                        } else keep(PS_EXZ);
+                        if (zpe && ylt) {
+                            const float ps = __builtin_fmaf(czp[3], PSo[PS_EYZ][r], czp[4] * dhx_z);
+                            const float e2 = __builtin_fmaf(G * czp[5], ps, ey);
+                            ey = xint ? e2 : ey;
+                            PSn[PS_EYZ][r] = xint ? ps : PSo[PS_EYZ][r];
+                        } else keep(PS_EYZ);
+                        if (tile_x && ylt && pint) {
+                            const float ps = __builtin_fmaf(cxp[3], PSo[PS_EYX][r], cxp[4] * dhz_x);
+                            const float e2 = __builtin_fmaf(-(G * cxp[5]), ps, ey);
+                            ey = xpe ? e2 : ey;
+                            PSn[PS_EYX][r] = xpe ? ps : PSo[PS_EYX][r];
+                        } else keep(PS_EYX);
+                        if (tile_x && plt && yint) {
+                            const float ps = __builtin_fmaf(cxp[3], PSo[PS_EZX][r], cxp[4] * dhy_x);
+                            const float e2 = __builtin_fmaf(G * cxp[5], ps, ez);
+                            ez = xpe ? e2 : ez;
+                            PSn[PS_EZX][r] = xpe ? ps : PSo[PS_EZX][r];
+                        } else keep(PS_EZX);
+                        if (ype[r] && plt) {
+                            const float ps = __builtin_fmaf(cye[0], PSo[PS_EZY][r], cye[1] * dhx_y);
+                            const float e2 = __builtin_fmaf(-(G * cye[2]), ps, ez);
+                            ez = xint ? e2 : ez;
+                            PSn[PS_EZY][r] = xint ? ps : PSo[PS_EZY][r];
+                        } else keep(PS_EZY);
+                    }
                     if constexpr (INNER) {
                         En[0][r] = pint ? ex : Eo[0][r];
                         En[1][r] = pint ? ey : Eo[1][r];
@@ -558,6 +775,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                         Ho[c][r] = ht;
                     }
                 }
+                if constexpr (PSI) {
+                    if (t < T) {
+#pragma unroll
+                        for (int c = 0; c < NPS; ++c)
+#pragma unroll
+                            for (int r = 0; r < RY; ++r) {
+                                const float pt = PS[t < T ? t : 0][c][r];
+                                PS[t < T ? t : 0][c][r] = PSn[c][r];
+                                PSo[c][r] = pt;
+                            }
+                    } else if (ALL || (p >= z0 && p < z1)) {
+                        store_psi(p, PSn);      // level T: the owned values of plane p
+                    }
+                }
             } else {
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
@@ -565,6 +796,14 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     for (int c = 0; c < 3; ++c) {
                         Eo[c][r] = E[t][c][r];
                         Ho[c][r] = H[t][c][r];
+                    }
+                }
+                if constexpr (PSI) {
+                    if (t < T) {
+#pragma unroll
+                        for (int c = 0; c < NPS; ++c)
+#pragma unroll
+                            for (int r = 0; r < RY; ++r) PSo[c][r] = PS[t < T ? t : 0][c][r];
                     }
                 }
             }
@@ -594,13 +833,25 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
         int K = kb;
         const int kw = min(max(kb > 0 ? kb + 2 * T - 1 : T + 1, z0 + T), ke);
         const int kend = ke < nz ? ke : nz + T;
-        for (; K < kw; ++K) iterate(K, F{}, inner_c);
+        for (; K < kw; ++K) iterate(K, F{}, inner_c, Tr{});
         // Drain every outstanding load and store once before the steady loop
         // (s_waitcnt vmcnt(0)): the compiler's wait counts at the loop head
         // then only account for the loop's own traffic.
         __builtin_amdgcn_s_waitcnt(0x0f70);
-        for (; K < ke; ++K) iterate(K, Tr{}, inner_c);
-        for (; K <= kend; ++K) iterate(K, F{}, inner_c);
+        if (!CP || tile_xy) {
+            for (; K < ke; ++K) iterate(K, Tr{}, inner_c, Tr{});
+        } else {
+            // Only the z slabs: psi enters with the plane loaded at step K and
+            // leaves with level T's, so steps K in [0, N + T) and
+            // [nz - N, nz + T) carry it.
+            while (K < ke) {
+                const bool in = K < N + T || (K >= nz - N && K < nz + T);
+                const int next = min(ke, K < N + T ? N + T : K < nz - N ? nz - N : nz + T);
+                if (in) for (; K < next; ++K) iterate(K, Tr{}, inner_c, Tr{});
+                else for (; K < next; ++K) iterate(K, Tr{}, inner_c, F{});
+            }
+        }
+        for (; K <= kend; ++K) iterate(K, F{}, inner_c, Tr{});
     };
     const bool inner = xl >= 1 && xl + 63 <= nx - 1 && yt >= 1 && yt + NR - 1 <= ny - 1;
     if (inner) march(std::true_type{});
@@ -648,8 +899,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     __syncthreads();   // LDS is reused by the next tile of a batched launch
 }
 
-template <int T, int RY, int NW, class Codec, bool GR>
-__global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
+template <int T, int RY, int NW, class Codec, bool GR, bool CP = false>
+__global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a, CpmlFused cpa)
 {
     __shared__ TileShared<T, NW> sm;
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
@@ -660,7 +911,7 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a)
     if (logical >= a.nwg || !tile_coords(a, logical, tx, ty, tz)) return;   // uniform per workgroup
     if constexpr (Codec::scaled)         // a second pass runs only after an overflow
         if (a.sb.retry && a.sb.ctrl->ovf[a.sb.slot_out] == 0u) return;
-    fused_tile<T, RY, NW, Codec, GR>(a, logical, tx, ty, tz, sm);
+    fused_tile<T, RY, NW, Codec, GR, CP>(a, logical, tx, ty, tz, sm, cpa);
 }
 
 // Several solves in one launch: the workgroups take the concatenated tile
@@ -700,6 +951,9 @@ constexpr Tiling kTilings[MAX_T + 1][3] = {
     {{2, 16}, {4, 8}, {3, 12}},   // T = 5
     {{4, 8}, {2, 16}, {3, 12}},   // T = 6
 };
+// With CPML layers the kernel holds twelve psi values per row and time level
+// besides the fields: one row per lane keeps them within 128 VGPRs at T <= 3.
+constexpr Tiling kCpmlTiling = {1, 16};
 
 int planes_fit(const Layout &L, int es)
 {
@@ -714,10 +968,9 @@ int planes_fit(const Layout &L, int es)
 // time grows with its planes plus the cone overhead at its two ends, and the
 // launch takes ceil(workgroups / slots) rounds -- a few workgroups spilling
 // into another round cost a whole round.
-void geometry_for(int T, int variant, int zc_req, int es, const Layout &L, int slots, int *ntx, int *nty, int *ntz,
+void geometry_for(int T, Tiling tl, int zc_req, int es, const Layout &L, int slots, int *ntx, int *nty, int *ntz,
                   int *zc, int *threads, LiveNodes *live = nullptr)
 {
-    const Tiling tl = kTilings[T][variant];
     const int OX = 64 - 2 * T, OY = tl.nw * tl.ry - 2 * T;
     *ntx = (L.nx + 1 + OX - 1) / OX;
     *nty = (L.ny + 1 + OY - 1) / OY;
@@ -788,14 +1041,14 @@ bool restrict_to_box(FusedArgs &a)
     return true;
 }
 
-template <int T, int V, class Codec, bool GR>
-hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
+template <int T, int RY, int NW, class Codec, bool GR, bool CP = false>
+hipError_t launch_shape(const FusedArgs &a0, int zc_req, hipStream_t st, const CpmlFused &cpa = {})
 {
-    constexpr Tiling tl = kTilings[T][V];
-    static const int slots = resident_slots(yee_fused<T, tl.ry, tl.nw, Codec, GR>, 64 * tl.nw);
+    constexpr Tiling tl = {RY, NW};
+    static const int slots = resident_slots(yee_fused<T, tl.ry, tl.nw, Codec, GR, CP>, 64 * tl.nw);
     FusedArgs a = a0;
     int threads;
-    geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads, a.live);
+    geometry_for(T, tl, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads, a.live);
     const long long full = (long long)a.ntx * a.nty * a.ntz;
     int listed = 0;
     a.tiles = nullptr;
@@ -819,14 +1072,20 @@ hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
         a.tile_stats[1] += full;
     }
     const int grid = (a.nwg + 7) / 8 * 8;
-    hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR>), dim3(grid), dim3(threads), 0, st, a);
+    hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR, CP>), dim3(grid), dim3(threads), 0, st, a, cpa);
     if constexpr (Codec::scaled) {       // the block again, with new scales, if it overflowed
         if (hipError_t e = hipGetLastError()) return e;
         a.sb.retry = 1;
         a.tile_stats = nullptr;
-        hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR>), dim3(grid), dim3(threads), 0, st, a);
+        hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR, CP>), dim3(grid), dim3(threads), 0, st, a, cpa);
     }
     return hipGetLastError();
+}
+
+template <int T, int V, class Codec, bool GR>
+hipError_t launch_tv(const FusedArgs &a0, int zc_req, hipStream_t st)
+{
+    return launch_shape<T, kTilings[T][V].ry, kTilings[T][V].nw, Codec, GR>(a0, zc_req, st);
 }
 
 template <int T, int V, class Codec>
@@ -843,7 +1102,7 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
         a = args[i];
         a.live = nullptr;                           // batched solves run every tile of their range
         a.tiles = nullptr;
-        geometry_for(T, V, zc_req, sizeof(typename Codec::T), a.L, 0, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
+        geometry_for(T, tl, zc_req, sizeof(typename Codec::T), a.L, 0, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
         const long long full = (long long)a.ntx * a.nty * a.ntz;
         if (!restrict_to_box<T, tl.ry * tl.nw>(a)) {
             a.ntx = a.nty = a.ntz = Codec::scaled ? 1 : 0;

@@ -82,6 +82,27 @@ const int *live_tile_list(LiveNodes *d, int ox, int oy, int zc, int ntx, int nty
 // none qualifies.  Cached per geometry until the map changes.
 int live_best_zc(LiveNodes *d, int ox, int oy, int ntx, int nty, int T, int slots, int zmax);
 
+// CPML absorbing layers of n cells on every face.  cp: per axis (x, y, z)
+// and node index q, 6 floats {b_h, a_h, c dt / d[q], b_e, a_e, c dt / d'[q]}
+// (H values at cell q, E values at node q).  psi: the auxiliary state of each
+// (component, derivative axis), kept only in the layers: an index q along the
+// derivative axis maps to the slab slot l = q (q < n) or q - (n_axis - 2 n)
+// (upper layer), l < 2 n.  The four values that share a derivative axis sit
+// together, one 16-byte group per slab position, in three blocks starting at
+// base[axis] (floats):
+//   x-type (Hy, Hz, Ey, Ez), group ((k (ny+1) + j) 2n + l)
+//   y-type (Hx, Hz, Ex, Ez), group ((k 2n + l)(nx+1) + i)
+//   z-type (Hx, Hy, Ex, Ey), group ((l (ny+1) + j)(nx+1) + i)
+// PsiArray numbers them axis * 4 + place in the group.
+enum PsiArray { PS_HYX = 0, PS_HZX, PS_EYX, PS_EZX, PS_HXY, PS_HZY, PS_EXY, PS_EZY, PS_HXZ, PS_HYZ, PS_EXZ, PS_EYZ };
+struct Cpml {
+    int n;                // cells per layer (0: no layers)
+    const float *cp;
+    float *psi;
+    long long base[3];    // start of the x-, y- and z-type blocks
+    long long elems;      // floats in all three
+};
+
 struct FusedArgs {
     Layout L;
     const void *fin;
@@ -117,33 +138,25 @@ struct FusedArgs {
     long long *tile_stats;
 };
 
+// CPML layers for the fused kernel (a kernel argument of its own, so that
+// batch descriptors stay small): psi of the input state in pml.psi, of the
+// output state in psi_out (ping-pong, like the fields).
+struct CpmlFused {
+    Cpml pml;
+    float *psi_out;
+};
+
 // Up to MAX_BATCH solves in one launch; start[i] is the first work item
 // (tile) of solve i, start[n] the total.  Passed by value as kernel
 // arguments (no device copy of the descriptors).
 constexpr int MAX_BATCH = 12;
 // Longest time block of the fused kernel, and of its batched and
 // graded-spacing forms.
-constexpr int MAX_T = 6, MAX_T_BATCH = 4, MAX_T_GRADED = 4;
+constexpr int MAX_T = 6, MAX_T_BATCH = 4, MAX_T_GRADED = 4, MAX_T_CPML = 3;
 struct BatchArgs {
     int n;
     int start[MAX_BATCH + 1];
     FusedArgs s[MAX_BATCH];
-};
-
-// CPML absorbing layers of n cells on every face.  cp: per axis (x, y, z)
-// and node index q, 6 floats {b_h, a_h, c dt / d[q], b_e, a_e, c dt / d'[q]}
-// (H values at cell q, E values at node q).  psi: the auxiliary state, one
-// array per (component, derivative axis) in the order of PsiArray, kept only
-// in the layers: an index q along the derivative axis maps to the slab slot
-// l = q (q < n) or q - (n_axis - 2 n) (upper layer), l < 2 n, and the arrays
-// are laid out x-type (k (ny+1) + j) 2n + l, y-type (k 2n + l)(nx+1) + i,
-// z-type (l (ny+1) + j)(nx+1) + i.
-enum PsiArray { PS_HXY = 0, PS_HXZ, PS_HYZ, PS_HYX, PS_HZX, PS_HZY, PS_EXY, PS_EXZ, PS_EYZ, PS_EYX, PS_EZX, PS_EZY };
-struct Cpml {
-    int n;                // cells per layer (0: no layers)
-    const float *cp;
-    float *psi;
-    long long off[12];    // start of each psi array
 };
 
 struct PlainArgs {
@@ -184,6 +197,11 @@ hipError_t launch_plain_step(const PlainArgs &a, const SourceTable &src, const P
 // variant: tile shape (0 = default; FP32 also has 1 and 2); zc: planes per
 // z chunk (0 = automatic).  a.gc set: graded spacing (FP32 storage only).
 hipError_t launch_fused(int storage, int T, const FusedArgs &a, int variant, int zc, hipStream_t st);
+// The fused kernel with CPML layers (graded FP32, T <= MAX_T_CPML, its own
+// tile shape).
+hipError_t launch_fused_cpml(int T, const FusedArgs &a, const CpmlFused &c, int zc, hipStream_t st);
+// false if the psi arrays or a z chunk cannot be addressed with 32-bit offsets
+bool cpml_fused_fits(const Layout &L, long long psi_elems, int T);
 // One persistent launch over several solves sharing storage, T and shape;
 // each args[i] is complete except for its tile geometry, which is filled in.
 hipError_t launch_fused_batch(int storage, int T, const FusedArgs *args, int n, int variant, int zc,

@@ -25,16 +25,15 @@ __device__ inline bool h_in(int n, int N, int q) { return q < N || q >= n - N; }
 __device__ inline bool e_in(int n, int N, int q) { return (q > 0 && q < N) || (q > n - N && q < n); }
 __device__ inline int slot(int n, int N, int q) { return q < N ? q : q - n + 2 * N; }
 
-// psi entry of array `arr` for a value at (i, j, k) whose derivative runs
-// along `axis`
-__device__ inline float &psi_at(const Cpml &c, const Layout &L, int arr, int axis, int i, int j, int k)
+// psi entry of array `arr` for a value at (i, j, k)
+__device__ inline float &psi_at(const Cpml &c, const Layout &L, int arr, int i, int j, int k)
 {
-    const int N = c.n;
-    long long idx;
-    if (axis == 0) idx = ((long long)k * (L.ny + 1) + j) * (2 * N) + slot(L.nx, N, i);
-    else if (axis == 1) idx = ((long long)k * (2 * N) + slot(L.ny, N, j)) * (L.nx + 1) + i;
-    else idx = ((long long)slot(L.nz, N, k) * (L.ny + 1) + j) * (L.nx + 1) + i;
-    return c.psi[c.off[arr] + idx];
+    const int N = c.n, axis = arr >> 2;
+    long long g;
+    if (axis == 0) g = ((long long)k * (L.ny + 1) + j) * (2 * N) + slot(L.nx, N, i);
+    else if (axis == 1) g = ((long long)k * (2 * N) + slot(L.ny, N, j)) * (L.nx + 1) + i;
+    else g = ((long long)slot(L.nz, N, k) * (L.ny + 1) + j) * (L.nx + 1) + i;
+    return c.psi[c.base[axis] + 4 * g + (arr & 3)];
 }
 
 // one psi term of an H value: psi <- b psi + a diff, then v + sign (c dt/d) psi
@@ -82,8 +81,8 @@ __global__ __launch_bounds__(BX *BY) void h_plain(PlainArgs a)
         float dez_y = ez[p + L.pitch] - ez[p];
         float h = __builtin_fmaf(-chy, dez_y, __builtin_fmaf(chz, dey_z, hx[p]));
         if constexpr (CP) {
-            if (h_in(L.nz, N, k)) h = h_term(cpz, psi_at(a.pml, L, PS_HXZ, 2, i, j, k), dey_z, h, false);
-            if (h_in(L.ny, N, j)) h = h_term(cpy, psi_at(a.pml, L, PS_HXY, 1, i, j, k), dez_y, h, true);
+            if (h_in(L.nz, N, k)) h = h_term(cpz, psi_at(a.pml, L, PS_HXZ, i, j, k), dey_z, h, false);
+            if (h_in(L.ny, N, j)) h = h_term(cpy, psi_at(a.pml, L, PS_HXY, i, j, k), dez_y, h, true);
         }
         hx[p] = h;
     }
@@ -92,8 +91,8 @@ __global__ __launch_bounds__(BX *BY) void h_plain(PlainArgs a)
         float dex_z = ex[p + L.kstride] - ex[p];
         float h = __builtin_fmaf(-chz, dex_z, __builtin_fmaf(chx, dez_x, hy[p]));
         if constexpr (CP) {
-            if (h_in(L.nx, N, i)) h = h_term(cpx, psi_at(a.pml, L, PS_HYX, 0, i, j, k), dez_x, h, false);
-            if (h_in(L.nz, N, k)) h = h_term(cpz, psi_at(a.pml, L, PS_HYZ, 2, i, j, k), dex_z, h, true);
+            if (h_in(L.nx, N, i)) h = h_term(cpx, psi_at(a.pml, L, PS_HYX, i, j, k), dez_x, h, false);
+            if (h_in(L.nz, N, k)) h = h_term(cpz, psi_at(a.pml, L, PS_HYZ, i, j, k), dex_z, h, true);
         }
         hy[p] = h;
     }
@@ -102,8 +101,8 @@ __global__ __launch_bounds__(BX *BY) void h_plain(PlainArgs a)
         float dey_x = ey[p + 1] - ey[p];
         float h = __builtin_fmaf(-chx, dey_x, __builtin_fmaf(chy, dex_y, hz[p]));
         if constexpr (CP) {
-            if (h_in(L.ny, N, j)) h = h_term(cpy, psi_at(a.pml, L, PS_HZY, 1, i, j, k), dex_y, h, false);
-            if (h_in(L.nx, N, i)) h = h_term(cpx, psi_at(a.pml, L, PS_HZX, 0, i, j, k), dey_x, h, true);
+            if (h_in(L.ny, N, j)) h = h_term(cpy, psi_at(a.pml, L, PS_HZY, i, j, k), dex_y, h, false);
+            if (h_in(L.nx, N, i)) h = h_term(cpx, psi_at(a.pml, L, PS_HZX, i, j, k), dey_x, h, true);
         }
         hz[p] = h;
     }
@@ -145,8 +144,8 @@ __global__ __launch_bounds__(BX *BY) void e_plain(PlainArgs a)
         float dhy_z = hy[p] - hy[p - L.kstride];
         float e = __builtin_fmaf(-cbz, dhy_z, __builtin_fmaf(cby, dhz_y, cf.x * ex[p]));
         if constexpr (CP) {
-            if (e_in(L.ny, N, j)) e = e_term(cpy, cf.y, psi_at(a.pml, L, PS_EXY, 1, i, j, k), dhz_y, e, false);
-            if (e_in(L.nz, N, k)) e = e_term(cpz, cf.y, psi_at(a.pml, L, PS_EXZ, 2, i, j, k), dhy_z, e, true);
+            if (e_in(L.ny, N, j)) e = e_term(cpy, cf.y, psi_at(a.pml, L, PS_EXY, i, j, k), dhz_y, e, false);
+            if (e_in(L.nz, N, k)) e = e_term(cpz, cf.y, psi_at(a.pml, L, PS_EXZ, i, j, k), dhy_z, e, true);
         }
         ex[p] = e;
     }
@@ -155,8 +154,8 @@ __global__ __launch_bounds__(BX *BY) void e_plain(PlainArgs a)
         float dhz_x = hz[p] - hz[p - 1];
         float e = __builtin_fmaf(-cbx, dhz_x, __builtin_fmaf(cbz, dhx_z, cf.x * ey[p]));
         if constexpr (CP) {
-            if (e_in(L.nz, N, k)) e = e_term(cpz, cf.y, psi_at(a.pml, L, PS_EYZ, 2, i, j, k), dhx_z, e, false);
-            if (e_in(L.nx, N, i)) e = e_term(cpx, cf.y, psi_at(a.pml, L, PS_EYX, 0, i, j, k), dhz_x, e, true);
+            if (e_in(L.nz, N, k)) e = e_term(cpz, cf.y, psi_at(a.pml, L, PS_EYZ, i, j, k), dhx_z, e, false);
+            if (e_in(L.nx, N, i)) e = e_term(cpx, cf.y, psi_at(a.pml, L, PS_EYX, i, j, k), dhz_x, e, true);
         }
         ey[p] = e;
     }
@@ -165,8 +164,8 @@ __global__ __launch_bounds__(BX *BY) void e_plain(PlainArgs a)
         float dhx_y = hx[p] - hx[p - L.pitch];
         float e = __builtin_fmaf(-cby, dhx_y, __builtin_fmaf(cbx, dhy_x, cf.x * ez[p]));
         if constexpr (CP) {
-            if (e_in(L.nx, N, i)) e = e_term(cpx, cf.y, psi_at(a.pml, L, PS_EZX, 0, i, j, k), dhy_x, e, false);
-            if (e_in(L.ny, N, j)) e = e_term(cpy, cf.y, psi_at(a.pml, L, PS_EZY, 1, i, j, k), dhx_y, e, true);
+            if (e_in(L.nx, N, i)) e = e_term(cpx, cf.y, psi_at(a.pml, L, PS_EZX, i, j, k), dhy_x, e, false);
+            if (e_in(L.ny, N, j)) e = e_term(cpy, cf.y, psi_at(a.pml, L, PS_EZY, i, j, k), dhx_y, e, true);
         }
         ez[p] = e;
     }

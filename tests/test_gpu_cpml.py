@@ -1,7 +1,11 @@
-"""GPU parity of CPML absorbing layers: the HIP plain kernels with layers
-against the oracle's CPML FP32 operation-order mode, bit for bit (fields and
-probes), on uniform and graded grids, split steps, the 256^3 open-space
-workload at full size; and the rules of fdtd_set_cpml."""
+"""GPU parity of CPML absorbing layers: the HIP plain kernels and the fused
+kernel (T = 1..3) with layers against the oracle's CPML FP32 operation-order
+mode, bit for bit (fields and probes), on uniform and graded grids, split
+steps, from zero with the zero-tile skip on and off and with NaN-poisoned
+outputs, plain and fused steps interleaved, the 256^3 open-space workload at
+full size; and the rules of fdtd_set_cpml."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -49,6 +53,63 @@ def test_cpml_bitexact(graded):
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("graded", [False, True])
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_cpml_fused_bitexact(graded, T):
+    """The fused kernel with layers (psi carried through the T levels in
+    registers) against the oracle, in split calls that end mid-block."""
+    wl = open_ragged(graded=graded)
+    print(f"cpml fused T={T} 71x45x38 graded={graded}, 40 steps in chunks 7+13+20", flush=True)
+    f, p = G.gpu_run(wl, 40, kernel=fdtd.KERNEL_FUSED, T=T, chunks=[7, 13, 20])
+    fo, po = G.oracle_f32(wl, 40)
+    _assert_same(f, fo, "fields")
+    _assert_same(p, po, "probes")
+
+
+@pytest.mark.parametrize("skip,poison", [(True, False), (False, False), (False, True)])
+def test_cpml_fused_from_zero(skip, poison):
+    """Source-driven from zero fields: the zero-tile skip leaves out tiles
+    whose fields and psi are all +0; with every output buffer (fields and
+    psi) NaN-filled before each launch, every owned value is still rewritten."""
+    wl = open_ragged(n_steps=60, seed=4248)
+    wl.init_fields = None
+    print(f"cpml fused T=2 from zero, skip={skip} poison={poison}, 60 steps", flush=True)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=2)
+    try:
+        s.set_zero_skip(skip)
+        s.set_poison(poison)
+        s.step(25)
+        s.step(35)
+        f, p = s.read_fields(), s.read_probes(0, 60)
+    finally:
+        s.close()
+    fo, po = G.oracle_f32(wl, 60)
+    _assert_same(f, fo, "fields")
+    _assert_same(p, po, "probes")
+
+
+def test_cpml_plain_and_fused_interleaved():
+    """The plain kernels update psi in place, the fused one reads one copy and
+    writes the other: switching between them mid-run keeps the state."""
+    wl = open_ragged(n_steps=31, seed=4249, graded=True)
+    print("cpml plain 9 + fused T=3 11 + plain 5 + fused T=2 6", flush=True)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_PLAIN, time_block=1)
+    try:
+        s.step(9)
+        s.set_kernel(fdtd.KERNEL_FUSED, 3)
+        s.step(11)
+        s.set_kernel(fdtd.KERNEL_PLAIN, 1)
+        s.step(5)
+        s.set_kernel(fdtd.KERNEL_FUSED, 2)
+        s.step(6)
+        f, p = s.read_fields(), s.read_probes(0, 31)
+    finally:
+        s.close()
+    fo, po = G.oracle_f32(wl, 31)
+    _assert_same(f, fo, "fields")
+    _assert_same(p, po, "probes")
+
+
 def test_cpml_thin_layers_and_automatic_kernel():
     layer = dict(thickness=1, order=2, sigma_factor=0.8, kappa_max=2.0, alpha_max=0.0)
     wl = open_ragged(n_steps=30, seed=4246, layer=layer)
@@ -78,14 +139,22 @@ def test_cpml_state_cleared_by_set_fields():
     _assert_same(f, fo, "fields after set_fields")
 
 
-def test_open256_full_size_bitexact():
-    """The 256^3 open-space workload (10-cell layers) at full size, 100 steps
-    from random fields, through the automatic kernel choice."""
+@functools.lru_cache(maxsize=1)
+def _open256_oracle():
     wl = W.open256(n_steps=100)
     init = np.random.default_rng(257).standard_normal((6, wl.nz + 1, wl.ny + 1, wl.nx + 1), dtype=np.float32)
-    print("open256 full size, random initial fields, 100 steps", flush=True)
-    f, p = G.gpu_run(wl, 100, kernel=fdtd.KERNEL_AUTO, T=0, init=init)
     fo, po = G.oracle_f32(wl, 100, init=init)
+    return wl, init, fo, po
+
+
+@pytest.mark.parametrize("kernel", [fdtd.KERNEL_AUTO, fdtd.KERNEL_PLAIN])
+def test_open256_full_size_bitexact(kernel):
+    """The 256^3 open-space workload (10-cell layers) at full size, 100 steps
+    from random fields, through the automatic kernel choice (the fused kernel
+    at its default T, as the benchmark runs it) and the plain kernels."""
+    wl, init, fo, po = _open256_oracle()
+    print(f"open256 full size, random initial fields, 100 steps, kernel={kernel}", flush=True)
+    f, p = G.gpu_run(wl, 100, kernel=kernel, T=0 if kernel == fdtd.KERNEL_AUTO else 1, init=init)
     _assert_same(f, fo, "fields")
     _assert_same(p, po, "probes")
 
@@ -99,14 +168,15 @@ def test_set_cpml_rules():
                 s.set_cpml(**bad)
             assert e.value.code == fdtd.EINVAL
         s.set_kernel(fdtd.KERNEL_FUSED, 4)
-        with pytest.raises(fdtd.FdtdError) as e:
+        with pytest.raises(fdtd.FdtdError) as e:     # layers run fused blocks of at most 3 steps
             s.set_cpml(3)
         assert e.value.code == fdtd.EINVAL
         s.set_kernel(fdtd.KERNEL_AUTO, 0)
         s.set_cpml(3)
         with pytest.raises(fdtd.FdtdError) as e:
-            s.set_kernel(fdtd.KERNEL_FUSED, 2)
+            s.set_kernel(fdtd.KERNEL_FUSED, 4)
         assert e.value.code == fdtd.EINVAL
+        s.set_kernel(fdtd.KERNEL_FUSED, 2)
         for call in (lambda: s.diagnostics(), lambda: fdtd.step_batch([s], [2])):
             with pytest.raises(fdtd.FdtdError) as e:
                 call()
