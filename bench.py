@@ -42,7 +42,8 @@ def kernel_source_hash() -> str:
     that only a change of code retires the stored traffic figures."""
     import re
     h = hashlib.sha256()
-    for name in ("yee_fused.hpp", "yee_fused.hip", "yee_device.hpp", "yee_internal.hpp", "yee_plain.hip"):
+    for name in ("yee_fused.hpp", "yee_fused.hip", "yee_fused_cpml.hip", "yee_device.hpp", "yee_internal.hpp",
+                 "yee_plain.hip"):
         with open(os.path.join(ROOT, "paper_1301_4539_amd", "csrc", name)) as f:
             text = f.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
