@@ -438,6 +438,25 @@ def main():
             ref64.out.clear()
         extras["precision"] = prec
 
+        # the energy traced inside the pass (FP64 sums in the Faraday half-step
+        # of one level per recorded state): every 250 steps, and every 4 steps
+        # (one level of every launch)
+        def traced_rate(every):
+            sx = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_FUSED, time_block=T)
+            try:
+                sx.set_zero_skip(False)
+                sx.set_energy_trace(every)
+                if args.warmup:
+                    sx.step(args.warmup)
+                return median_rate(sx, cells, args.steps, reps, torch, stream)[0]
+            finally:
+                sx.close()
+        ve250, ve4 = traced_rate(250), traced_rate(4)
+        extras["energy_trace"] = {"every_250": ve250, "every_4": ve4, "untraced": value,
+                                  "cost_every_4": 1.0 - ve4 / value}
+        print(f"[bench] energy trace: every 250 steps {ve250:.2f}, every 4 steps {ve4:.2f} G cell-updates/s "
+              f"(untraced {value:.2f})", file=sys.stderr, flush=True)
+
         # the 256^3 grid of 40 spheres and one source, FP32 T=4 and FP16 T=3
         w256 = W.spheres256()
         extras["spheres256"] = {"fp32": {"value": rate(w256, W.FP32, 4), "T": 4},

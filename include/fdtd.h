@@ -311,6 +311,34 @@ int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst);
  * meanwhile), and copies on a stream of the library's own. */
 int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int n_steps);
 
+/* Energy trace: record k is the discrete energy W^n of the state n =
+ * k * every (fdtd_diag's energy: 1/2 sum eps_r E^n.E^n + 1/2 sum
+ * H^(n-1/2).H^(n+1/2), the quantity the leapfrog conserves by the
+ * antisymmetry of its two half-steps, Sec. 2.1), written when a step starts
+ * from that state.  The FUSED kernel forms it inside the pass, in the
+ * Faraday half-step of the time level that takes state n -- E^n and
+ * H^(n-1/2) are that level's inputs, H^(n+1/2) its result -- as FP64
+ * products summed per tile (wave butterflies, then the waves in order) and
+ * the tiles' sums added in tile order: the same value on every run of the
+ * same launch sequence, equal to fdtd_diagnostics' energy up to the order
+ * of the FP64 sums.  The PLAIN kernels take it with the diagnostics pass.
+ *   every: 1.. (0 turns the trace off); before the first step (FDTD_ESTATE);
+ *   uniform spacing and no CPML layers (FDTD_EINVAL, also from fdtd_step
+ *   when spacing or layers are set afterwards); fused blocks of at most 4
+ *   steps; with FP16/BF16 storage every >= T (a block holds at most one
+ *   recorded state), with FP32 storage a block ends before a second one.
+ *   fdtd_step_batch rejects solvers with a trace (FDTD_EINVAL).  The records
+ *   of states from a restored step on are unwritten again after
+ *   fdtd_load_state.  Memory: one double per record and one per tile of a
+ *   launch, allocated here and by fdtd_step. */
+int fdtd_set_energy_trace(fdtd_solver *s, int every);
+
+/* Copy energy records [first_record, first_record + n_records) to host_dst
+ * (record k: the state k * every).  Records of states no step has started
+ * from are rejected (FDTD_EINVAL), and so is a solver without a trace.
+ * Waits for the solver's own enqueued steps only, like fdtd_read_probes. */
+int fdtd_read_energy(fdtd_solver *s, double *host_dst, long long first_record, int n_records);
+
 /* Compute diagnostics of the current state (fdtd_diag; the energy is the
  * quantity the leapfrog conserves by the antisymmetry of its two half-steps,
  * Sec. 2.1).  FDTD_EINVAL with CPML layers.  The first call allocates the

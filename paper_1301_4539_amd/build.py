@@ -18,6 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtd.so")
 SOURCES = ["yee_fused_f32.hip", "yee_fused_f16.hip", "yee_fused_bf16.hip", "yee_fused_graded.hip", "yee_fused_cpml.hip",
+           "yee_fused_energy_f32.hip", "yee_fused_energy_f16.hip", "yee_fused_energy_bf16.hip",
            "yee_fused_graded_f16.hip", "yee_fused_graded_bf16.hip", "fdtd_runtime.cpp", "yee_plain.hip",
            "yee_fused.hip", "yee_diag.hip"]
 

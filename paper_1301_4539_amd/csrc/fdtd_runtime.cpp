@@ -248,6 +248,13 @@ struct fdtd_solver {
     // diagnostics scratch
     double *diag_part_d = nullptr;
     double *diag_out_d = nullptr;
+    // energy trace (fdtd_set_energy_trace): record k is W^n of the state
+    // n = k * energy_every, written when a step starts from that state
+    int energy_every = 0;
+    double *energy_d = nullptr;         // records (all-ones bits, a NaN, until written)
+    long long energy_cap = 0;           // records
+    double *epart_d = nullptr;          // per-tile partials of one fused launch
+    double *half_eps_d = nullptr;       // eps_r / 2 per material
     // pinned host staging for uploads and read-backs: two buffers of one
     // z-plane of all six components in device layout, used alternately so
     // that host work on one plane overlaps the copy of the other
@@ -539,6 +546,29 @@ int ensure_probe_rows(fdtd_solver *s, long long rows)
     free_dev(s->probe_out_d);
     s->probe_out_d = p;
     s->probe_cap = cap;
+    return FDTD_OK;
+}
+
+// Energy records for every state a step may start from below `steps`.
+int ensure_energy_rows(fdtd_solver *s, long long steps)
+{
+    if (s->energy_every <= 0 || steps <= 0) return FDTD_OK;
+    const long long need = (steps - 1) / s->energy_every + 1;
+    if (need <= s->energy_cap) return FDTD_OK;
+    const long long cap = std::max(std::max(need, 2 * s->energy_cap), 64LL);
+    double *p = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc(&p, (size_t)cap * sizeof(double)))) return hip_fail(e, "hipMalloc(energy records)");
+    const size_t keep = (size_t)s->energy_cap * sizeof(double);
+    if ((e = hipMemsetAsync((char *)p + keep, 0xff, (size_t)cap * sizeof(double) - keep, s->st)) ||
+        (s->energy_d && (e = hipMemcpyAsync(p, s->energy_d, keep, hipMemcpyDeviceToDevice, s->st))) ||
+        (e = hipStreamSynchronize(s->st))) {
+        free_dev(p);
+        return hip_fail(e, "initialise energy records");
+    }
+    free_dev(s->energy_d);
+    s->energy_d = p;
+    s->energy_cap = cap;
     return FDTD_OK;
 }
 
@@ -947,6 +977,9 @@ int apply_graded(fdtd_solver *s, const std::vector<double> *sz, const CpmlParams
     if (s->T_auto) s->T = auto_T(s);
     return FDTD_OK;
 }
+
+hipError_t launch_diagnostics(fdtd_solver *s, double *partial, double *dout);
+int ensure_diag_buffers(fdtd_solver *s);
 
 yee::Cpml cpml_args(const fdtd_solver *s)
 {
@@ -1419,8 +1452,19 @@ int fdtd_step(fdtd_solver *s, int n_steps)
     if (!s) return fail(FDTD_EINVAL, "solver is NULL");
     if (n_steps < 0) return fail(FDTD_EINVAL, "negative step count");
     if (n_steps == 0) return FDTD_OK;
+    const long long every = s->energy_every;
+    if (every > 0) {
+        if (s->gc_d || s->pml.n > 0)
+            return fail(FDTD_EINVAL, "the energy trace needs uniform spacing and no CPML layers");
+        if (s->T > yee::MAX_T_ENERGY)
+            return fail(FDTD_EINVAL, "the energy trace runs blocks of at most " + std::to_string(yee::MAX_T_ENERGY) +
+                                         " steps");
+        if (s->storage != FDTD_FP32 && every < s->T)
+            return fail(FDTD_EINVAL, "with 16-bit storage the energy trace needs every >= T");
+    }
     int rc = ensure_probe_rows(s, s->steps + n_steps);
     if (rc) return rc;
+    if ((rc = ensure_energy_rows(s, s->steps + n_steps))) return rc;
     const yee::SourceTable src = src_table(s);
     const yee::ProbeTable probe = probe_table(s);
     hipError_t e;
@@ -1443,7 +1487,15 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         a.pml = cpml_args(s);
         box_take_sources(s);
         for (int q = 0; q < n_steps; ++q) {
-            if ((e = yee::launch_plain_step(a, src, probe, s->steps + q, s->st))) return hip_fail(e, "plain step");
+            const long long n = s->steps + q;
+            if (every > 0 && n % every == 0) {       // the energy of state n, by the diagnostics pass
+                if ((rc = ensure_diag_buffers(s))) return rc;
+                if ((e = launch_diagnostics(s, s->diag_part_d, s->diag_out_d)) ||
+                    (e = hipMemcpyAsync(s->energy_d + n / every, s->diag_out_d, sizeof(double),
+                                        hipMemcpyDeviceToDevice, s->st)))
+                    return hip_fail(e, "energy trace");
+            }
+            if ((e = yee::launch_plain_step(a, src, probe, n, s->st))) return hip_fail(e, "plain step");
         }
         box_grow(s, n_steps);
         s->steps += n_steps;
@@ -1451,7 +1503,20 @@ int fdtd_step(fdtd_solver *s, int n_steps)
     }
     int left = n_steps;
     while (left > 0) {
-        const int len = next_block(s, left);
+        int len = next_block(s, left);
+        // the recorded state of this block, if any: at most one per launch
+        // (FP32 blocks end before a second; 16-bit blocks hold at most one
+        // since every >= T)
+        int level = 0;
+        long long rec = 0;
+        if (every > 0) {
+            const long long n0 = (s->steps + every - 1) / every * every;
+            if (n0 < s->steps + len) {
+                if (n0 + every < s->steps + len) len = (int)(n0 + every - s->steps);
+                level = (int)(n0 - s->steps) + 1;
+                rec = n0 / every;
+            }
+        }
         yee::FusedArgs a;
         fill_fused(s, &a);
         const int shape = s->tiling > 0 ? s->tiling - 1
@@ -1477,8 +1542,18 @@ int fdtd_step(fdtd_solver *s, int n_steps)
                 (cpml && (e = hipMemsetAsync(cp.psi_out, 0xff, s->psi_bytes, s->st))))
                 return hip_fail(e, "poison");
         }
-        e = cpml ? yee::launch_fused_cpml(len, a, cp, s->zchunk, s->st)
-                 : yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st);
+        if (cpml) {
+            e = yee::launch_fused_cpml(len, a, cp, s->zchunk, s->st);
+        } else if (level > 0) {
+            yee::EnergyFused en;
+            en.level = level;
+            en.partial = s->epart_d;
+            en.half_eps = s->half_eps_d;
+            en.out = s->energy_d + rec;
+            e = yee::launch_fused_energy(s->storage, len, a, en, shape, s->zchunk, s->st);
+        } else {
+            e = yee::launch_fused(s->storage, len, a, shape, s->zchunk, s->st);
+        }
         if (e) return hip_fail(e, "fused step");
         box_grow(s, len);
         advance(s, len);
@@ -1499,6 +1574,7 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
         if (s->st != st) return fail(FDTD_EINVAL, "batched solvers must share one stream");
         if (s->kernel == FDTD_KERNEL_PLAIN || !yee::fused_fits(s->L, s->storage, s->T))
             return fail(FDTD_EINVAL, "batched steps use the fused kernel");
+        if (s->energy_every > 0) return fail(FDTD_EINVAL, "solvers with an energy trace are stepped alone (fdtd_step)");
         if (s->gc_d) return fail(FDTD_EINVAL, "graded-spacing solvers are stepped alone (fdtd_step)");
         if (s->T > yee::MAX_T_BATCH)
             return fail(FDTD_EINVAL, "batched steps run blocks of at most " + std::to_string(yee::MAX_T_BATCH) + " steps");
@@ -1632,15 +1708,63 @@ int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int
     return e ? hip_fail(e, "read probes") : FDTD_OK;
 }
 
+int fdtd_set_energy_trace(fdtd_solver *s, int every)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (every < 0) return fail(FDTD_EINVAL, "negative energy trace interval");
+    if (s->steps > 0) return fail(FDTD_ESTATE, "the energy trace must be set before the first step");
+    if (every > 0 && (s->gc_d || s->pml.n > 0))
+        return fail(FDTD_EINVAL, "the energy trace needs uniform spacing and no CPML layers");
+    free_dev(s->energy_d);
+    s->energy_d = nullptr;
+    s->energy_cap = 0;
+    s->energy_every = 0;
+    if (every == 0) return FDTD_OK;
+    hipError_t e;
+    if (!s->half_eps_d) {
+        double half[256];
+        for (int m = 0; m < 256; ++m) half[m] = m < s->n_mat ? 0.5 * s->eps_h[m] : 0.0;
+        double *p = nullptr, *q = nullptr;
+        const size_t nt = (size_t)yee::fused_tiles_bound(s->L);
+        if ((e = hipMalloc(&p, sizeof(half))) || (e = hipMalloc(&q, nt * sizeof(double))) ||
+            (e = hipMemcpyAsync(p, half, sizeof(half), hipMemcpyHostToDevice, s->st)) ||
+            (e = hipStreamSynchronize(s->st))) {
+            free_dev(p);
+            free_dev(q);
+            return hip_fail(e, "energy trace buffers");
+        }
+        s->half_eps_d = p;
+        s->epart_d = q;
+    }
+    s->energy_every = every;
+    return FDTD_OK;
+}
+
+int fdtd_read_energy(fdtd_solver *s, double *host_dst, long long first_record, int n_records)
+{
+    if (!s || (!host_dst && n_records > 0)) return fail(FDTD_EINVAL, "NULL argument");
+    if (s->energy_every <= 0) return fail(FDTD_EINVAL, "no energy trace (fdtd_set_energy_trace)");
+    const long long have = s->steps > 0 ? (s->steps - 1) / s->energy_every + 1 : 0;
+    if (first_record < 0 || n_records < 0 || first_record + n_records > have)
+        return fail(FDTD_EINVAL, "requested records have not been written");
+    if (n_records == 0) return FDTD_OK;
+    hipError_t e = hipSuccess;
+    if (!s->priv) e = hipStreamCreateWithFlags(&s->priv, hipStreamNonBlocking);
+    if (!e && s->done_pending) e = hipEventSynchronize(s->done_ev);
+    if (!e) e = hipMemcpyAsync(host_dst, s->energy_d + first_record, (size_t)n_records * sizeof(double),
+                               hipMemcpyDeviceToHost, s->priv);
+    if (!e) e = hipStreamSynchronize(s->priv);
+    return e ? hip_fail(e, "read energy") : FDTD_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
-// Diagnostics of the current state with the block partials in `partial`
-// and the 11 reduced values in `dout` (device), copied to *out.
-int run_diagnostics(fdtd_solver *s, double *partial, double *dout, fdtd_diag *out)
+// Diagnostics of the current state into the 11 doubles at dout (device),
+// with the block partials in `partial`.
+hipError_t launch_diagnostics(fdtd_solver *s, double *partial, double *dout)
 {
-    hipError_t e;
     yee::DiagArgs a;
     a.L = s->L;
     a.f = s->fbuf[s->cur];
@@ -1654,7 +1778,26 @@ int run_diagnostics(fdtd_solver *s, double *partial, double *dout, fdtd_diag *ou
     a.gsz = s->gsz_d;
     a.partial = partial;
     a.sb = storage_block(s);
-    if ((e = yee::launch_diag(s->storage, a, dout, s->st))) return hip_fail(e, "diagnostics");
+    return yee::launch_diag(s->storage, a, dout, s->st);
+}
+
+int ensure_diag_buffers(fdtd_solver *s)
+{
+    if (s->diag_part_d) return FDTD_OK;
+    const size_t nb = (size_t)yee::diag_blocks(s->L);
+    hipError_t e;
+    if ((e = hipMalloc(&s->diag_part_d, nb * yee::DIAG_W * sizeof(double))) ||
+        (e = hipMalloc(&s->diag_out_d, yee::DIAG_W * sizeof(double))))
+        return hip_fail(e, "hipMalloc(diagnostics)");
+    return FDTD_OK;
+}
+
+// Diagnostics of the current state with the block partials in `partial`
+// and the 11 reduced values in `dout` (device), copied to *out.
+int run_diagnostics(fdtd_solver *s, double *partial, double *dout, fdtd_diag *out)
+{
+    hipError_t e;
+    if ((e = launch_diagnostics(s, partial, dout))) return hip_fail(e, "diagnostics");
     double v[yee::DIAG_W];
     e = hipMemcpyAsync(v, dout, sizeof(v), hipMemcpyDeviceToHost, s->st);
     if (!e) e = hipStreamSynchronize(s->st);
@@ -1676,13 +1819,7 @@ int fdtd_diagnostics(fdtd_solver *s, fdtd_diag *out)
 {
     if (!s || !out) return fail(FDTD_EINVAL, "NULL argument");
     if (s->pml.n > 0) return fail(FDTD_EINVAL, "diagnostics are not defined with CPML layers");
-    hipError_t e;
-    if (!s->diag_part_d) {
-        const size_t nb = (size_t)yee::diag_blocks(s->L);
-        if ((e = hipMalloc(&s->diag_part_d, nb * yee::DIAG_W * sizeof(double))) ||
-            (e = hipMalloc(&s->diag_out_d, yee::DIAG_W * sizeof(double))))
-            return hip_fail(e, "hipMalloc(diagnostics)");
-    }
+    if (int rc = ensure_diag_buffers(s)) return rc;
     return run_diagnostics(s, s->diag_part_d, s->diag_out_d, out);
 }
 
@@ -1775,6 +1912,13 @@ int fdtd_load_state(fdtd_solver *s, const void *host_src, size_t bytes)
                                 (size_t)(s->probe_cap - h.steps) * np * sizeof(double), s->st)))
             return hip_fail(e, "load state");
     }
+    // energy records of states from the restored step on: unwritten again
+    if (s->energy_every > 0 && s->energy_d) {
+        const long long k0 = (h.steps + s->energy_every - 1) / s->energy_every;
+        if (k0 < s->energy_cap &&
+            (e = hipMemsetAsync(s->energy_d + k0, 0xff, (size_t)(s->energy_cap - k0) * sizeof(double), s->st)))
+            return hip_fail(e, "load state");
+    }
     if ((e = hipStreamSynchronize(s->st))) return hip_fail(e, "load state");
     s->cur = 0;
     s->steps = h.steps;
@@ -1851,6 +1995,9 @@ void fdtd_destroy(fdtd_solver *s)
     free_dev(s->probe_out_d);
     free_dev(s->diag_part_d);
     free_dev(s->diag_out_d);
+    free_dev(s->energy_d);
+    free_dev(s->epart_d);
+    free_dev(s->half_eps_d);
     for (int b = 0; b < 2; ++b) {
         if (s->stage[b]) (void)hipHostFree(s->stage[b]);
         if (s->stage_ev[b]) (void)hipEventDestroy(s->stage_ev[b]);

@@ -183,6 +183,20 @@ __global__ __launch_bounds__(256) void diag_final(const double *partial, long lo
     block_reduce<4>(v, s_w, t, out);
 }
 
+// Sum of n partials in a fixed order: each thread its strided partials in
+// order, then the wave butterflies, then the waves in order.
+__global__ __launch_bounds__(256) void energy_sum(const double *partial, long long n, double *out)
+{
+    __shared__ double s_w[4];
+    const int t = threadIdx.x;
+    double v = 0.0;
+    for (long long b = t; b < n; b += 256) v += partial[b];
+    v = wave_sum(v);
+    if ((t & 63) == 0) s_w[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) *out = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+}
+
 template <class Codec>
 hipError_t launch_diag_t(const DiagArgs &a, double *out, hipStream_t st)
 {
@@ -239,6 +253,13 @@ hipError_t diag_static_scratch(double **out, double **partial)
 int diag_blocks(const Layout &L)
 {
     return ((L.nx + 1 + DBX - 1) / DBX) * ((L.ny + 1 + DBY - 1) / DBY) * std::min(DZ, L.nz + 1);
+}
+
+hipError_t launch_energy_sum(const double *partial, long long n, double *out, hipStream_t st)
+{
+    if (!out || (n > 0 && !partial)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(energy_sum, dim3(1), dim3(256), 0, st, partial, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_diag(int storage, const DiagArgs &a, double *out, hipStream_t st)

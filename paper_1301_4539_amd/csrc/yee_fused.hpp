@@ -162,9 +162,13 @@ __device__ __forceinline__ bool tile_coords(const FusedArgs &a, const int logica
                             tz >= a.tz0 && tz < a.tz0 + a.ntz);
 }
 
-template <int T, int RY, int NW, class Codec, bool GR = false, bool CP = false>
+// EN: the pass also sums the energy of its input state at one time level
+// (EnergyFused), over the values this tile owns, into en.partial[logical];
+// s_en holds half of each material's eps_r, then the per-wave sums.
+template <int T, int RY, int NW, class Codec, bool GR = false, bool CP = false, bool EN = false>
 __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical, const int tx, const int ty,
-                                           const int tz, TileShared<T, NW> &sm, const CpmlFused &cpa = {})
+                                           const int tz, TileShared<T, NW> &sm, const CpmlFused &cpa = {},
+                                           const EnergyFused &en = {}, double *s_en = nullptr)
 {
     constexpr int OX = 64 - 2 * T;      // owned points per tile in x
     constexpr int NR = NW * RY;         // rows per tile
@@ -179,6 +183,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int q = tid; q < a.n_mat; q += 64 * NW) s_coef[q] = a.coef[q];
+    if constexpr (EN)
+        for (int q = tid; q < a.n_mat; q += 64 * NW) s_en[q] = en.half_eps[q];
     if (tid < 64) {
         for (int t = 0; t < T; ++t) s_e[t][NW][tid] = make_float2(0.0f, 0.0f);
         for (int b = 0; b < TileShared<T, NW>::NHB; ++b) s_h[b][0][tid] = make_float2(0.0f, 0.0f);
@@ -276,6 +282,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     // write zero at the positions outside each component's range.
     const bool xwall = x == 0 || x == nx;
     const bool xlt = x < nx;
+    const bool xint = x > 0 && x < nx;
     const bool xown = lane >= T && lane < T + OX && x <= nx;
     const int xc = min(max(x, 0), nx);
     const int vo = xc * ES;             // per-lane byte offset of the field arrays
@@ -328,7 +335,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     static_assert(!CP || (GR && std::is_same<Codec, CodecF32>::value), "CPML layers: graded FP32 kernels");
     constexpr int NPS = CP ? 12 : 1;
     const int N = CP ? cpa.pml.n : 0;
-    bool xph = false, xpe = false, xint = false, tile_x = false, tile_xy = false;
+    bool xph = false, xpe = false, tile_x = false, tile_xy = false;
     int vpx = 0, vpxs = 0;
     float cxp[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // {b_h, a_h, c dt/d, b_e, a_e, c dt/d'} of x
     bool yph[RY], ype[RY];
@@ -339,7 +346,6 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     if constexpr (CP) {
         xph = x >= 0 && x < nx && (x < N || x >= nx - N);
         xpe = (x > 0 && x < N) || (x > nx - N && x < nx);
-        xint = x > 0 && x < nx;
         const int slot = x < N ? x : x - nx + 2 * N;
         vpx = xph ? slot * 16 : (int)0x80000000u;
         vpxs = (xph && xown) ? slot * 16 : (int)0x80000000u;
@@ -500,6 +506,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     // INNER: every lane and row of the tile lies strictly inside the grid in
     // x and y (no wall in reach), so only the plane tests remain in the masks.
     // Otherwise only the tangential E of the x and y walls is held.
+    // energy of the recorded level's input state over the owned values (EN)
+    double eacc = 0.0;
+
     // PSI: a step that carries psi (CP kernels only; steps of a tile outside
     // every slab leave the all-zero psi registers alone).
     auto iterate = [&](const int K, auto all_c, auto inner_c, auto psi_c) __attribute__((always_inline)) {
@@ -631,6 +640,35 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
                     Hn[0][r] = plt ? hx : Ho[0][r];
                     Hn[1][r] = plt ? hy : Ho[1][r];
                     Hn[2][r] = hz;
+                }
+                // ---- energy W^n of level t's input state n = step0 + t - 1 ----
+                // 1/2 eps_r E^n.E^n on interior edges (eps of the owner cell)
+                // plus 1/2 H^(n-1/2).H^(n+1/2) on every H value in range: E^n and
+                // H^(n-1/2) are level t-1's values at plane p, H^(n+1/2) the ones
+                // just computed.  FP64 products and sums.
+                if constexpr (EN) {
+                    // owned planes only: in steady steps the lower levels also
+                    // run on the halo planes past z1
+                    if (t == en.level && p >= z0 && p < z1) {                // uniform
+                        const bool zin = ALL || (p > 0 && p < nz), zlt = ALL || p < nz;
+#pragma unroll
+                        for (int r = 0; r < RY; ++r) {
+                            const int row = w * RY + r;
+                            const int y = yw + r;
+                            if (!(row >= T && row < T + OY && y <= ny)) continue;   // uniform
+                            const bool yin = y > 0 && y < ny, ylt = y < ny;
+                            const double he = s_en[(uint32_t)(MP[r] >> (8 * (t - 1))) & 0xffu];
+                            const double e0 = Eo[0][r], e1 = Eo[1][r], e2 = Eo[2][r];
+                            double v = 0.0;
+                            v = (xlt && yin && zin) ? __builtin_fma(he * e0, e0, v) : v;
+                            v = (xint && ylt && zin) ? __builtin_fma(he * e1, e1, v) : v;
+                            v = (xint && yin && zlt) ? __builtin_fma(he * e2, e2, v) : v;
+                            v = (ylt && zlt) ? __builtin_fma(0.5 * (double)Ho[0][r], (double)Hn[0][r], v) : v;
+                            v = (xlt && zlt) ? __builtin_fma(0.5 * (double)Ho[1][r], (double)Hn[1][r], v) : v;
+                            v = (xlt && ylt) ? __builtin_fma(0.5 * (double)Ho[2][r], (double)Hn[2][r], v) : v;
+                            eacc += xown ? v : 0.0;
+                        }
+                    }
                 }
                 // ---- Ampere: E^(t) at plane p from H^(t) at p and p-1 ----
                 // Only row 0 needs the H row of the wave below: rows 1..RY-1 are
@@ -858,6 +896,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     else march(std::false_type{});
 #undef YEE_LOAD_PLANE
 
+    if constexpr (EN) {
+        // the tile's energy: a fixed butterfly over each wave, then the waves
+        // in order (the partials are summed in tile order afterwards)
+        double v = eacc;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) s_en[256 + w] = v;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = s_en[256];
+            for (int q = 1; q < NW; ++q) sum += s_en[256 + q];
+            en.partial[logical] = sum;
+        }
+    }
+
     if constexpr (Codec::scaled) {
         // Largest stored magnitude per component and the saturation flag:
         // reduce over the wave, then over the workgroup in LDS, and only then
@@ -899,19 +951,25 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, const int logical
     __syncthreads();   // LDS is reused by the next tile of a batched launch
 }
 
-template <int T, int RY, int NW, class Codec, bool GR, bool CP = false>
-__global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a, CpmlFused cpa)
+template <int T, int RY, int NW, class Codec, bool GR, bool CP = false, bool EN = false>
+__global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a, CpmlFused cpa, EnergyFused en)
 {
     __shared__ TileShared<T, NW> sm;
+    __shared__ double s_en[EN ? 256 + NW : 1];
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
     // contiguous run of tiles so that halo re-reads hit its own L2.
     const int nb = gridDim.x, b = blockIdx.x;
     const int logical = (b & 7) * (nb >> 3) + (b >> 3);
     int tx, ty, tz;
-    if (logical >= a.nwg || !tile_coords(a, logical, tx, ty, tz)) return;   // uniform per workgroup
+    if (logical >= a.nwg) return;                                           // uniform per workgroup
+    if (!tile_coords(a, logical, tx, ty, tz)) {       // a listed tile that only rewrites +0
+        if constexpr (EN)
+            if (threadIdx.x == 0) en.partial[logical] = 0.0;
+        return;
+    }
     if constexpr (Codec::scaled)         // a second pass runs only after an overflow
         if (a.sb.retry && a.sb.ctrl->ovf[a.sb.slot_out] == 0u) return;
-    fused_tile<T, RY, NW, Codec, GR, CP>(a, logical, tx, ty, tz, sm, cpa);
+    fused_tile<T, RY, NW, Codec, GR, CP, EN>(a, logical, tx, ty, tz, sm, cpa, en, s_en);
 }
 
 // Several solves in one launch: the workgroups take the concatenated tile
@@ -1041,11 +1099,12 @@ bool restrict_to_box(FusedArgs &a)
     return true;
 }
 
-template <int T, int RY, int NW, class Codec, bool GR, bool CP = false>
-hipError_t launch_shape(const FusedArgs &a0, int zc_req, hipStream_t st, const CpmlFused &cpa = {})
+template <int T, int RY, int NW, class Codec, bool GR, bool CP = false, bool EN = false>
+hipError_t launch_shape(const FusedArgs &a0, int zc_req, hipStream_t st, const CpmlFused &cpa = {},
+                        const EnergyFused &en = {})
 {
     constexpr Tiling tl = {RY, NW};
-    static const int slots = resident_slots(yee_fused<T, tl.ry, tl.nw, Codec, GR, CP>, 64 * tl.nw);
+    static const int slots = resident_slots(yee_fused<T, tl.ry, tl.nw, Codec, GR, CP, EN>, 64 * tl.nw);
     FusedArgs a = a0;
     int threads;
     geometry_for(T, tl, zc_req, sizeof(typename Codec::T), a.L, slots, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads, a.live);
@@ -1060,6 +1119,7 @@ hipError_t launch_shape(const FusedArgs &a0, int zc_req, hipStream_t st, const C
     if (!restrict_to_box<T, tl.ry * tl.nw>(a) || (a.tiles && listed == 0)) {
         if (!Codec::scaled) {                       // all +0 and stays so
             if (a.tile_stats) a.tile_stats[1] += full;
+            if constexpr (EN) return launch_energy_sum(en.partial, 0, en.out, st);   // W = 0
             return hipSuccess;
         }
         a.ntx = a.nty = a.ntz = 1;                  // one tile publishes the next block's scales
@@ -1072,12 +1132,17 @@ hipError_t launch_shape(const FusedArgs &a0, int zc_req, hipStream_t st, const C
         a.tile_stats[1] += full;
     }
     const int grid = (a.nwg + 7) / 8 * 8;
-    hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR, CP>), dim3(grid), dim3(threads), 0, st, a, cpa);
+    hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR, CP, EN>), dim3(grid), dim3(threads), 0, st, a, cpa, en);
     if constexpr (Codec::scaled) {       // the block again, with new scales, if it overflowed
         if (hipError_t e = hipGetLastError()) return e;
         a.sb.retry = 1;
         a.tile_stats = nullptr;
-        hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR, CP>), dim3(grid), dim3(threads), 0, st, a, cpa);
+        hipLaunchKernelGGL((yee_fused<T, tl.ry, tl.nw, Codec, GR, CP, EN>), dim3(grid), dim3(threads), 0, st, a, cpa,
+                           en);
+    }
+    if constexpr (EN) {                  // the tiles' partials, in tile order
+        if (hipError_t e = hipGetLastError()) return e;
+        return launch_energy_sum(en.partial, a.nwg, en.out, st);
     }
     return hipGetLastError();
 }

@@ -146,13 +146,27 @@ struct CpmlFused {
     float *psi_out;
 };
 
+// Energy in the pass (uniform-spacing kernels, T <= MAX_T_ENERGY): time level
+// `level` (1..T) sums W^n of its input state n = step0 + level - 1,
+//   W^n = 1/2 sum eps_r E^n.E^n + 1/2 sum H^(n-1/2).H^(n+1/2)
+// (eps_r of the edge's owner cell on interior edges; every H value in
+// range), over the values each tile owns, into partial[work item] (FP64);
+// launch_energy_sum then adds the partials in tile order into *out.
+// half_eps[m] = eps_r(m) / 2.
+struct EnergyFused {
+    int level;
+    double *partial;
+    const double *half_eps;
+    double *out;
+};
+
 // Up to MAX_BATCH solves in one launch; start[i] is the first work item
 // (tile) of solve i, start[n] the total.  Passed by value as kernel
 // arguments (no device copy of the descriptors).
 constexpr int MAX_BATCH = 12;
 // Longest time block of the fused kernel, and of its batched and
 // graded-spacing forms.
-constexpr int MAX_T = 6, MAX_T_BATCH = 4, MAX_T_GRADED = 4, MAX_T_CPML = 3;
+constexpr int MAX_T = 6, MAX_T_BATCH = 4, MAX_T_GRADED = 4, MAX_T_CPML = 3, MAX_T_ENERGY = 4;
 struct BatchArgs {
     int n;
     int start[MAX_BATCH + 1];
@@ -200,6 +214,16 @@ hipError_t launch_fused(int storage, int T, const FusedArgs &a, int variant, int
 // The fused kernel with CPML layers (graded FP32, T <= MAX_T_CPML, its own
 // tile shape).
 hipError_t launch_fused_cpml(int T, const FusedArgs &a, const CpmlFused &c, int zc, hipStream_t st);
+// The fused kernel (uniform spacing, T <= MAX_T_ENERGY) that also sums the
+// energy of one level's input state into *en.out; en.partial holds at least
+// one double per launched tile (fused_tiles_bound).
+hipError_t launch_fused_energy(int storage, int T, const FusedArgs &a, const EnergyFused &en, int variant, int zc,
+                               hipStream_t st);
+// Sum of partial[0..n) in a fixed order into *out (0 when n = 0).
+hipError_t launch_energy_sum(const double *partial, long long n, double *out, hipStream_t st);
+// Upper bound on the tiles of one fused launch over every T <= MAX_T_ENERGY,
+// tile shape and z chunk.
+long long fused_tiles_bound(const Layout &L);
 // false if the psi arrays or a z chunk cannot be addressed with 32-bit offsets
 bool cpml_fused_fits(const Layout &L, long long psi_elems, int T);
 // One persistent launch over several solves sharing storage, T and shape;

@@ -1,0 +1,202 @@
+"""Energy traced inside the fused pass (fdtd_set_energy_trace): record k is
+W^n of the state n = k * every, formed in the Faraday half-step of the level
+that takes that state.  Checked against the oracle's discrete energy of the
+same state (FP64 sums in another order: relative 1e-12) for FP32 storage at
+several T, tile shapes and call splits, with the zero-tile skip and dead
+tiles, for FP16 storage against the emulation's state, through the plain
+kernels (the diagnostics pass), in a lossless cavity (conserved to FP32
+round-off), across a checkpoint rewind; and the rules of the entry points."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_4539_amd import fdtd, workload as W
+from tests import gpu_helpers as G
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def lossy(seed=4290, n_steps=40, nx=71, ny=45, nz=38, storage=W.FP32):
+    """Ragged grid (two 64-point tiles in x), lossy dielectric spheres, three
+    sources, random initial fields."""
+    wl = W.spheres(nx, ny, nz, 8, n_steps, seed=seed, n_sources=3, n_probes=4, rmin=3, rmax=9, name="energy",
+                   storage=storage)
+    rng = np.random.default_rng(seed)
+    wl.waveforms = rng.standard_normal(wl.waveforms.shape)
+    wl.init_fields = rng.standard_normal((6, nz + 1, ny + 1, nx + 1))
+    return wl
+
+
+def oracle_energies(wl, every, n_records, storage=W.FP32, T=1):
+    """W^(k every), k < n_records, of the oracle's FP32 (or 16-bit emulation)
+    state, advancing `every` steps per call."""
+    prob = oracle.Problem.from_workload(wl)
+    f = G.pec_clean(wl, G.init32(wl))
+    st = prob.quantize_upload(f, storage) if storage != W.FP32 else None
+    out = []
+    for k in range(n_records):
+        out.append(prob.energy(f))
+        if k + 1 < n_records:
+            if st is None:
+                prob.run_f32(f, k * every, every)
+            else:
+                prob.run_q(f, k * every, every, storage, T, st)
+    return np.array(out)
+
+
+def gpu_energies(wl, every, chunks, kernel=fdtd.KERNEL_FUSED, T=4, tiling=0, skip=True, storage=None, zc=0):
+    s = fdtd.Solver.from_workload(wl, kernel=kernel, time_block=T, storage=storage)
+    try:
+        s.set_tiling(tiling, zc)
+        s.set_zero_skip(skip)
+        s.set_energy_trace(every)
+        for n in chunks:
+            s.step(n)
+        have = (sum(chunks) - 1) // every + 1
+        return s.read_energy(0, have)
+    finally:
+        s.close()
+
+
+def assert_close(got, ref, what):
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+    assert np.all(np.isfinite(got)), f"{what}: unwritten record {got}"
+    assert err.max() <= RTOL, f"{what}: max relative error {err.max():.3e} at record {err.argmax()}"
+
+
+@pytest.mark.parametrize("T,tiling,every,chunks,zc", [(4, 0, 5, [13, 27], 0), (4, 2, 7, [40], 0),
+                                                      (3, 3, 4, [9, 31], 0), (2, 1, 3, [40], 0), (1, 0, 6, [40], 0),
+                                                      (4, 1, 1, [12], 0), (4, 0, 5, [13, 27], 9),
+                                                      (3, 1, 1, [13], 7)])
+def test_fp32_energy_matches_oracle(T, tiling, every, chunks, zc):
+    """zc: planes per z chunk (0: automatic, one chunk on this grid); short
+    chunks put every level on the halo planes of its chunk."""
+    wl = lossy()
+    n = sum(chunks)
+    print(f"energy FP32 T={T} tiling={tiling} every={every} chunks={chunks} zc={zc}", flush=True)
+    got = gpu_energies(wl, every, chunks, T=T, tiling=tiling, zc=zc)
+    ref = oracle_energies(wl, every, len(got))
+    assert len(got) == (n - 1) // every + 1
+    assert_close(got, ref, "energy")
+
+
+def test_energy_with_zero_skip_and_dead_tiles():
+    """Source-driven from zero fields with perfect-conductor cells (a slab
+    that covers whole tiles, and a sphere): skipped tiles contribute nothing
+    and W^0 = 0."""
+    from tests.test_gpu_zero_skip import spreading
+    wl = spreading(n_steps=48, seed=4291)
+    wl.eps_r = np.append(wl.eps_r, 1.0)
+    wl.mu_r = np.append(wl.mu_r, 1.0)
+    wl.sigma = np.append(wl.sigma, np.inf)
+    k, j, i = np.meshgrid(*(np.arange(v) for v in (wl.nz, wl.ny, wl.nx)), indexing="ij")
+    wl.mat[(i >= 150) | ((i + 0.5 - 60) ** 2 + (j + 0.5 - 40) ** 2 + (k + 0.5 - 50) ** 2 <= 100)] = 16
+    print("energy FP32 T=4, conductor cells from zero, every=6, skip on and off", flush=True)
+    got = gpu_energies(wl, 6, [20, 28], T=4, skip=True)
+    ref = oracle_energies(wl, 6, len(got))
+    assert got[0] == 0.0
+    assert_close(got[1:], ref[1:], "energy")
+    off = gpu_energies(wl, 6, [20, 28], T=4, skip=False)
+    assert_close(off[1:], ref[1:], "energy, skip off")
+
+
+@pytest.mark.parametrize("fmt", [W.FP16, W.BF16])
+def test_16bit_energy_matches_emulation(fmt):
+    wl = lossy(seed=4292, storage=fmt)
+    print(f"energy storage={fmt} T=3 every=3", flush=True)
+    got = gpu_energies(wl, 3, [12, 18], T=3, storage=fmt)
+    ref = oracle_energies(wl, 3, len(got), storage=fmt, T=3)
+    assert_close(got, ref, "energy")
+
+
+def test_plain_kernel_energy_by_diagnostics_pass():
+    wl = lossy(seed=4293, n_steps=20)
+    print("energy plain kernels every=4", flush=True)
+    got = gpu_energies(wl, 4, [7, 13], kernel=fdtd.KERNEL_PLAIN, T=1)
+    ref = oracle_energies(wl, 4, len(got))
+    assert_close(got, ref, "energy")
+
+
+def test_lossless_cavity_conserves_energy():
+    """cavity32 (TM110 mode plus noise, vacuum PEC box): the recorded energy
+    is the oracle's and stays constant to FP32 round-off."""
+    wl = W.cavity32(n_steps=100)
+    print("energy cavity32 T=4 every=10, 100 steps", flush=True)
+    got = gpu_energies(wl, 10, [100], T=4)
+    ref = oracle_energies(wl, 10, len(got))
+    assert_close(got, ref, "energy")
+    assert np.abs(got / got[0] - 1.0).max() < 1e-5
+
+
+def test_energy_after_rewind():
+    """save at step 20, run on, restore and run again: the records equal the
+    straight run's."""
+    wl = lossy(seed=4294, n_steps=40)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    try:
+        s.set_energy_trace(5)
+        s.step(20)
+        state = s.save_state()
+        s.set_fields(np.random.default_rng(1).standard_normal((6, wl.nz + 1, wl.ny + 1, wl.nx + 1)).astype(np.float32))
+        s.step(20)
+        s.load_state(state)
+        s.step(20)
+        got = s.read_energy(0, 8)
+    finally:
+        s.close()
+    ref = oracle_energies(wl, 5, 8)
+    assert_close(got, ref, "energy after rewind")
+
+
+def test_energy_trace_rules():
+    wl = lossy(seed=4295, n_steps=10, nx=20, ny=16, nz=12)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    try:
+        for bad in (-1,):
+            with pytest.raises(fdtd.FdtdError) as e:
+                s.set_energy_trace(bad)
+            assert e.value.code == fdtd.EINVAL
+        with pytest.raises(fdtd.FdtdError) as e:
+            s.read_energy(0, 1)                         # no trace
+        assert e.value.code == fdtd.EINVAL
+        s.set_energy_trace(2)
+        with pytest.raises(fdtd.FdtdError) as e:
+            fdtd.step_batch([s], [2])
+        assert e.value.code == fdtd.EINVAL
+        s.set_kernel(fdtd.KERNEL_FUSED, 5)
+        with pytest.raises(fdtd.FdtdError) as e:       # fused blocks of at most 4 steps
+            s.step(2)
+        assert e.value.code == fdtd.EINVAL
+        s.set_kernel(fdtd.KERNEL_FUSED, 4)
+        s.step(3)
+        with pytest.raises(fdtd.FdtdError) as e:
+            s.read_energy(0, 3)                         # states 0 and 2 only
+        assert e.value.code == fdtd.EINVAL
+        assert s.read_energy(0, 2).shape == (2,)
+        with pytest.raises(fdtd.FdtdError) as e:
+            s.set_energy_trace(3)                       # after the first step
+        assert e.value.code == fdtd.ESTATE
+    finally:
+        s.close()
+    s16 = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=3, storage=W.FP16)
+    try:
+        s16.set_energy_trace(2)
+        with pytest.raises(fdtd.FdtdError) as e:       # 16-bit storage: every >= T
+            s16.step(3)
+        assert e.value.code == fdtd.EINVAL
+    finally:
+        s16.close()
+    for layers in (True, False):
+        sg = fdtd.Solver.from_workload(wl)
+        try:
+            if layers:
+                sg.set_cpml(3)
+            else:
+                sg.set_spacing(np.full(wl.nx, wl.dx), np.full(wl.ny, wl.dy), np.full(wl.nz, wl.dz))
+            with pytest.raises(fdtd.FdtdError) as e:
+                sg.set_energy_trace(2)
+            assert e.value.code == fdtd.EINVAL
+        finally:
+            sg.close()
