@@ -121,11 +121,16 @@ typedef struct {
 } fdtd_diag;
 
 /* Device bytes fdtd_create needs for a caller-supplied workspace: two field
- * buffers (ping-pong), the material index and a small control block.
+ * buffers (ping-pong: the fused passes read one time level and write the
+ * other), the material index (the per-cell byte whose bandwidth Sec. 2.2
+ * counts) and a small control block.  Probe rows, energy records, CPML psi
+ * and diagnostics partials are allocated by the library on first use.
  * Returns 0 for invalid dimensions or storage. */
 size_t fdtd_workspace_bytes(int nx, int ny, int nz, int storage);
 
-/* Create a solver with all fields zero.
+/* Create a solver with all fields zero: the Yee scheme of Sec. 2.1 on a box
+ * of nx x ny x nz cells with perfectly conducting walls, E on the cell edges
+ * and H on the faces, one material per cell.
  *   nx, ny, nz    >= 2 cells each (and (nx+1)(ny+1) < 2^31)
  *   dx, dy, dz    > 0; dt > 0 and <= 1/(c sqrt(dx^-2+dy^-2+dz^-2)) (else FDTD_ECFL)
  *   table         n_materials entries (1..256), copied
@@ -249,11 +254,13 @@ int fdtd_set_poison(fdtd_solver *s, int enable);
 
 /* Tile shape of the FUSED kernel -- variant 0 = chosen per storage format and
  * T (default), 1..3 = the three rows-per-lane / waves-per-workgroup splits of
- * that T -- and planes per z chunk (0 = chosen from the grid).  Results do
- * not depend on either; they only change speed.  For tuning. */
+ * that T -- and planes per z chunk (0 = chosen from the grid): the sizes of
+ * the sub-domains of Sec. 3.1.  Results do not depend on either; they only
+ * change speed.  For tuning. */
 int fdtd_set_tiling(fdtd_solver *s, int variant, int z_chunk);
 
-/* Replace the whole state.  host: 6*(nx+1)*(ny+1)*(nz+1) floats, components
+/* Replace the whole state (the leapfrog's E^n and H^{n-1/2}, Sec. 2.1).
+ * host: 6*(nx+1)*(ny+1)*(nz+1) floats, components
  * Ex, Ey, Ez, Hx, Hy, Hz one after another (E^n, then H^{n-1/2}); NULL sets
  * every field to zero.  Positions outside a component's range, tangential E
  * on the walls and E on edges owned by perfect-conductor cells are forced to
@@ -262,25 +269,32 @@ int fdtd_set_tiling(fdtd_solver *s, int variant, int z_chunk);
  * sources registered so far.  Synchronises the stream. */
 int fdtd_set_fields(fdtd_solver *s, const float *host);
 
-/* Add a soft source E_comp(i,j,k) += waveform[n] during step n (the step
- * that produces E^{n+1}), for n < n_samples; zero afterwards.  comp is an E
+/* Add a soft source -- a current added to Ampere's equation, which Sec. 3.3
+ * names among the work between the two half-steps: E_comp(i,j,k) +=
+ * waveform[n] during step n (the step that produces E^{n+1}), for n <
+ * n_samples; zero afterwards.  comp is an E
  * component and (i,j,k) must be an interior (non-PEC) edge.  waveform is
  * copied.  At most 256 sources per solver; several sources on one edge add
  * in index order.  *id receives the source index (0, 1, ...). */
 int fdtd_set_source(fdtd_solver *s, int comp, int i, int j, int k,
                     const float *waveform, int n_samples, int *id);
 
-/* Add a probe of component comp at storage position (i,j,k) (inside that
- * component's range).  After every step n (E^{n+1}, H^{n+1/2}) the value is
+/* Add a probe -- a pin-point output as in Sec. 3.4 and Sec. 4.2 -- of
+ * component comp at storage position (i,j,k) (inside that component's
+ * range).  After every step n (E^{n+1}, H^{n+1/2}) the value is
  * recorded in FP64.  Only allowed before the first step; at most 256 probes
  * per solver.  *id receives the probe index. */
 int fdtd_set_probe(fdtd_solver *s, int comp, int i, int j, int k, int *id);
 
-/* Enqueue n_steps >= 0 steps on the solver's stream and return without
- * waiting.  Saturation of reduced storage is reported by fdtd_synchronize. */
+/* Enqueue n_steps >= 0 leapfrog steps (Sec. 2.1: the H half-step from curl
+ * E, then the E half-step from curl H) on the solver's stream and return
+ * without waiting.  The FUSED kernel advances T steps per pass over the
+ * fields (Sec. 3.2-3.4), the PLAIN one a step per pair of passes (Sec. 2.2).
+ * Saturation of reduced storage is reported by fdtd_synchronize. */
 int fdtd_step(fdtd_solver *s, int n_steps);
 
-/* Advance several solvers at once: n_steps[i] (>= 0) steps for solvers[i],
+/* Advance several solvers at once (continuous batching for serving; the
+ * paper runs one problem at a time): n_steps[i] (>= 0) steps for solvers[i],
  * count >= 0, every solver distinct, all created on the same stream, none
  * set to the PLAIN kernel and none with planes too large for the FUSED one
  * (else FDTD_EINVAL).  Each block (up to T steps, ending on multiples of
@@ -298,7 +312,7 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps);
  * solvers must share one).  FDTD_EINVAL on NULL solver. */
 int fdtd_set_stream(fdtd_solver *s, void *hip_stream);
 
-/* Copy one component of the current state to host (float,
+/* Copy one component of the current state (E^n or H^{n-1/2}, Sec. 2.1) to host (float,
  * (nx+1)(ny+1)(nz+1), x fastest; decoded if stored in reduced precision).
  * Synchronises the stream. */
 int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst);
