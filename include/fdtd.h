@@ -325,6 +325,16 @@ int fdtd_read_fields(fdtd_solver *s, int comp, float *host_dst);
  * meanwhile), and copies on a stream of the library's own. */
 int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int n_steps);
 
+/* Allocate the probe rows (and energy records) of the first total_steps
+ * steps now, so that fdtd_step up to that count allocates nothing and never
+ * synchronises the stream; otherwise fdtd_step grows them by doubling, each
+ * time with hipMalloc and a wait for the solver's stream.  A serving loop
+ * calls it when it admits a request, on the stream the solver was created
+ * on.  After the probes (fdtd_set_probe discards the rows) and the energy
+ * trace are set.  FDTD_EINVAL for a negative count, FDTD_EDEVICE if the
+ * memory cannot be allocated. */
+int fdtd_reserve_steps(fdtd_solver *s, long long total_steps);
+
 /* Energy trace: record k is the discrete energy W^n of the state n =
  * k * every (fdtd_diag's energy: 1/2 sum eps_r E^n.E^n + 1/2 sum
  * H^(n-1/2).H^(n+1/2), the quantity the leapfrog conserves by the

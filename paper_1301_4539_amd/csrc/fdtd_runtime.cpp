@@ -1708,6 +1708,14 @@ int fdtd_read_probes(fdtd_solver *s, double *host_dst, long long first_step, int
     return e ? hip_fail(e, "read probes") : FDTD_OK;
 }
 
+int fdtd_reserve_steps(fdtd_solver *s, long long total_steps)
+{
+    if (!s) return fail(FDTD_EINVAL, "solver is NULL");
+    if (total_steps < 0) return fail(FDTD_EINVAL, "negative step count");
+    if (int rc = ensure_probe_rows(s, total_steps)) return rc;
+    return ensure_energy_rows(s, total_steps);
+}
+
 int fdtd_set_energy_trace(fdtd_solver *s, int every)
 {
     if (!s) return fail(FDTD_EINVAL, "solver is NULL");

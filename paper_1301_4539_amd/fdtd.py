@@ -63,6 +63,7 @@ def lib():
         L.fdtd_read_fields.argtypes = [vp, i, vp]
         L.fdtd_read_probes.argtypes = [vp, vp, ll, i]
         L.fdtd_set_energy_trace.argtypes = [vp, i]
+        L.fdtd_reserve_steps.argtypes = [vp, ll]
         L.fdtd_read_energy.argtypes = [vp, vp, ll, i]
         L.fdtd_diagnostics.argtypes = [vp, C.POINTER(_Diag)]
         L.fdtd_diagnostics_noalloc.argtypes = [vp, C.POINTER(_Diag)]
@@ -87,7 +88,7 @@ def lib():
         L.fdtd_tile_stats.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         for name in ("fdtd_create", "fdtd_set_kernel", "fdtd_set_tiling", "fdtd_set_zero_skip", "fdtd_set_poison", "fdtd_set_fields", "fdtd_set_source", "fdtd_set_probe",
                      "fdtd_step", "fdtd_step_batch", "fdtd_read_fields", "fdtd_read_probes", "fdtd_diagnostics", "fdtd_diagnostics_noalloc",
-                     "fdtd_steps_done", "fdtd_set_stream", "fdtd_set_energy_trace", "fdtd_read_energy",
+                     "fdtd_steps_done", "fdtd_set_stream", "fdtd_set_energy_trace", "fdtd_read_energy", "fdtd_reserve_steps",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
                      "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
                      "fdtd_load_state", "fdtd_live_nodes", "fdtd_tile_stats"):
@@ -294,6 +295,12 @@ class Solver:
         out = np.zeros((n, max(self.n_probes, 1)), np.float64)
         _check(lib().fdtd_read_probes(self._h, out.ctypes.data, first, n))
         return out[:, :self.n_probes]
+
+    def reserve_steps(self, total_steps: int):
+        """Allocate the probe rows (and energy records) of the first
+        total_steps steps now, so that stepping up to there allocates nothing
+        and never synchronises the stream."""
+        _check(lib().fdtd_reserve_steps(self._h, int(total_steps)))
 
     def set_energy_trace(self, every: int):
         """Record the energy W^n of every state n = k * every a step starts from

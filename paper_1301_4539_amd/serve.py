@@ -263,6 +263,9 @@ class GpuBackend:
             with self.torch.cuda.stream(self.side):
                 h = self.fdtd.Solver.from_workload(self.wl[req.rid], kernel=kernel, time_block=tb,
                                                    stream=self.side)
+                # its probe rows for the whole solve, so that no tick waits on
+                # a row allocation
+                h.reserve_steps(req.n_steps)
             h.set_stream(self.main)              # its uploads are done; it now steps with the others
             if h._ws is not None:
                 h._ws.record_stream(self.main)

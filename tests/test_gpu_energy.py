@@ -150,6 +150,27 @@ def test_energy_after_rewind():
     assert_close(got, ref, "energy after rewind")
 
 
+def test_reserved_rows_hold_probes_and_energy():
+    """fdtd_reserve_steps allocates the probe rows and energy records up
+    front; the records and probes are the same as when they grow."""
+    wl = lossy(seed=4296, n_steps=30)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    try:
+        s.set_energy_trace(3)
+        s.reserve_steps(30)
+        with pytest.raises(fdtd.FdtdError) as e:
+            s.reserve_steps(-1)
+        assert e.value.code == fdtd.EINVAL
+        s.step(11)
+        s.step(19)
+        got, p = s.read_energy(0, 10), s.read_probes(0, 30)
+    finally:
+        s.close()
+    assert_close(got, oracle_energies(wl, 3, 10), "energy")
+    fo, po = G.oracle_f32(wl, 30)
+    assert G.first_mismatch(p, po) is None
+
+
 def test_energy_trace_rules():
     wl = lossy(seed=4295, n_steps=10, nx=20, ny=16, nz=12)
     s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
