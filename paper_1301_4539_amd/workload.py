@@ -205,19 +205,25 @@ def tm110_state(nx: int, ny: int, nz: int, dx: float, dy: float, dz: float, dt: 
     """Closed-form discrete TM110 cavity mode, amplitude 1 (float64).
 
     E^0_z(i,j,k) = sin(pi i/nx) sin(pi j/ny); other E components are 0.
-    H^{-1/2} is half a time step of the mode's discrete rotation, in closed
-    form, chosen so that H^{+1/2} = -H^{-1/2} (the mode is then advanced at
-    its exact discrete frequency).  H is stored as eta0*H, in V/m.
+    H^{-1/2} is the mode's magnetic part half a time step back, chosen so
+    that H^{+1/2} = -H^{-1/2} (the mode is then advanced at its exact
+    discrete frequency):
+        eta0 Hx(i, j+1/2) =  (c dt / dy) sin(pi/(2 ny)) cos(pi (j+1/2)/ny) sin(pi i/nx)
+        eta0 Hy(i+1/2, j) = -(c dt / dx) sin(pi/(2 nx)) cos(pi (i+1/2)/nx) sin(pi j/ny)
+    -- analytic expressions of the mode (each equals the difference of the
+    two neighbouring sines by the sum-to-product identity), so no update of
+    the scheme is evaluated here.  H is stored as eta0*H, in V/m.
     """
     f = np.zeros((6, nz + 1, ny + 1, nx + 1))
     si = np.sin(math.pi * np.arange(nx + 1) / nx)
     sj = np.sin(math.pi * np.arange(ny + 1) / ny)
     f[EZ, 0:nz, :, :] = sj[None, :, None] * si[None, None, :]
-    half = 0.5 * C0 * dt
-    dsj = (sj[1:] - sj[:-1]) / dy           # j in [0, ny)
-    dsi = (si[1:] - si[:-1]) / dx           # i in [0, nx)
-    f[HX, 0:nz, 0:ny, :] = half * dsj[None, :, None] * si[None, None, :]
-    f[HY, 0:nz, :, 0:nx] = -half * sj[None, :, None] * dsi[None, None, :]
+    cj = np.cos(math.pi * (np.arange(ny) + 0.5) / ny)       # j + 1/2, j in [0, ny)
+    ci = np.cos(math.pi * (np.arange(nx) + 0.5) / nx)       # i + 1/2, i in [0, nx)
+    ax = C0 * dt / dy * math.sin(math.pi / (2 * ny))
+    ay = C0 * dt / dx * math.sin(math.pi / (2 * nx))
+    f[HX, 0:nz, 0:ny, :] = ax * cj[None, :, None] * si[None, None, :]
+    f[HY, 0:nz, :, 0:nx] = -ay * sj[None, :, None] * ci[None, None, :]
     return f
 
 
