@@ -1453,15 +1453,8 @@ int fdtd_step(fdtd_solver *s, int n_steps)
     if (n_steps < 0) return fail(FDTD_EINVAL, "negative step count");
     if (n_steps == 0) return FDTD_OK;
     const long long every = s->energy_every;
-    if (every > 0) {
-        if (s->gc_d || s->pml.n > 0)
-            return fail(FDTD_EINVAL, "the energy trace needs uniform spacing and no CPML layers");
-        if (s->T > yee::MAX_T_ENERGY)
-            return fail(FDTD_EINVAL, "the energy trace runs blocks of at most " + std::to_string(yee::MAX_T_ENERGY) +
-                                         " steps");
-        if (s->storage != FDTD_FP32 && every < s->T)
-            return fail(FDTD_EINVAL, "with 16-bit storage the energy trace needs every >= T");
-    }
+    if (every > 0 && (s->gc_d || s->pml.n > 0))
+        return fail(FDTD_EINVAL, "the energy trace needs uniform spacing and no CPML layers");
     int rc = ensure_probe_rows(s, s->steps + n_steps);
     if (rc) return rc;
     if ((rc = ensure_energy_rows(s, s->steps + n_steps))) return rc;
@@ -1500,6 +1493,13 @@ int fdtd_step(fdtd_solver *s, int n_steps)
         box_grow(s, n_steps);
         s->steps += n_steps;
         return record_done(s);
+    }
+    if (every > 0) {           // the fused energy kernels: blocks of at most MAX_T_ENERGY steps
+        if (s->T > yee::MAX_T_ENERGY)
+            return fail(FDTD_EINVAL, "the energy trace runs fused blocks of at most " +
+                                         std::to_string(yee::MAX_T_ENERGY) + " steps");
+        if (s->storage != FDTD_FP32 && every < s->T)
+            return fail(FDTD_EINVAL, "with 16-bit storage the energy trace needs every >= T");
     }
     int left = n_steps;
     while (left > 0) {

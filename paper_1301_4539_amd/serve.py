@@ -255,7 +255,12 @@ class GpuBackend:
             time.sleep(d)
 
     def footprint(self, req) -> int:
-        return self.fdtd.workspace_bytes(req.nx, req.ny, req.nz, req.storage) + 8 * 8 * (req.n_steps + 256)
+        b = self.fdtd.workspace_bytes(req.nx, req.ny, req.nz, req.storage) + 8 * 8 * (req.n_steps + 256)
+        layer = getattr(self.wl[req.rid], "cpml", None)
+        if layer:      # two copies of the psi state: 4-float groups over three pairs of slabs
+            n = int(layer["thickness"])
+            b += 2 * 16 * 2 * n * ((req.ny + 1) * (req.nz + 1) + (req.nx + 1) * (req.nz + 1) + (req.nx + 1) * (req.ny + 1))
+        return b
 
     def create(self, req):
         kernel, tb, batched = self.solver_options(self.wl[req.rid])
