@@ -1613,6 +1613,7 @@ int fdtd_step_batch(fdtd_solver *const *solvers, int count, const int *n_steps)
                     fill_fused(solvers[j], &group[n]);
                     box_take_sources(solvers[j]);
                     box_args(solvers[j], &group[n]);
+                    group[n].live = solvers[j]->zero_skip ? solvers[j]->live : nullptr;
                     members[n++] = j;
                     done[j] = 1;
                 }

@@ -974,7 +974,8 @@ __global__ __launch_bounds__(64 * NW) void yee_fused(FusedArgs a, CpmlFused cpa,
 
 // Several solves in one launch: the workgroups take the concatenated tile
 // lists of up to MAX_BATCH solves (same storage format and block length), one
-// tile each, so small grids that could not fill the GPU alone share it.
+// tile each, so small grids that could not fill the GPU alone share it.  A
+// solve with dead tiles contributes its list of live tiles (as fdtd_step).
 template <int T, int RY, int NW, class Codec>
 __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
 {
@@ -987,7 +988,7 @@ __global__ __launch_bounds__(64 * NW) void yee_fused_batch(BatchArgs a)
     if constexpr (Codec::scaled)         // a second pass runs only after an overflow
         if (a.s[i].sb.retry && a.s[i].sb.ctrl->ovf[a.s[i].sb.slot_out] == 0u) return;
     int tx, ty, tz;
-    tile_coords(a.s[i], item - a.start[i], tx, ty, tz);   // a range: always true
+    if (!tile_coords(a.s[i], item - a.start[i], tx, ty, tz)) return;   // a listed tile that only rewrites +0
     fused_tile<T, RY, NW, Codec>(a.s[i], item - a.start[i], tx, ty, tz, sm);
 }
 
@@ -1165,15 +1166,22 @@ hipError_t launch_batch_tv(const FusedArgs *args, int n, int zc_req, hipStream_t
     for (int i = 0; i < n; ++i) {
         FusedArgs &a = b.s[i];
         a = args[i];
-        a.live = nullptr;                           // batched solves run every tile of their range
         a.tiles = nullptr;
         geometry_for(T, tl, zc_req, sizeof(typename Codec::T), a.L, 0, &a.ntx, &a.nty, &a.ntz, &a.zc, &threads);
         const long long full = (long long)a.ntx * a.nty * a.ntz;
-        if (!restrict_to_box<T, tl.ry * tl.nw>(a)) {
-            a.ntx = a.nty = a.ntz = Codec::scaled ? 1 : 0;
-            a.tx0 = a.ty0 = a.tz0 = 0;
+        int listed = 0;
+        if (a.live) {                               // the tiles owning a live node
+            a.tiles = live_tile_list(a.live, 64 - 2 * T, tl.ry * tl.nw - 2 * T, a.zc, a.ntx, a.nty, a.ntz, &listed, st);
+            a.ltx = a.ntx;
+            a.lty = a.nty;
         }
-        a.nwg = a.ntx * a.nty * a.ntz;
+        a.live = nullptr;
+        if (!restrict_to_box<T, tl.ry * tl.nw>(a) || (a.tiles && listed == 0)) {
+            a.ntx = a.nty = a.ntz = Codec::scaled ? 1 : 0;   // one tile publishes the next block's scales
+            a.tx0 = a.ty0 = a.tz0 = 0;
+            a.tiles = nullptr;
+        }
+        a.nwg = a.tiles ? listed : a.ntx * a.nty * a.ntz;
         if (a.tile_stats) {
             a.tile_stats[0] += a.nwg;
             a.tile_stats[1] += full;

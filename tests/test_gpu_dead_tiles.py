@@ -170,3 +170,28 @@ def test_tile_stats_show_the_skip():
     run, full = out[True]
     assert 0 < run < 0.8 * full
     assert out[False][0] == out[False][1] > 0
+
+
+def test_dead_tiles_in_batched_launches():
+    """fdtd_step_batch skips the dead tiles of each solve too: two conductor
+    shells and an open dielectric grid in one batch equal each solve alone
+    and the oracle, and the shells dispatch fewer workgroups than their full
+    tilings hold."""
+    wls = [shell(n_steps=24, seed=4271, nx=90, ny=70, nz=60), shell(n_steps=24, seed=4272, nx=70, ny=90, nz=50),
+           W.spheres(60, 50, 40, 3, 24, seed=4273, n_sources=1, n_probes=4, rmin=3, rmax=6, name="open")]
+    print("batched dead tiles: two shells and a dielectric grid, 24 steps at T=4 in chunks 9+15", flush=True)
+    ss = [fdtd.Solver.from_workload(w, kernel=fdtd.KERNEL_FUSED, time_block=4) for w in wls]
+    try:
+        for n in (9, 15):
+            fdtd.step_batch(ss, [n] * len(ss))
+        got = [(s.read_fields(), s.read_probes(0, 24) if w.probes else None) for s, w in zip(ss, wls)]
+        stats = [s.tile_stats() for s in ss]
+    finally:
+        for s in ss:
+            s.close()
+    for (f, p), w, st in zip(got, wls, stats):
+        fo, po = G.oracle_f32(w, 24)
+        _assert_same(f, fo, f"{w.name} fields")
+        if p is not None:
+            _assert_same(p, po, f"{w.name} probes")
+    assert stats[0][0] < stats[0][1] and stats[1][0] < stats[1][1]
