@@ -233,7 +233,8 @@ int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
  *    fields) and fdtd_load_state; fdtd_set_source wakes the nodes around its
  *    edge.  The first fused launch of each tile geometry lists the tiles and
  *    uploads the list (a small device allocation, kept until the map
- *    changes).  Batched steps run every tile.
+ *    changes); batched steps skip them too.  Solvers with CPML layers run
+ *    conductor interiors (their psi keeps following the curl next door).
  * Skipped tiles' probes record 0.  Results are bit-identical either way. */
 int fdtd_set_zero_skip(fdtd_solver *s, int enable);
 
