@@ -171,6 +171,27 @@ def test_reserved_rows_hold_probes_and_energy():
     assert G.first_mismatch(p, po) is None
 
 
+def test_energy_at_full_size_matches_diagnostics():
+    """The 512^3 dielectric cavity in the bench's launch configuration (FP32,
+    T = 4, the automatic 4 x 8 shape and z chunks): records every 20 steps
+    equal the diagnostics pass (itself pinned to the oracle's energy) on the
+    same stored state, to the order of the FP64 sums."""
+    wl = W.spheres512(n_steps=60)
+    print("energy 512^3 FP32 T=4, every 20, 60 steps, against fdtd_diagnostics", flush=True)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    try:
+        s.set_energy_trace(20)
+        ref = []
+        for _ in range(3):
+            ref.append(s.diagnostics()["energy"])      # state 20 k, before the step leaves it
+            s.step(20)
+        got = s.read_energy(0, 3)
+    finally:
+        s.close()
+    assert ref[0] == 0.0 and got[0] == 0.0
+    assert_close(got[1:], np.array(ref[1:]), "energy vs diagnostics")
+
+
 def test_energy_trace_rules():
     wl = lossy(seed=4295, n_steps=10, nx=20, ny=16, nz=12)
     s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
