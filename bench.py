@@ -2,7 +2,8 @@
 
 Headline workload: the 512^3 dielectric-scatterer cavity (16-entry material
 table, 200 seeded spheres, soft sources on Ex, Ey and Ez, 16 probes), FP32
-storage, fused kernel with T steps per HBM pass.  A "step" is one leapfrog
+storage, fused kernel with T steps per HBM pass (by default the library's
+automatic choice, 4).  A "step" is one leapfrog
 time step of the whole grid (H and E half-steps with materials, PEC walls,
 sources, probes); --steps K steps are timed with HIP events on the solver's
 stream, after --warmup W untimed steps, --repeats R times, and the median is
@@ -250,7 +251,8 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--repeats", type=int, default=5, help="timed runs of --steps steps; the median is reported")
-    ap.add_argument("--T", type=int, default=4, help="steps per HBM pass of the fused kernel (1..6)")
+    ap.add_argument("--T", type=int, default=0,
+                    help="steps per HBM pass of the fused kernel (1..6; 0 = the library's automatic choice)")
     ap.add_argument("--workload", default="spheres512", choices=WORKLOADS)
     ap.add_argument("--kernel", default="fused", choices=["fused", "plain"],
                     help="kernel family of the timed run")
@@ -301,20 +303,21 @@ def main():
     if wl.cpml and not plain and T > 3:
         T = 2          # CPML layers run fused blocks of at most 3 steps; 2 is the fastest
 
+    s = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_PLAIN if plain else fdtd.KERNEL_FUSED,
+                                  time_block=T)
+    s.set_tiling(args.tiling, args.zchunk)
+    T = s.time_block                     # the automatic choice, if --T 0
     print(f"[bench] workload {wl.name} {wl.nx}x{wl.ny}x{wl.nz}, {args.storage}, T={T}, warmup {args.warmup}, "
           f"{reps} x {args.steps} steps", file=sys.stderr, flush=True)
     # One-time library start-up outside the timed region, whatever --warmup
-    # says: a small solver with the same kernel, storage, T and tile shape
-    # loads the code object and sizes the launch (occupancy query) once.
+    # says: a small solver with the same kernel, storage and T loads the code
+    # object once.
     wi = W.spheres(40, 40, 40, 2, 2 * T, seed=7, n_sources=1, n_probes=1, rmin=2, rmax=4, name="init", storage=storage)
     si = fdtd.Solver.from_workload(wi, storage=storage, kernel=fdtd.KERNEL_PLAIN if plain else fdtd.KERNEL_FUSED,
                                    time_block=T)
     si.set_tiling(args.tiling, 0)
     si.step(2 * T)
     si.close()
-    s = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_PLAIN if plain else fdtd.KERNEL_FUSED,
-                                  time_block=T)
-    s.set_tiling(args.tiling, args.zchunk)
     # Every timed launch does its full work (the zero-tile skip off), so the
     # algorithmic bytes per launch hold for each of them; the skip's effect
     # is measured on its own in latency_ms.
@@ -384,17 +387,19 @@ def main():
                 sx.close()
 
         # 16-bit storage on the headline grid, each at its fastest T (FP32
-        # storage is compute-bound at T=4, 16-bit storage at T=3), and at
+        # storage at the timed leg's T, 16-bit storage at T=3), and at
         # matched T (4, and 1 where both forms are bandwidth-bound)
         t16 = serve.DEFAULT_T[W.FP16]
         v16 = rate(wl, W.FP16, t16)
         v16_4 = rate(wl, W.FP16, 4) if t16 != 4 else v16
+        v32_4 = value if (T == 4 and storage == W.FP32) else rate(wl, W.FP32, 4)
         v32_1, v16_1 = rate(wl, W.FP32, 1), rate(wl, W.FP16, 1)
         vbf = rate(wl, W.BF16, serve.DEFAULT_T[W.BF16])
         extras["fp16_store"] = {"value": v16, "T": t16, "ratio_vs_fp32": v16 / value,
                                 "target_ratio": 1.7,
                                 "roofline_frac": roofline.algorithmic_bytes(2) * v16 / roofline.HBM_PEAK_GBPS,
-                                "matched_T": {"T4": {"fp32": value, "fp16": v16_4, "ratio": v16_4 / value},
+                                "T_fp32": T,
+                                "matched_T": {"T4": {"fp32": v32_4, "fp16": v16_4, "ratio": v16_4 / v32_4},
                                               "T1": {"fp32": v32_1, "fp16": v16_1, "ratio": v16_1 / v32_1}},
                                 "traffic": measured_traffic(wl.name, "fp16", t16)}
         extras["bf16_store"] = {"value": vbf, "T": serve.DEFAULT_T[W.BF16], "ratio_vs_fp32": vbf / value}
@@ -440,20 +445,21 @@ def main():
 
         # the energy traced inside the pass (FP64 sums in the Faraday half-step
         # of one level per recorded state): every 250 steps, and every 4 steps
-        # (one level of every launch)
+        # (one level of every launch); the automatic T
         def traced_rate(every):
-            sx = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_FUSED, time_block=T)
+            sx = fdtd.Solver.from_workload(wl, storage=storage, kernel=fdtd.KERNEL_FUSED, time_block=0)
             try:
                 sx.set_zero_skip(False)
                 sx.set_energy_trace(every)
+                tb = sx.time_block
                 if args.warmup:
                     sx.step(args.warmup)
-                return median_rate(sx, cells, args.steps, reps, torch, stream)[0]
+                return median_rate(sx, cells, args.steps, reps, torch, stream)[0], tb
             finally:
                 sx.close()
-        ve250, ve4 = traced_rate(250), traced_rate(4)
-        extras["energy_trace"] = {"every_250": ve250, "every_4": ve4, "untraced": value,
-                                  "cost_every_4": 1.0 - ve4 / value}
+        (ve250, te), (ve4, _) = traced_rate(250), traced_rate(4)
+        extras["energy_trace"] = {"every_250": ve250, "every_4": ve4, "T": te, "untraced": value,
+                                  "untraced_T": T, "cost_every_4": 1.0 - ve4 / value}
         print(f"[bench] energy trace: every 250 steps {ve250:.2f}, every 4 steps {ve4:.2f} G cell-updates/s "
               f"(untraced {value:.2f})", file=sys.stderr, flush=True)
 
@@ -461,10 +467,13 @@ def main():
         w256 = W.spheres256()
         extras["spheres256"] = {"fp32": {"value": rate(w256, W.FP32, 4), "T": 4},
                                 "fp16": {"value": rate(w256, W.FP16, t16), "T": t16}}
-        # deeper step gathering, T = 5 and 6: past the register file (slower),
-        # but 16-bit storage is re-encoded less often
-        extras["deep_blocks"] = {f: {f"T{tb}": rate(wl, st, tb) for tb in (5, 6)}
-                                 for f, st in (("fp32", W.FP32), ("fp16", W.FP16))}
+        # deeper step gathering on the headline grid: FP32 at T = 4 (the
+        # automatic choice), 5 and 6 (past the register file), and 16-bit
+        # storage at 5 and 6 (slower than 3, but re-encoded less often)
+        extras["deep_blocks"] = {
+            "fp32": {f"T{tb}": (value if (tb == T and storage == W.FP32) else
+                                v32_4 if tb == 4 else rate(wl, W.FP32, tb)) for tb in (4, 5, 6)},
+            "fp16": {f"T{tb}": rate(wl, W.FP16, tb) for tb in (5, 6)}}
         print(f"[bench] 256^3: {extras['spheres256']}; deep blocks: {extras['deep_blocks']}",
               file=sys.stderr, flush=True)
         # graded cell sizes (per-index coefficient arrays), FP32, automatic T and tile shape

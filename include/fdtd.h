@@ -203,16 +203,19 @@ int fdtd_set_cpml(fdtd_solver *s, int thickness, int order, double sigma_factor,
 
 /* Kernel family (fdtd_kernel) and steps per HBM pass T for the FUSED family:
  * 1..6, or 0 = automatic (the default after fdtd_create): 4 for FP32
- * storage, 3 for FP16/BF16 storage and for graded spacing, the fastest on
- * MI355X, lowered for grids whose planes are too large for that T (an
- * automatic T is chosen again by fdtd_set_spacing).  T = 5 and 6 (deeper step
- * gathering, Sec. 3.4 and the conclusion) exceed the register file and run
- * slower, but re-quantise 16-bit storage less often; solvers with graded
- * spacing and fdtd_step_batch take T <= 4 (FDTD_EINVAL otherwise, also from
- * fdtd_set_spacing on a solver with a fixed T > 4), solvers with CPML layers
- * T <= 3 with FUSED (AUTO caps its blocks at 3 steps).  Allowed before the first
- * step and between steps.  Results do not depend on T for FP32 storage; for
- * FP16/BF16 storage, T sets where values are re-quantised (every T steps). */
+ * storage, 3 for FP16/BF16 storage and for graded spacing, 2 with CPML
+ * layers, the fastest on MI355X, lowered for grids whose planes are too large
+ * for that T (an automatic T is chosen again by fdtd_set_spacing and
+ * fdtd_set_cpml).  T = 5 and 6 (deeper step gathering, Sec. 3.4 and the
+ * conclusion) exceed the register file -- FP32 at T = 5 still runs faster
+ * on some large grids (512^3) and slower on others -- and re-quantise 16-bit
+ * storage less often; solvers with graded spacing and fdtd_step_batch take
+ * T <= 4 (FDTD_EINVAL otherwise, also from fdtd_set_spacing on a solver with
+ * a fixed T > 4), solvers with CPML layers T <= 3 with FUSED (AUTO caps its
+ * blocks at 3 steps).  Allowed before the first step and between steps.
+ * Results do not depend on T for FP32 storage; for FP16/BF16 storage, T sets
+ * where values are re-quantised (every T steps).  fdtd_time_block reports
+ * the T in use. */
 int fdtd_set_kernel(fdtd_solver *s, int kernel, int time_block);
 
 /* Zero-tile skipping of the FUSED kernel (enable != 0, the default after
@@ -387,6 +390,11 @@ int fdtd_diagnostics_noalloc(fdtd_solver *s, fdtd_diag *out);
 
 /* Number of steps enqueued so far. */
 int fdtd_steps_done(const fdtd_solver *s, long long *n);
+
+/* Steps per launch of the next fdtd_step: the FUSED kernel's T as chosen
+ * (automatic or fixed; with CPML layers at most 3), 1 when the PLAIN
+ * kernels run.  FDTD_EINVAL on NULL. */
+int fdtd_time_block(const fdtd_solver *s, int *T);
 
 /* Checkpoint and resume.  fdtd_save_state copies the whole evolving state
  * to host memory: the fields exactly as stored (reduced storage included),

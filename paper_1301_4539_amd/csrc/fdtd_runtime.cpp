@@ -712,6 +712,16 @@ void fill_fused(const fdtd_solver *s, yee::FusedArgs *a)
     a->box_hi = make_int4(1 << 28, 1 << 28, 1 << 28, 0);
 }
 
+// fdtd_step runs the plain kernels: asked for, or the planes (or, with
+// CPML layers, the psi arrays) too large for the fused kernel's 32-bit
+// addressing.
+bool runs_plain(const fdtd_solver *s)
+{
+    return s->kernel == FDTD_KERNEL_PLAIN ||
+           (s->pml.n > 0 && !yee::cpml_fused_fits(s->L, psi_elems(s), std::min(s->T, yee::MAX_T_CPML))) ||
+           (s->kernel == FDTD_KERNEL_AUTO && !yee::fused_fits(s->L, s->storage, 1));
+}
+
 void advance(fdtd_solver *s, int len)
 {
     s->cur ^= 1;
@@ -1465,10 +1475,7 @@ int fdtd_step(fdtd_solver *s, int n_steps)
     // CPML arrays) are too large for the fused kernel's 32-bit addressing
     // (FP32 only: create rejects 16-bit storage for such grids).
     const bool cpml = s->pml.n > 0;
-    const bool plain = s->kernel == FDTD_KERNEL_PLAIN ||
-                       (cpml && !yee::cpml_fused_fits(s->L, psi_elems(s), std::min(s->T, yee::MAX_T_CPML))) ||
-                       (s->kernel == FDTD_KERNEL_AUTO && !yee::fused_fits(s->L, s->storage, 1));
-    if (plain) {
+    if (runs_plain(s)) {
         yee::PlainArgs a;
         a.L = s->L;
         a.f = (float *)s->fbuf[s->cur];
@@ -1948,6 +1955,13 @@ int fdtd_steps_done(const fdtd_solver *s, long long *n)
 {
     if (!s || !n) return fail(FDTD_EINVAL, "NULL argument");
     *n = s->steps;
+    return FDTD_OK;
+}
+
+int fdtd_time_block(const fdtd_solver *s, int *T)
+{
+    if (!s || !T) return fail(FDTD_EINVAL, "NULL argument");
+    *T = runs_plain(s) ? 1 : s->pml.n > 0 ? std::min(s->T, yee::MAX_T_CPML) : s->T;
     return FDTD_OK;
 }
 

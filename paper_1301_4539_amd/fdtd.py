@@ -69,6 +69,7 @@ def lib():
         L.fdtd_diagnostics_noalloc.argtypes = [vp, C.POINTER(_Diag)]
         L.fdtd_set_stream.argtypes = [vp, vp]
         L.fdtd_steps_done.argtypes = [vp, C.POINTER(ll)]
+        L.fdtd_time_block.argtypes = [vp, C.POINTER(i)]
         L.fdtd_state_bytes.argtypes = [vp]
         L.fdtd_state_bytes.restype = sz
         L.fdtd_save_state.argtypes = [vp, vp, sz]
@@ -91,7 +92,7 @@ def lib():
                      "fdtd_steps_done", "fdtd_set_stream", "fdtd_set_energy_trace", "fdtd_read_energy", "fdtd_reserve_steps",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
                      "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
-                     "fdtd_load_state", "fdtd_live_nodes", "fdtd_tile_stats"):
+                     "fdtd_load_state", "fdtd_live_nodes", "fdtd_tile_stats", "fdtd_time_block"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -347,6 +348,13 @@ class Solver:
         n = C.c_longlong()
         _check(lib().fdtd_steps_done(self._h, C.byref(n)))
         return n.value
+
+    @property
+    def time_block(self) -> int:
+        """Steps per launch of the next step call (1: the plain kernels)."""
+        t = C.c_int()
+        _check(lib().fdtd_time_block(self._h, C.byref(t)))
+        return t.value
 
     def storage_state(self):
         sc = (C.c_int * 6)()

@@ -139,3 +139,8 @@ def test_tile_stats_rejects_null():
     import ctypes as C
     a, b = C.c_longlong(), C.c_longlong()
     assert fdtd.lib().fdtd_tile_stats(None, C.byref(a), C.byref(b)) == fdtd.EINVAL
+
+
+def test_time_block_rejects_null():
+    t = C.c_int()
+    assert fdtd.lib().fdtd_time_block(None, C.byref(t)) == fdtd.EINVAL

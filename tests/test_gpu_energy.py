@@ -173,13 +173,14 @@ def test_reserved_rows_hold_probes_and_energy():
 
 def test_energy_at_full_size_matches_diagnostics():
     """The 512^3 dielectric cavity in the bench's launch configuration (FP32,
-    T = 4, the automatic 4 x 8 shape and z chunks): records every 20 steps
+    the automatic T = 4, 4 x 8 shape and z chunks): records every 20 steps
     equal the diagnostics pass (itself pinned to the oracle's energy) on the
     same stored state, to the order of the FP64 sums."""
     wl = W.spheres512(n_steps=60)
-    print("energy 512^3 FP32 T=4, every 20, 60 steps, against fdtd_diagnostics", flush=True)
-    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    print("energy 512^3 FP32 automatic T, every 20, 60 steps, against fdtd_diagnostics", flush=True)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=0)
     try:
+        assert s.time_block == 4
         s.set_energy_trace(20)
         ref = []
         for _ in range(3):

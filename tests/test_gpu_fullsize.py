@@ -1,5 +1,5 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
-times (fused kernel, T=4, automatic tile shape).
+times (fused kernel, automatic T and tile shape).
 
 Short runs from a seeded random state are compared element by element with
 the oracle (the oracle takes a few seconds per step at these sizes on the
@@ -28,13 +28,16 @@ def _check(a, b, what):
     assert msg is None, f"{what}: {msg}"
 
 
-@pytest.mark.parametrize("name", ["spheres256", "spheres512", "cavity402"])
-def test_fullsize_fp32_short_run_bitexact(name):
+@pytest.mark.parametrize("name,T", [("spheres256", 4), ("spheres512", 4), ("cavity402", 4)])
+def test_fullsize_fp32_short_run_bitexact(name, T):
+    """A full block and a partial one at the automatic T."""
     wl = {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402}[name]()
-    steps = 8 if name == "spheres256" else 4
+    steps = T + 2
     init = _random_init(wl, 11)
-    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=4)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=0)
     try:
+        assert s.time_block == T
+        print(f"fullsize {name} FP32 automatic T={T}, {steps} steps", flush=True)
         s.set_fields(init)
         s.step(steps)
         probes = s.read_probes(0, steps)
