@@ -172,11 +172,16 @@ def test_set_cpml_rules():
             s.set_cpml(3)
         assert e.value.code == fdtd.EINVAL
         s.set_kernel(fdtd.KERNEL_AUTO, 0)
+        assert s.time_block == 4
         s.set_cpml(3)
+        assert s.time_block == 2                     # the automatic T with layers
         with pytest.raises(fdtd.FdtdError) as e:
             s.set_kernel(fdtd.KERNEL_FUSED, 4)
         assert e.value.code == fdtd.EINVAL
+        s.set_kernel(fdtd.KERNEL_PLAIN, 0)
+        assert s.time_block == 1
         s.set_kernel(fdtd.KERNEL_FUSED, 2)
+        assert s.time_block == 2
         for call in (lambda: s.diagnostics(), lambda: fdtd.step_batch([s], [2])):
             with pytest.raises(fdtd.FdtdError) as e:
                 call()
