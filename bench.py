@@ -2,8 +2,9 @@
 
 Headline workload: the 512^3 dielectric-scatterer cavity (16-entry material
 table, 200 seeded spheres, soft sources on Ex, Ey and Ez, 16 probes), FP32
-storage, fused kernel with T steps per HBM pass (by default the library's
-automatic choice, 4).  A "step" is one leapfrog
+storage, fused kernel with T steps per HBM pass (by default the fastest of
+T = 3, 4, 5 on this grid, measured by fdtd_tune_time_block after the
+warm-up; FP32 results do not depend on T).  A "step" is one leapfrog
 time step of the whole grid (H and E half-steps with materials, PEC walls,
 sources, probes); --steps K steps are timed with HIP events on the solver's
 stream, after --warmup W untimed steps, --repeats R times, and the median is
@@ -258,6 +259,8 @@ def main():
                     help="kernel family of the timed run")
     ap.add_argument("--tiling", type=int, default=0, help="fused-kernel tile variant (0 = auto, 1..3)")
     ap.add_argument("--zchunk", type=int, default=0, help="planes per z chunk (0 = automatic)")
+    ap.add_argument("--tune-steps", type=int, default=60,
+                    help="with --T 0 and FP32 storage: steps per candidate T of fdtd_tune_time_block (0 = no tuning)")
     ap.add_argument("--solves", type=int, default=5, help="full solves for the latency percentiles")
     ap.add_argument("--error-steps", type=int, default=250,
                     help="steps from zero fields after which the 16-bit forms are compared with the FP64 oracle")
@@ -324,6 +327,14 @@ def main():
     s.set_zero_skip(False)
     if args.warmup:
         s.step(args.warmup)
+    tuning = None
+    if (args.T == 0 and args.tune_steps > 0 and not plain and storage == W.FP32 and not wl.cpml
+            and wl.spacing is None):
+        T, tns = s.tune_time_block(args.tune_steps)
+        tuning = {"call": "fdtd_tune_time_block", "steps_each": args.tune_steps, "chosen": T,
+                  "ms_per_step": {f"T{k}": v / 1e6 for k, v in tns.items()}}
+        print(f"[bench] tuned T: {T} ({', '.join(f'T={k} {v / 1e6:.4f} ms/step' for k, v in tns.items())})",
+              file=sys.stderr, flush=True)
     start = s.steps_done()
     value, runs = median_rate(s, cells, args.steps, reps, torch, stream)
     t = cells * args.steps / value / 1e9                     # seconds of the median run
@@ -337,7 +348,7 @@ def main():
           f"{', '.join(f'{r:.1f}' for r in runs)}), {t * 1e3 / launches:.3f} ms per launch",
           file=sys.stderr, flush=True)
 
-    extras = {"runs_G": runs}
+    extras = {"runs_G": runs, "T_tuning": tuning}
     if not args.no_extras:
         # FP64 references of the precision grids, computed on the host while
         # the GPU legs below run
@@ -458,10 +469,11 @@ def main():
             finally:
                 sx.close()
         (ve250, te), (ve4, _) = traced_rate(250), traced_rate(4)
-        extras["energy_trace"] = {"every_250": ve250, "every_4": ve4, "T": te, "untraced": value,
-                                  "untraced_T": T, "cost_every_4": 1.0 - ve4 / value}
-        print(f"[bench] energy trace: every 250 steps {ve250:.2f}, every 4 steps {ve4:.2f} G cell-updates/s "
-              f"(untraced {value:.2f})", file=sys.stderr, flush=True)
+        vu = value if te == T else v32_4 if te == 4 else rate(wl, storage, te)   # untraced, same T
+        extras["energy_trace"] = {"every_250": ve250, "every_4": ve4, "T": te, "untraced": vu,
+                                  "cost_every_4": 1.0 - ve4 / vu}
+        print(f"[bench] energy trace (T={te}): every 250 steps {ve250:.2f}, every 4 steps {ve4:.2f} "
+              f"G cell-updates/s (untraced {vu:.2f})", file=sys.stderr, flush=True)
 
         # the 256^3 grid of 40 spheres and one source, FP32 T=4 and FP16 T=3
         w256 = W.spheres256()

@@ -396,6 +396,21 @@ int fdtd_steps_done(const fdtd_solver *s, long long *n);
  * kernels run.  FDTD_EINVAL on NULL. */
 int fdtd_time_block(const fdtd_solver *s, int *T);
 
+/* Choose T by measurement (Sec. 3.4 gathers steps per pass; which count is
+ * fastest depends on the grid's tile count as much as on the blocking): for
+ * each of T = 3, 4, 5 the solver runs one untimed block, then the largest
+ * multiple of T up to n_steps (>= 1) timed with HIP events on its stream,
+ * every launch with the zero-tile skip off; it keeps the fastest T as a
+ * fixed T (fdtd_set_kernel) and writes it to *chosen, and the per-step
+ * times in ns to ns_per_step[0..2] (NULL: not wanted; 0 for a T the grid's
+ * planes do not allow).  The solver advances by all these steps, at most
+ * 3 n_steps + 12: FP32 results do not depend on T, so they are the steps of
+ * any T.  Synchronises the stream.  Only for FP32 storage with uniform
+ * spacing, no CPML layers, no energy trace and the fused kernel
+ * (FDTD_EINVAL otherwise).  Measure where the field fills the grid: early
+ * steps from zero fields run little work anyway. */
+int fdtd_tune_time_block(fdtd_solver *s, int n_steps, int *chosen, double *ns_per_step);
+
 /* Checkpoint and resume.  fdtd_save_state copies the whole evolving state
  * to host memory: the fields exactly as stored (reduced storage included),
  * the storage scales and saturation flag, the CPML psi state, the step count

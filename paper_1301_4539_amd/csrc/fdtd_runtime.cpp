@@ -1965,6 +1965,63 @@ int fdtd_time_block(const fdtd_solver *s, int *T)
     return FDTD_OK;
 }
 
+int fdtd_tune_time_block(fdtd_solver *s, int n_steps, int *chosen, double *ns_per_step)
+{
+    if (!s || !chosen) return fail(FDTD_EINVAL, "NULL argument");
+    if (n_steps < 1) return fail(FDTD_EINVAL, "n_steps must be positive");
+    if (s->storage != FDTD_FP32 || s->gc_d || s->pml.n > 0 || s->energy_every > 0 || runs_plain(s))
+        return fail(FDTD_EINVAL, "tuning T needs FP32 storage, uniform spacing, no CPML layers, no energy trace "
+                                 "and the fused kernel");
+    constexpr int NC = 3, cand[NC] = {3, 4, 5};
+    // the steps every candidate runs: an untimed block (first-launch costs),
+    // then the largest multiple of T up to n_steps
+    long long total = 0;
+    for (int T : cand) total += T + std::max(T, n_steps / T * T);
+    int rc = ensure_probe_rows(s, s->steps + total);
+    if (rc) return rc;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < 2 && !e; ++q) e = hipEventCreate(&ev[q]);
+    const bool skip = s->zero_skip, automatic = s->T_auto;
+    const int T0 = s->T;
+    s->zero_skip = false;               // full launches, as once a field fills the grid
+    int best = 0;
+    double best_ns = 0.0;
+    for (int c = 0; c < NC && !e && !rc; ++c) {
+        const int T = cand[c];
+        if (ns_per_step) ns_per_step[c] = 0.0;
+        if (!yee::fused_fits(s->L, s->storage, T)) continue;
+        s->T = T;
+        const int m = std::max(T, n_steps / T * T);
+        float ms = 0.0f;
+        if ((rc = fdtd_step(s, T))) break;
+        if ((e = hipEventRecord(ev[0], s->st))) break;
+        if ((rc = fdtd_step(s, m))) break;
+        if ((e = hipEventRecord(ev[1], s->st)) || (e = hipEventSynchronize(ev[1])) ||
+            (e = hipEventElapsedTime(&ms, ev[0], ev[1])))
+            break;
+        const double ns = 1e6 * ms / m;
+        if (ns_per_step) ns_per_step[c] = ns;
+        if (best == 0 || ns < best_ns) {
+            best = T;
+            best_ns = ns;
+        }
+    }
+    s->zero_skip = skip;
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (rc || e || best == 0) {
+        s->T = T0;
+        s->T_auto = automatic;
+        if (rc) return rc;
+        return e ? hip_fail(e, "tune time block") : fail(FDTD_EINVAL, "no candidate T fits the grid");
+    }
+    s->T = best;
+    s->T_auto = false;
+    *chosen = best;
+    return FDTD_OK;
+}
+
 int fdtd_storage_state(fdtd_solver *s, int scales[6], int *saturated)
 {
     if (!s || !scales || !saturated) return fail(FDTD_EINVAL, "NULL argument");

@@ -70,6 +70,7 @@ def lib():
         L.fdtd_set_stream.argtypes = [vp, vp]
         L.fdtd_steps_done.argtypes = [vp, C.POINTER(ll)]
         L.fdtd_time_block.argtypes = [vp, C.POINTER(i)]
+        L.fdtd_tune_time_block.argtypes = [vp, i, C.POINTER(i), vp]
         L.fdtd_state_bytes.argtypes = [vp]
         L.fdtd_state_bytes.restype = sz
         L.fdtd_save_state.argtypes = [vp, vp, sz]
@@ -92,7 +93,8 @@ def lib():
                      "fdtd_steps_done", "fdtd_set_stream", "fdtd_set_energy_trace", "fdtd_read_energy", "fdtd_reserve_steps",
                      "fdtd_storage_state", "fdtd_synchronize", "fdtd_coefficients", "fdtd_set_spacing",
                      "fdtd_graded_coefficients", "fdtd_set_cpml", "fdtd_cpml_coefficients", "fdtd_save_state",
-                     "fdtd_load_state", "fdtd_live_nodes", "fdtd_tile_stats", "fdtd_time_block"):
+                     "fdtd_load_state", "fdtd_live_nodes", "fdtd_tile_stats", "fdtd_time_block",
+                     "fdtd_tune_time_block"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -355,6 +357,14 @@ class Solver:
         t = C.c_int()
         _check(lib().fdtd_time_block(self._h, C.byref(t)))
         return t.value
+
+    def tune_time_block(self, n_steps: int):
+        """Measure T = 3, 4, 5 over about n_steps steps each (the solver
+        advances by them) and keep the fastest: (T, {T: ns per step})."""
+        t = C.c_int()
+        ns = (C.c_double * 3)()
+        _check(lib().fdtd_tune_time_block(self._h, n_steps, C.byref(t), ns))
+        return t.value, {T: ns[q] for q, T in enumerate((3, 4, 5))}
 
     def storage_state(self):
         sc = (C.c_int * 6)()

@@ -144,3 +144,8 @@ def test_tile_stats_rejects_null():
 def test_time_block_rejects_null():
     t = C.c_int()
     assert fdtd.lib().fdtd_time_block(None, C.byref(t)) == fdtd.EINVAL
+
+
+def test_tune_time_block_rejects_null():
+    t = C.c_int()
+    assert fdtd.lib().fdtd_tune_time_block(None, 10, C.byref(t), None) == fdtd.EINVAL

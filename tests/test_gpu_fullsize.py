@@ -1,5 +1,6 @@
-"""Parity at the benchmark's full sizes, in the launch configuration bench.py
-times (fused kernel, automatic T and tile shape).
+"""Parity at the benchmark's full sizes, in the launch configurations bench.py
+times (fused kernel, automatic T and tile shape; on 512^3 also T = 5, which
+the bench's tuning keeps there).
 
 Short runs from a seeded random state are compared element by element with
 the oracle (the oracle takes a few seconds per step at these sizes on the
@@ -28,16 +29,17 @@ def _check(a, b, what):
     assert msg is None, f"{what}: {msg}"
 
 
-@pytest.mark.parametrize("name,T", [("spheres256", 4), ("spheres512", 4), ("cavity402", 4)])
-def test_fullsize_fp32_short_run_bitexact(name, T):
-    """A full block and a partial one at the automatic T."""
+@pytest.mark.parametrize("name,T,fixed", [("spheres256", 4, False), ("spheres512", 4, False), ("spheres512", 5, True),
+                                          ("cavity402", 4, False)])
+def test_fullsize_fp32_short_run_bitexact(name, T, fixed):
+    """A full block and a partial one at the automatic T (or a fixed one)."""
     wl = {"spheres256": W.spheres256, "spheres512": W.spheres512, "cavity402": W.cavity402}[name]()
     steps = T + 2
     init = _random_init(wl, 11)
-    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=0)
+    s = fdtd.Solver.from_workload(wl, kernel=fdtd.KERNEL_FUSED, time_block=T if fixed else 0)
     try:
         assert s.time_block == T
-        print(f"fullsize {name} FP32 automatic T={T}, {steps} steps", flush=True)
+        print(f"fullsize {name} FP32 T={T} ({'fixed' if fixed else 'automatic'}), {steps} steps", flush=True)
         s.set_fields(init)
         s.step(steps)
         probes = s.read_probes(0, steps)
